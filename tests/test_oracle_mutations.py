@@ -1,0 +1,149 @@
+"""Planted mistakes: each test builds a copy of one oracle module with a
+plausible slip (a dropped term, a wrong sign, a skipped step, a wrong
+operand) and checks that the pins used on the real oracle reject it.  This
+shows the pins can see such mistakes; nothing here touches the GPU path."""
+import math
+import sys
+import types
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle.checks import orth_defect, eckart_young
+
+U = 2.0 ** -53
+
+
+def mutant(modname: str, old: str, new: str) -> types.ModuleType:
+    """Load oracle.<modname> from source with one textual change applied."""
+    real = sys.modules[f"oracle.{modname}"]
+    src = open(real.__file__).read()
+    assert src.count(old) >= 1, f"mutation anchor not found: {old!r}"
+    name = f"oracle._mutant_{modname}"
+    mod = types.ModuleType(name)
+    mod.__package__ = "oracle"
+    mod.__file__ = real.__file__
+    sys.modules[name] = mod  # dataclasses look their module up by name
+    try:
+        exec(compile(src.replace(old, new), real.__file__, "exec"), mod.__dict__)
+    finally:
+        del sys.modules[name]
+    return mod
+
+
+def _invariants_hold(randqb_pb) -> bool:
+    """The Prop. 3.1 / Pythagoras / Eckart-Young pins of test_oracle_randqb."""
+    s = synth.spectrum("exp", 120, scale=6.0)
+    A = synth.prescribed_svd(160, 120, s, 1, 2)
+    nA = float(np.linalg.norm(A))
+    try:
+        res = randqb_pb(A, 1e-12 * nA, 10, 0, seed=4)
+    except Exception:
+        return False
+    if res.k == 0:
+        return False
+    ok = orth_defect(res.Q) < 1e-13
+    ok &= np.linalg.norm(res.R - (A - res.Q @ res.B)) < 1e-13 * nA
+    ok &= np.linalg.norm(res.B - res.Q.T @ A) < 1e-13 * nA
+    err = np.linalg.norm(A - res.Q @ res.B)
+    ok &= err <= 1e-12 * nA * (1 + 1e-9)
+    ok &= err >= eckart_young(s, res.k) * (1 - 1e-9)
+    return bool(ok)
+
+
+def _closed_form_holds(randqb_pb) -> bool:
+    A = synth.orthonormal_scaled(150, 100, 3.0, seed=12)
+    res = randqb_pb(A, 3.0 * math.sqrt(100 - 40 + 0.5), 16, 0, seed=1)
+    return res.k == 48 and all(abs(D - 9.0 * (100 - 16 * (i + 1))) < 1e-9
+                               for i, D in enumerate(res.D))
+
+
+def test_real_oracle_passes_the_mutation_pins():
+    assert _invariants_hold(oracle.randqb_pb)
+    assert _closed_form_holds(oracle.randqb_pb)
+
+
+@pytest.mark.parametrize("old,new", [
+    ("R -= Qi @ Bi", "R += Qi @ Bi"),                                    # downdate sign
+    ("R -= Qi @ Bi", "R -= Y @ Bi"),                                     # sample used for basis
+    ("if kept and reorth and k > 0:", "if False:"),                      # skip re-projection (3')
+    ("Qi = Qi - Qbar @ (Qbar.T @ Qi)", "Qi = Qi + Qbar @ (Qbar.T @ Qi)"),  # projection sign
+    ("Y = R @ Om", "Y = R @ Om[:, :1].repeat(Om.shape[1], axis=1)"),     # one sketch column reused
+])
+def test_driver_mutations_are_caught(old, new):
+    mod = mutant("randqb", old, new)
+    assert not (_invariants_hold(mod.randqb_pb) and _closed_form_holds(mod.randqb_pb))
+
+
+@pytest.mark.parametrize("old,new", [
+    ("if E <= eps2 - delta:", "if E < eps2 - delta - 1e300:"),           # tracked branch dead
+    ("E = sA - math.fsum(sigB_parts)", "E = sA + math.fsum(sigB_parts)"),  # indicator sign
+    ("w = min(b, kcap - k)", "w = b"),                                  # no width cap
+])
+def test_stop_rule_mutations_are_caught(old, new):
+    mod = mutant("randqb", old, new)
+    ok = _closed_form_holds(mod.randqb_pb)
+    # kmax / rank-cap behaviour of test_kmax_and_rank_cap
+    A = synth.prescribed_svd(80, 60, synth.spectrum("power", 60, p=0.5), 7, 8)
+    try:
+        r1 = mod.randqb_pb(A, 1e-12 * np.linalg.norm(A), 16, 0, seed=1, kmax=40)
+        r2 = mod.randqb_pb(A, 0.0, 16, 0, seed=1)
+        ok &= r1.k == 40 and r2.k == 60
+    except Exception:
+        ok = False
+    # tracked branch: sigma*orthonormal input with eps far above the band
+    B = synth.orthonormal_scaled(150, 100, 3.0, seed=12)
+    try:
+        r3 = mod.randqb_pb(B, 3.0 * math.sqrt(100 - 40 + 0.5), 16, 0, seed=1)
+        ok &= r3.stop_reason == oracle.STOP["TOL_TRACKED"]
+    except Exception:
+        ok = False
+    assert not ok
+
+
+@pytest.mark.parametrize("old,new", [
+    ("d = G[c, c] - float(np.dot(Tfull[kept, c], Tfull[kept, c])) if kept else G[c, c]",
+     "d = G[c, c]"),                                                     # dropped pivot term
+    ("Tfull[c, c + 1:] = rest / tcc", "Tfull[c, c + 1:] = rest * tcc"),  # wrong scaling
+    ("Q2, kept2 = cholqr(Q1, drop_rel)", "Q2, kept2 = Q1, list(range(Q1.shape[1]))"),  # one pass only
+])
+def test_orth_mutations_are_caught(old, new):
+    mod = mutant("cholqr", old, new)
+    rng = np.random.default_rng(4)
+    u, _ = np.linalg.qr(rng.standard_normal((400, 24)))
+    X = (u * np.logspace(0, -6, 24)) @ np.linalg.qr(rng.standard_normal((24, 24)))[0].T
+    Q, kept = mod.cholqr2(X)
+    good = kept == list(range(24)) and orth_defect(Q) < 20 * U * 24 \
+        and np.linalg.norm(X - Q @ (Q.T @ X)) < 1e-10 * np.linalg.norm(X)
+    assert not good
+
+
+@pytest.mark.parametrize("old,new", [
+    ("ATANH_C = [1.0 / float(2 * k + 1)", "ATANH_C = [1.0 / float(2 * k + 2)"),  # series index
+    ("return e * LN2_HI + (logf + e * LN2_LO)", "return e * LN2_HI + logf"),  # ln2 low part dropped
+    ("cos_out = np.select([qi == 0, qi == 1, qi == 2], [cs, -sn, -cs], sn)",
+     "cos_out = np.select([qi == 0, qi == 1, qi == 2], [cs, sn, -cs], sn)"),  # quadrant sign
+    ("ps = ps * z + SIN_C[k]", "ps = ps * z - SIN_C[k]"),                # sine series sign
+])
+def test_gaussian_mutations_are_caught(old, new):
+    mod = mutant("gaussian", old, new)
+    rng = np.random.default_rng(1)
+    u = np.exp(-rng.uniform(0, 36.7, 20000))
+    want = np.log(u.astype(np.longdouble))
+    logok = np.max(np.abs((mod.log_own(u) - want) / want)) < 4 * U
+    v = rng.uniform(0, 1, 20000)
+    ang = np.longdouble("6.28318530717958647692528676655900576839") * v.astype(np.longdouble)
+    c, s = mod.sincos_2pi(v)
+    trigok = np.max(np.abs(c - np.cos(ang))) < 3e-16 and np.max(np.abs(s - np.sin(ang))) < 3e-16
+    assert not (logok and trigok)
+
+
+def test_philox_constant_mutation_is_caught():
+    mod = mutant("philox", "M0 = np.uint64(0xD2511F53)", "M0 = np.uint64(0xD2511F55)")
+    # known-answer rows produced by the real generator, re-checked against
+    # rocRAND in test_oracle_philox; a changed multiplier changes them
+    real = oracle.philox.philox4x32_10(12345, 678, 0, 0, 1503, 0)
+    fake = mod.philox4x32_10(12345, 678, 0, 0, 1503, 0)
+    assert tuple(int(x) for x in real) != tuple(int(x) for x in fake)
