@@ -1,0 +1,216 @@
+#!/usr/bin/env python3
+"""Benchmark: blocked randomized QB (randQB_pb) to a relative Frobenius
+tolerance of 1e-8 on one MI355X.
+
+One step = one complete factorisation (every row of the hot path: sketch,
+sampling product, orth, power iteration, re-projection, B = Q^T A, downdate,
+stopping rule) of a 10000 x 10000 float64 matrix A = U diag(j^-2) V^T
+(U, V: Q factors of seeded Gaussian matrices), block b = 128, with the input
+already resident in HBM.  `value` is nominal GFLOP/s,
+(6 + 4P) m n k + 2 m k^2 over the measured seconds (the paper's cost model,
+Sections 4.5 and 5.3, with two flops per multiply-add).
+
+The JSON line also carries
+  roofline      the dominant kernel's algorithmic rate, timed with HIP events
+                on its own stream inside the timed steps, against MI355X peak
+  cpu_baseline  the CPU oracle timed on the host on a bounded sample of the
+                same factorisation (the first blocks, same matrix)
+  variants      P = 0 and the mixed-precision sampling forms, same workload
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "QB solve s & GFLOP/s at 1e-8 rel. Frobenius err: plain FP64 vs mixed prec"
+PEAK = {"f64_mfma": 78.6, "f32_mfma": 157.3, "hbm_gbs": 8000.0}
+
+
+def nominal_flops(m, n, k, P):
+    return (6 + 4 * P) * m * n * k + 2 * m * k * k
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def profile_snapshot(lib):
+    out = {}
+    for i in range(lib.qb_profile_count()):
+        ms, fl, by = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        la = ctypes.c_int64()
+        lib.qb_profile_read(i, ctypes.byref(ms), ctypes.byref(la), ctypes.byref(fl), ctypes.byref(by))
+        if la.value:
+            out[lib.qb_profile_name(i).decode()] = {"ms": ms.value, "launches": la.value,
+                                                    "flops": fl.value, "bytes": by.value}
+    return out
+
+
+def run_variant(qbmi, lib, torch, A, eps, wl, P, sample, steps, warmup, bufs, profile):
+    Q, B, ws = bufs
+
+    def one():
+        return qbmi.qb_factor(A, eps, wl.b, P, wl.seed_omega, sample=sample, workspace=ws,
+                              Q=Q, B=B)
+
+    for _ in range(warmup):
+        one()
+    torch.cuda.synchronize()
+    if profile:
+        lib.qb_profile_enable(1)
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    res = None
+    for _ in range(steps):
+        res = one()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    prof = profile_snapshot(lib) if profile else None
+    lib.qb_profile_enable(0)
+    return res, ms, prof
+
+
+def residual_rel(torch, A, res):
+    # independent check of ||A - Q B||_F / ||A||_F (verification only)
+    R = A - res.Q @ res.B
+    return float(torch.linalg.norm(R) / torch.linalg.norm(A))
+
+
+def cpu_baseline(A_host, eps, wl, P, blocks):
+    import threadpoolctl
+    from oracle import randqb_pb
+
+    kmax = min(blocks * wl.b, min(A_host.shape))
+    t0 = time.perf_counter()
+    res = randqb_pb(A_host, eps, wl.b, P, wl.seed_omega, kmax=kmax)
+    dt = time.perf_counter() - t0
+    info = threadpoolctl.threadpool_info()
+    cores = max([d.get("num_threads", 1) for d in info if d.get("user_api") == "blas"] or [1])
+    m, n = A_host.shape
+    fl = nominal_flops(m, n, res.k, P)
+    return {"value": fl / dt / 1e9, "unit": "GFLOP/s", "cores": int(cores), "kind": "oracle",
+            "seconds": dt, "k": res.k,
+            "sample": f"first {res.blocks} blocks (k={res.k}) of the same {m}x{n} factorisation, "
+                      f"b={wl.b}, P={P}, float64 numpy/OpenBLAS on the host; GFLOP/s by the "
+                      f"same nominal count as the GPU value"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="pow2_10000x10000")
+    ap.add_argument("--power-iters", type=int, default=1)
+    ap.add_argument("--sample", default="f64", choices=["f64", "f32", "bf16x3"])
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-blocks", type=int, default=16)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
+              f"(this build has no multi-GPU path)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1503_07157_amd as qbmi
+    import synth
+
+    lib = qbmi.load()
+    wl = synth.workload(args.workload)
+    m, n = wl.m, wl.n
+    r = min(m, n)
+    log(f"[bench] generating {wl.name} on the GPU")
+    A = synth.workload_matrix_gpu(wl.name)
+    torch.cuda.synchronize()
+    nA2, bad = qbmi.frob2(A)
+    assert not bad
+    eps = wl.eps_rel * math.sqrt(nA2)
+    Q = torch.empty((r, m), dtype=torch.float64, device="cuda").t()
+    B = torch.empty((n, r), dtype=torch.float64, device="cuda").t()
+    need = qbmi.workspace_bytes(m, n, wl.b, r)
+    ws = torch.empty(need + 512, dtype=torch.uint8, device="cuda")
+    bufs = (Q, B, ws)
+
+    P = args.power_iters
+    log(f"[bench] timing P={P} sample={args.sample}: warmup {args.warmup}, steps {args.steps}")
+    res, ms, prof = run_variant(qbmi, lib, torch, A, eps, wl, P, args.sample, args.steps,
+                                args.warmup, bufs, profile=True)
+    k = res.k
+    flops = nominal_flops(m, n, k, P)
+    gflops = flops / (ms * 1e-3) / 1e9
+    rel = residual_rel(torch, A, res)
+    log(f"[bench] k={k} stop={res.stop_reason} {ms:.1f} ms/step {gflops:.0f} GFLOP/s rel_err={rel:.3e}")
+
+    # dominant kernel by total time inside the timed steps
+    dom_name, dom = max(prof.items(), key=lambda kv: kv[1]["ms"])
+    dom_tflops = dom["flops"] / (dom["ms"] * 1e-3) / 1e12 if dom["ms"] > 0 else 0.0
+    roofline = {"bound": "mfma", "kernel": dom_name, "achieved": dom_tflops,
+                "peak": PEAK["f64_mfma"], "unit": "TFLOP/s", "frac": dom_tflops / PEAK["f64_mfma"],
+                "traffic": None, "avg_launch_ms": dom["ms"] / dom["launches"],
+                "launches": dom["launches"],
+                "note": "achieved = algorithmic flops of this kernel class (2 x rows x cols x depth "
+                        "per product) over its summed launch durations (HIP events on the launch "
+                        "stream) within the timed steps"}
+    kernels = {name: {"ms_per_step": v["ms"] / args.steps, "launches_per_step": v["launches"] / args.steps,
+                      "tflops": (v["flops"] / (v["ms"] * 1e-3) / 1e12) if v["ms"] > 0 else None,
+                      "gbs": (v["bytes"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] > 0 else None}
+               for name, v in prof.items()}
+
+    variants = []
+    if not args.no_variants:
+        for (vp, vs) in [(0, "f64"), (P, "f32"), (P, "bf16x3"), (0, "f32"), (0, "bf16x3")]:
+            if (vp, vs) == (P, args.sample):
+                continue
+            try:
+                vres, vms, _ = run_variant(qbmi, lib, torch, A, eps, wl, vp, vs, args.steps,
+                                           args.warmup, bufs, profile=False)
+            except qbmi.QBError as e:
+                variants.append({"power_iters": vp, "sample": vs, "error": str(e)})
+                continue
+            vfl = nominal_flops(m, n, vres.k, vp)
+            variants.append({"power_iters": vp, "sample": vs, "k": vres.k, "solve_s": vms / 1e3,
+                             "gflops": vfl / (vms * 1e-3) / 1e9,
+                             "rel_err": residual_rel(torch, A, vres), "stop": vres.stop_reason})
+            log(f"[bench] variant P={vp} {vs}: k={vres.k} {vms:.1f} ms")
+
+    cpu = None
+    if not args.no_cpu:
+        log(f"[bench] timing the CPU oracle on the first {args.cpu_blocks} blocks")
+        A_host = A.cpu().numpy()
+        cpu = cpu_baseline(A_host, eps, wl, P, args.cpu_blocks)
+        log(f"[bench] cpu oracle: {cpu['seconds']:.1f} s, {cpu['value']:.1f} GFLOP/s on {cpu['cores']} threads")
+
+    line = {
+        "metric": METRIC, "value": gflops, "unit": "GFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.sample == "f64" else f"f64+{args.sample}-sampling",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "m": m, "n": n, "b": wl.b, "power_iters": P,
+                   "eps_rel": wl.eps_rel, "sample": args.sample, "k": k, "solve_s": ms / 1e3,
+                   "rel_err": rel, "stop": res.stop_reason, "blocks": res.blocks,
+                   "seeds": {"U": wl.seed_u, "V": wl.seed_v, "omega": wl.seed_omega}},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "variants": variants,
+        "kernels": kernels,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,189 @@
+/*
+ * qb.h -- C ABI of the MI355X (gfx950) blocked randomized QB library.
+ *
+ * Method: Martinsson & Voronin, "A randomized blocked algorithm for
+ * efficiently computing rank-revealing factorizations of matrices",
+ * randQB_b (Figure 4, Sections 4.1-4.4) and its power-iteration form
+ * randQB_pb (Figure 6, Section 5.2).  Given an m x n matrix A and a
+ * tolerance eps, it returns Q (m x k, orthonormal columns), B (k x n) and
+ * the rank k, built b columns at a time, such that ||A - Q B||_F <= eps
+ * (Section 1.1, problem statement; Section 4.3, adaptive rank).
+ *
+ * Conventions for every entry point
+ *   - matrices are column-major (LAPACK order); an m x n matrix X with
+ *     leading dimension ldx >= m holds entry (i, j) at X[i + j * ldx];
+ *   - matrix pointers are DEVICE pointers on the current HIP device; the
+ *     caller owns every buffer, the library allocates no device memory;
+ *   - `stream` is a hipStream_t passed as void* (NULL = default stream);
+ *     all device work is ordered on it.  Entry points that return host
+ *     values synchronise that stream before returning;
+ *   - return value: 0 on success, > 0 a warning (outputs valid), < 0 an
+ *     error (outputs undefined, *k set to 0 where present).  The library
+ *     never prints and never aborts.
+ *
+ * Not thread-safe for concurrent calls that share a workspace.
+ */
+#ifndef QB_H
+#define QB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define QB_OK               0   /* stopped with ||A - QB||_F <= eps        */
+#define QB_KMAX             1   /* k reached kmax < min(m, n) before eps   */
+#define QB_RANK_EXHAUSTED   2   /* the residual is at the rounding level of
+                                   the downdate, or k = min(m, n), or a
+                                   block kept no column, before eps        */
+#define QB_EINVAL          -1   /* invalid argument                        */
+#define QB_ENONFINITE      -2   /* A holds a NaN or an infinity            */
+#define QB_EWORKSPACE      -3   /* workspace NULL or smaller than required */
+#define QB_EHIP            -4   /* a HIP runtime call failed               */
+#define QB_ENODEVICE       -5   /* no usable gfx950 device                 */
+
+/* ---- stop reasons (qb_info.stop_reason) -------------------------------- */
+#define QB_STOP_TOL_TRACKED 0   /* ||A||^2 - sum ||B_i||^2 <= eps^2 - delta */
+#define QB_STOP_TOL_DIRECT  1   /* inside the band: ||A^(i)||_F^2 <= eps^2  */
+#define QB_STOP_RANK_CAP    2   /* k = min(m, n)                           */
+#define QB_STOP_EXHAUSTED   3   /* block kept no column / rounding floor   */
+#define QB_STOP_KMAX        4   /* k = kmax < min(m, n)                    */
+#define QB_STOP_ZERO        5   /* ||A||_F <= eps: k = 0                   */
+
+/* ---- flags ------------------------------------------------------------- */
+#define QB_OVERWRITE_A    (1u << 0)  /* A becomes the residual (Figure 4
+                                        overwrites A); no copy is made     */
+/* precision of the sampling products A*Omega, A^T*Q, A*Z (Fig. 6 (3),(5),(6)) */
+#define QB_SAMPLE_F64     (0u << 4)
+#define QB_SAMPLE_F32     (1u << 4)
+#define QB_SAMPLE_BF16X3  (2u << 4)
+#define QB_SAMPLE_MASK    (3u << 4)
+
+/* Per-call report.  The trace arrays are optional HOST arrays owned by the
+ * caller (set the pointers to NULL or trace_cap to 0 to skip).  Entry i
+ * describes block i: kept columns, tracked indicator E_i = ||A||_F^2 -
+ * sum_{j<=i} ||B_j||_F^2, and direct D_i = ||A^(i)||_F^2. */
+typedef struct qb_info {
+  int64_t k;              /* rank of the factorisation (columns of Q)      */
+  int32_t blocks;         /* number of blocks added                        */
+  int32_t stop_reason;    /* QB_STOP_*                                     */
+  double  normA2;         /* ||A||_F^2                                     */
+  double  indicator;      /* last E_i                                      */
+  double  resid2;         /* last D_i                                      */
+  int32_t trace_cap;      /* capacity of the trace arrays                  */
+  int32_t trace_len;      /* entries written (<= trace_cap)                */
+  int32_t* trace_w;       /* kept columns per block                        */
+  double* trace_E;        /* E_i per block                                 */
+  double* trace_D;        /* D_i per block                                 */
+} qb_info;
+
+/* Bytes of device workspace qb_factor needs for these sizes.
+ * kmax <= 0 means min(m, n).  Returns 0 for invalid sizes. */
+size_t qb_workspace_bytes(int64_t m, int64_t n, int32_t b, int64_t kmax, uint32_t flags);
+
+/*
+ * qb_factor -- blocked adaptive randomized QB (randQB_pb; randQB_b when
+ * power_iters = 0).
+ *
+ *  A            m x n input, lda >= m.  Read-only unless QB_OVERWRITE_A, in
+ *               which case it holds the final residual A - Q B on return.
+ *  eps          Frobenius tolerance, finite and >= 0.
+ *  b            block size >= 1.  Each block adds at most b columns.
+ *  power_iters  P >= 0 power iterations per block (Figure 6 steps (4)-(7)).
+ *  seed         64-bit seed of the Gaussian sketch: entry (i, j) of the
+ *               n x infinity sketch depends only on (seed, i, j) (Philox4x32-10
+ *               with counter (i/2, j, 0, 0), Box-Muller), so block i uses
+ *               sketch columns [k, k + w) whatever b is.
+ *  Q, ldq       output, m x kmax, ldq >= m.  Columns [0, k) are written.
+ *  B, ldb       output, kmax x n, ldb >= kmax.  Rows [0, k) are written.
+ *  kmax         capacity (max rank), 0 <= kmax <= min(m, n); kmax < 0 means
+ *               min(m, n) (then Q and B must hold min(m, n) columns/rows).
+ *  k            HOST out: the rank.
+ *  info         HOST in/out, may be NULL.
+ *  workspace    device buffer of at least qb_workspace_bytes(...) bytes,
+ *               256-byte aligned.
+ *  flags        QB_OVERWRITE_A | one QB_SAMPLE_* value.
+ *
+ * Synchronises `stream` once per block (to read the stop quantities).
+ */
+int qb_factor(const double* A, int64_t m, int64_t n, int64_t lda,
+              double eps, int32_t b, int32_t power_iters, uint64_t seed,
+              double* Q, int64_t ldq, double* B, int64_t ldb, int64_t kmax,
+              int64_t* k, qb_info* info, void* workspace, size_t ws_bytes,
+              void* stream, uint32_t flags);
+
+/* Human-readable name of a status code (static string). */
+const char* qb_status_string(int status);
+
+/* ---- component entry points (same kernels the factorisation uses) ------ */
+
+/* Columns [col0, col0 + w) of the Gaussian sketch (Figure 4 step (2);
+ * Section 4.1 eq. (OmegaBlock)): out is n x w, ld >= n, device. */
+int qb_sketch(uint64_t seed, int64_t n, int64_t col0, int32_t w,
+              double* out, int64_t ld, void* stream);
+
+/* orth(X) (Section 2.4) by Cholesky QR applied twice with column dropping:
+ * Q (m x w, ldq >= m, may alias X only if ldq == ldx) receives the kept
+ * columns first, then zero columns; *kept (HOST out) is their number.
+ * X is m x w, ldx >= m, 1 <= w <= 256.  Workspace: qb_orth_workspace_bytes. */
+size_t qb_orth_workspace_bytes(int64_t m, int32_t w);
+int qb_orth(const double* X, int64_t m, int32_t w, int64_t ldx,
+            double* Q, int64_t ldq, int32_t* kept,
+            void* workspace, size_t ws_bytes, void* stream);
+
+/* Y = X * W (m x w) in the requested sampling precision (QB_SAMPLE_*):
+ * X m x K (ldx), W K x w (ldw), Y m x w (ldy); w <= 256.  This is the
+ * product of Figure 4 step (3) and Figure 6 step (6).
+ * Workspace: qb_gemm_workspace_bytes(m, K, w). */
+size_t qb_gemm_workspace_bytes(int64_t m, int64_t K, int32_t w);
+int qb_sample(const double* X, int64_t m, int64_t K, int64_t ldx,
+              const double* W, int32_t w, int64_t ldw,
+              double* Y, int64_t ldy, uint32_t precision,
+              void* workspace, size_t ws_bytes, void* stream);
+
+/* C = Q^T X (w x N) in the requested precision: Q is K x w (ldq), X is
+ * K x N (ldx), C is w x N (ldc); w <= 256.  Figure 4 step (4), Figure 6
+ * steps (5) and (9).  Workspace: qb_gemm_workspace_bytes(N, K, w). */
+int qb_project(const double* Qm, int64_t K, int32_t w, int64_t ldq,
+               const double* X, int64_t N, int64_t ldx,
+               double* C, int64_t ldc, uint32_t precision,
+               void* workspace, size_t ws_bytes, void* stream);
+
+/* R <- R - Q B (Figure 4 step (5)) with the fused residual norm:
+ * R m x n (ldr), Q m x w (ldq), B w x n (ldb); *resid2 (HOST out, may be
+ * NULL) receives ||R||_F^2 after the update.
+ * Workspace: qb_downdate_workspace_bytes(m, n). */
+size_t qb_downdate_workspace_bytes(int64_t m, int64_t n);
+int qb_downdate(double* R, int64_t m, int64_t n, int64_t ldr,
+                const double* Qm, int32_t w, int64_t ldq,
+                const double* B, int64_t ldb, double* resid2,
+                void* workspace, size_t ws_bytes, void* stream);
+
+/* ||X||_F^2 (notation of Section 2.1) with a compensated final sum;
+ * *out (HOST) receives it, *nonfinite (HOST, may be NULL) is set to 1 if X
+ * holds a NaN or infinity.  Workspace: qb_downdate_workspace_bytes(m, n). */
+int qb_frob2(const double* X, int64_t m, int64_t n, int64_t ldx,
+             double* out, int32_t* nonfinite,
+             void* workspace, size_t ws_bytes, void* stream);
+
+/* ---- measurement ---------------------------------------------------------
+ * Optional per-kernel timing: when enabled, every kernel launch of the
+ * library is bracketed by two HIP events on the stream it runs on and
+ * tagged with the algorithmic flops and bytes of the operation (for a
+ * product of an M x K by a K x N matrix: 2 M N K flops and one read of each
+ * operand plus one write of the result).  qb_profile_enable clears the
+ * counters; qb_profile_read waits for the pending events and returns the
+ * totals for kernel class `kernel` (0 <= kernel < qb_profile_count()). */
+int qb_profile_enable(int on);
+int32_t qb_profile_count(void);
+const char* qb_profile_name(int32_t kernel);
+int qb_profile_read(int32_t kernel, double* ms, int64_t* launches, double* flops, double* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QB_H */

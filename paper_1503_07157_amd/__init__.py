@@ -1,0 +1,18 @@
+"""Blocked randomized QB factorisation (randQB_b / randQB_pb) on AMD MI355X.
+
+The computation lives in the HIP library libqbmi.so (C ABI: include/qb.h);
+this package only loads it and marshals torch tensors into its calls.
+"""
+from ._lib import QBError, load  # noqa: F401
+from .qb import (  # noqa: F401
+    QBResult,
+    colmajor,
+    downdate,
+    frob2,
+    orth,
+    project,
+    qb_factor,
+    sample_product,
+    sketch,
+    workspace_bytes,
+)

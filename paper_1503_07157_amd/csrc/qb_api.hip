@@ -1,0 +1,441 @@
+// C ABI and host driver of the blocked randomized QB factorisation
+// (randQB_b, Figure 4; randQB_pb, Figure 6).  All device work is issued on
+// the caller's stream from carved caller workspace; the only host
+// synchronisation is one small device-to-host read per block for the
+// stopping rule (Section 4.3), plus one at the start for ||A||_F.
+//
+// Per block (A is the residual, overwritten as in eq. (def3)):
+//   Omega_i = sketch columns [k, k+w)                          Fig. 4 (2)
+//   Y = A Omega_i;  Q_i = orth(Y)                               Fig. 4 (3)
+//   P times: Z = orth(A^T Q_i);  Q_i = orth(A Z)                Fig. 6 (4)-(7)
+//   Q_i = orth(Q_i - Qbar (Qbar^T Q_i))                         Fig. 4 (3')
+//   B_i = Q_i^T A;  A = A - Q_i B_i  (+ ||A||_F^2)              Fig. 4 (4),(5)
+//   stop when the residual norm is at most eps                  Fig. 4 (6)
+// The stopping quantity is tracked as E_i = ||A||^2 - sum_j ||B_j||^2
+// (Proposition 3.1 (a),(b) and Pythagoras) and, inside a band of
+// half-width 1e-13 ||A||^2 around eps^2 where E_i cannot resolve the
+// threshold, decided by the directly computed D_i = ||A^(i)||_F^2.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "../../include/qb.h"
+#include "qb_internal.hpp"
+
+namespace qb {
+int sum_partials_ex(const double* part, int count, const int* flags, double* out, int* out_flag,
+                    hipStream_t s);
+
+namespace {
+
+constexpr double kDeltaRel = 1e-13;               // hybrid band, relative to ||A||_F^2
+constexpr double kFloorRel = 0x1p-46;             // rounding floor of the residual, rel. ||A||_F
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline int64_t even_up(int64_t x) { return (x + 1) & ~int64_t(1); }
+
+// ---- double-double helpers (host) ------------------------------------------
+struct DD { double hi, lo; };
+inline DD two_sum(double a, double b) {
+  const double s = a + b;
+  const double bb = s - a;
+  return {s, (a - (s - bb)) + (b - bb)};
+}
+inline DD dd_add(DD a, DD b) {
+  DD s = two_sum(a.hi, b.hi);
+  const double e = s.lo + a.lo + b.lo;
+  return two_sum(s.hi, e);
+}
+inline double dd_val(DD a) { return a.hi + a.lo; }
+
+// ---- workspace plan ----------------------------------------------------------
+struct Work {
+  double* R = nullptr;
+  int64_t ldr = 0;
+  int64_t ldm = 0;        // leading dimension of m-row panels
+  double* omega = nullptr;  // n x b
+  double* Y = nullptr;      // m x b
+  double* Qi = nullptr;     // m x b
+  double* Z = nullptr;      // n x b
+  double* C = nullptr;      // kcap x b
+  int64_t ldc = 1;
+  double* part = nullptr;   // split-K partials
+  double* sq1 = nullptr;    // per-workgroup sums of squares (B_i, ||A||)
+  double* sq2 = nullptr;    // per-workgroup sums of squares (residual)
+  int* flags = nullptr;     // per-workgroup non-finite flags
+  double* scal = nullptr;   // [0,1] D_i (hi, lo); [2,3] ||B_i||^2; [4,5] ||A||^2
+  int* iscal = nullptr;     // [0] non-finite flag
+  OrthWork ow{};
+};
+
+size_t max_partials(int64_t m, int64_t n, int b, int64_t kcap) {
+  size_t best = 1;
+  auto upd = [&](int64_t rows, int64_t cols, int64_t K) {
+    const int s = choose_split(rows, cols, K);
+    const size_t v = partial_doubles(rows, cols, s);
+    if (v > best) best = v;
+  };
+  upd(m, b, n);                // Y = A Omega, Y = A Z
+  upd(b, n, m);                // B_i = Q^T A, (A^T Q)^T
+  for (int64_t k = 1; k <= kcap; ++k) {
+    upd(b, k, m);              // Q_i^T Qbar (split is not monotone in k)
+    upd(m, b, k);              // Qbar C
+  }
+  return best;
+}
+
+size_t max_sq(int64_t m, int64_t n, int b) {
+  size_t v = downdate_partials(m, n);
+  v = std::max(v, sumsq_partials_count(m, n));
+  v = std::max(v, static_cast<size_t>(cdiv(static_cast<int64_t>(b) * n, 256)));
+  v = std::max(v, static_cast<size_t>(cdiv(n, kTileN) * cdiv(b, kTileM)));
+  return v + 1;
+}
+
+int carve(Arena& a, int64_t m, int64_t n, int b, int64_t kcap, int power_iters, uint32_t flags,
+          Work* w) {
+  w->ldm = even_up(m);
+  if (!(flags & QB_OVERWRITE_A)) {
+    w->ldr = even_up(m);
+    w->R = a.take<double>(static_cast<size_t>(w->ldr) * n);
+  }
+  w->omega = a.take<double>(static_cast<size_t>(n) * b);
+  w->Y = a.take<double>(static_cast<size_t>(w->ldm) * b);
+  w->Qi = a.take<double>(static_cast<size_t>(w->ldm) * b);
+  if (power_iters > 0) w->Z = a.take<double>(static_cast<size_t>(n) * b);
+  w->ldc = kcap > 0 ? kcap : 1;
+  w->C = a.take<double>(static_cast<size_t>(w->ldc) * b);
+  w->part = a.take<double>(max_partials(m, n, b, kcap));
+  const size_t nsq = max_sq(m, n, b);
+  w->sq1 = a.take<double>(nsq);
+  w->sq2 = a.take<double>(nsq);
+  w->flags = a.take<int>(nsq);
+  w->scal = a.take<double>(8);
+  w->iscal = a.take<int>(4);
+  int rc = orth_carve(a, std::max(m, n), b, &w->ow);
+  if (a.base != nullptr && a.used > a.cap) return kEWorkspace;
+  return rc;
+}
+
+bool valid_sizes(int64_t m, int64_t n, int32_t b) {
+  return m >= 1 && n >= 1 && b >= 1 && b <= kMaxPanel && m < (int64_t(1) << 31) &&
+         n < (int64_t(1) << 31);
+}
+
+int sample(uint32_t prec, const double* X, int64_t ldx, const double* W, int64_t ldw, double* Y,
+           int64_t ldy, int64_t M, int64_t N, int64_t K, double* part, hipStream_t s) {
+  const int split = choose_split(M, N, K);
+  if (prec == QB_SAMPLE_F64) return gemm_nn(X, ldx, W, ldw, Y, ldy, M, N, K, 1.0, 0.0, split, part, s);
+  return gemm_nn_lowp(prec == QB_SAMPLE_F32 ? 1 : 2, X, ldx, W, ldw, Y, ldy, M, N, K, split,
+                      part, s);
+}
+
+int project_t(uint32_t prec, const double* Qm, int64_t ldq, const double* X, int64_t ldx,
+              double* C, int64_t ldc, int64_t P, int64_t N, int64_t K, bool tr, double* part,
+              double* sq, int* sqc, hipStream_t s) {
+  const int split = choose_split(P, N, K);
+  if (prec == QB_SAMPLE_F64)
+    return gemm_tn(Qm, ldq, X, ldx, C, ldc, P, N, K, tr, split, part, sq, sqc, s);
+  return gemm_tn_lowp(prec == QB_SAMPLE_F32 ? 1 : 2, Qm, ldq, X, ldx, C, ldc, P, N, K, tr, split,
+                      part, s);
+}
+
+}  // namespace
+}  // namespace qb
+
+using namespace qb;
+
+extern "C" {
+
+const char* qb_status_string(int status) {
+  switch (status) {
+    case QB_OK: return "QB_OK";
+    case QB_KMAX: return "QB_KMAX: k reached kmax before the tolerance";
+    case QB_RANK_EXHAUSTED: return "QB_RANK_EXHAUSTED: residual at rounding level or full rank";
+    case QB_EINVAL: return "QB_EINVAL: invalid argument";
+    case QB_ENONFINITE: return "QB_ENONFINITE: input holds NaN or Inf";
+    case QB_EWORKSPACE: return "QB_EWORKSPACE: workspace missing or too small";
+    case QB_EHIP: return "QB_EHIP: HIP runtime error";
+    case QB_ENODEVICE: return "QB_ENODEVICE: no usable device";
+    default: return "QB_UNKNOWN";
+  }
+}
+
+size_t qb_workspace_bytes(int64_t m, int64_t n, int32_t b, int64_t kmax, uint32_t flags) {
+  if (!valid_sizes(m, n, b)) return 0;
+  const int64_t r = std::min(m, n);
+  const int64_t kcap = (kmax < 0) ? r : std::min(kmax, r);
+  Arena a{nullptr, 0, 0};
+  Work w;
+  carve(a, m, n, std::min<int64_t>(b, r), kcap, /*power_iters=*/1, flags, &w);
+  return a.used + 256;
+}
+
+int qb_factor(const double* A, int64_t m, int64_t n, int64_t lda, double eps, int32_t b,
+              int32_t power_iters, uint64_t seed, double* Q, int64_t ldq, double* B, int64_t ldb,
+              int64_t kmax, int64_t* k_out, qb_info* info, void* workspace, size_t ws_bytes,
+              void* stream, uint32_t flags) {
+  if (k_out) *k_out = 0;
+  if (!k_out || !A || !Q || !B) return QB_EINVAL;
+  if (!valid_sizes(m, n, b) || power_iters < 0 || !(eps >= 0.0) || !std::isfinite(eps))
+    return QB_EINVAL;
+  const uint32_t prec = flags & QB_SAMPLE_MASK;
+  if (prec == QB_SAMPLE_MASK) return QB_EINVAL;
+  const int64_t r = std::min(m, n);
+  if (kmax > r) return QB_EINVAL;
+  const int64_t kcap = (kmax < 0) ? r : kmax;
+  if (lda < m || ldq < m || ldb < std::max<int64_t>(kcap, 1)) return QB_EINVAL;
+  if (workspace == nullptr) return QB_EWORKSPACE;
+  if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return QB_EINVAL;
+  const int bw = static_cast<int>(std::min<int64_t>(b, r));
+
+  Work wk;
+  Arena arena{static_cast<char*>(workspace), ws_bytes, 0};
+  if (carve(arena, m, n, bw, kcap, power_iters, flags, &wk) != kOk) return QB_EWORKSPACE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+
+  // ||A||_F^2 and the non-finite check
+  int cnt = 0;
+  if (sumsq_partials(A, lda, m, n, wk.sq1, &cnt, wk.flags, st)) return QB_EHIP;
+  if (sum_partials_ex(wk.sq1, cnt, wk.flags, wk.scal + 4, wk.iscal, st)) return QB_EHIP;
+  double hsA[2];
+  int hbad = 0;
+  if (hipMemcpyAsync(hsA, wk.scal + 4, 2 * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipMemcpyAsync(&hbad, wk.iscal, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return QB_EHIP;
+  if (hbad) return QB_ENONFINITE;
+  if (!std::isfinite(hsA[0])) return QB_EINVAL;  // ||A||_F^2 overflows a double
+  const DD sA{hsA[0], hsA[1]};
+  const double sAv = dd_val(sA);
+  const double eps2 = eps * eps;
+  const double delta = kDeltaRel * sAv;
+  const double floor2 = (kFloorRel * std::sqrt(sAv)) * (kFloorRel * std::sqrt(sAv));
+
+  int64_t k = 0;
+  int blocks = 0;
+  int reason = QB_STOP_ZERO;
+  double lastE = sAv, lastD = sAv;
+  auto finish = [&](int why) -> int {
+    *k_out = k;
+    if (info) {
+      info->k = k;
+      info->blocks = blocks;
+      info->stop_reason = why;
+      info->normA2 = sAv;
+      info->indicator = lastE;
+      info->resid2 = lastD;
+    }
+    if (why == QB_STOP_ZERO || why == QB_STOP_TOL_TRACKED || why == QB_STOP_TOL_DIRECT) return QB_OK;
+    if (why == QB_STOP_KMAX) return QB_KMAX;
+    return QB_RANK_EXHAUSTED;
+  };
+  if (info) info->trace_len = 0;
+  if (sAv <= eps2) return finish(QB_STOP_ZERO);
+
+  double* R;
+  int64_t ldr;
+  if (flags & QB_OVERWRITE_A) {
+    R = const_cast<double*>(A);
+    ldr = lda;
+  } else {
+    R = wk.R;
+    ldr = wk.ldr;
+    if (copy_matrix(A, lda, R, ldr, m, n, st)) return QB_EHIP;
+  }
+
+  DD sigB{0.0, 0.0};
+  const int64_t ldm = wk.ldm;
+  for (;;) {
+    const int w = static_cast<int>(std::min<int64_t>(bw, kcap - k));
+    if (w <= 0) { reason = (kcap < r) ? QB_STOP_KMAX : QB_STOP_RANK_CAP; break; }
+    // (2)-(3) sample the residual and orthonormalise
+    if (launch_sketch(seed, n, k, w, wk.omega, n, st)) return QB_EHIP;
+    if (sample(prec, R, ldr, wk.omega, n, wk.Y, ldm, m, w, n, wk.part, st)) return QB_EHIP;
+    if (orth_cholqr2(wk.Y, ldm, wk.Qi, ldm, m, w, wk.ow, st)) return QB_EHIP;
+    // (4)-(7) power iterations on the residual
+    for (int p = 0; p < power_iters; ++p) {
+      if (project_t(prec, wk.Qi, ldm, R, ldr, wk.Z, n, w, n, m, true, wk.part, nullptr, nullptr, st))
+        return QB_EHIP;
+      if (orth_cholqr2(wk.Z, n, wk.Z, n, n, w, wk.ow, st)) return QB_EHIP;
+      if (sample(prec, R, ldr, wk.Z, n, wk.Y, ldm, m, w, n, wk.part, st)) return QB_EHIP;
+      if (orth_cholqr2(wk.Y, ldm, wk.Qi, ldm, m, w, wk.ow, st)) return QB_EHIP;
+    }
+    double* Qout = Q + k * ldq;
+    // (3') re-projection against the basis so far, then orth
+    if (k > 0) {
+      const int sp = choose_split(w, k, m);
+      if (gemm_tn(wk.Qi, ldm, Q, ldq, wk.C, wk.ldc, w, k, m, true, sp, wk.part, nullptr, nullptr, st))
+        return QB_EHIP;
+      const int sq = choose_split(m, w, k);
+      if (gemm_nn(Q, ldq, wk.C, wk.ldc, wk.Qi, ldm, m, w, k, -1.0, 1.0, sq, wk.part, st))
+        return QB_EHIP;
+      if (orth_cholqr2(wk.Qi, ldm, Qout, ldq, m, w, wk.ow, st)) return QB_EHIP;
+    } else {
+      if (copy_matrix(wk.Qi, ldm, Qout, ldq, m, w, st)) return QB_EHIP;
+    }
+    // (4) B_i = Q_i^T A with ||B_i||^2;  (5) downdate with ||A^(i)||^2
+    int nb = 0, nd = 0;
+    {
+      const int sp = choose_split(w, n, m);
+      if (gemm_tn(Qout, ldq, R, ldr, B + k, ldb, w, n, m, false, sp, wk.part, wk.sq1, &nb, st))
+        return QB_EHIP;
+    }
+    if (sum_partials(wk.sq1, nb, wk.scal + 2, st)) return QB_EHIP;
+    if (downdate(R, ldr, Qout, ldq, B + k, ldb, m, n, w, wk.sq2, &nd, st)) return QB_EHIP;
+    if (sum_partials(wk.sq2, nd, wk.scal + 0, st)) return QB_EHIP;
+    double hs[4];
+    int wkept = 0;
+    if (hipMemcpyAsync(hs, wk.scal, 4 * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipMemcpyAsync(&wkept, wk.ow.kept, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return QB_EHIP;
+    if (wkept <= 0) { reason = QB_STOP_EXHAUSTED; break; }
+    k += wkept;
+    ++blocks;
+    sigB = dd_add(sigB, DD{hs[2], hs[3]});
+    const DD Edd = dd_add(sA, DD{-sigB.hi, -sigB.lo});
+    lastE = dd_val(Edd);
+    lastD = hs[0] + hs[1];
+    if (info && info->trace_cap > info->trace_len) {
+      const int t = info->trace_len++;
+      if (info->trace_w) info->trace_w[t] = wkept;
+      if (info->trace_E) info->trace_E[t] = lastE;
+      if (info->trace_D) info->trace_D[t] = lastD;
+    }
+    // (6) stopping rule
+    if (lastE <= eps2 - delta) { reason = QB_STOP_TOL_TRACKED; break; }
+    if (!(lastE > eps2 + delta) && lastD <= eps2) { reason = QB_STOP_TOL_DIRECT; break; }
+    if (lastD <= floor2) { reason = QB_STOP_EXHAUSTED; break; }
+    if (k >= kcap) { reason = (kcap < r) ? QB_STOP_KMAX : QB_STOP_RANK_CAP; break; }
+  }
+  return finish(reason);
+}
+
+int qb_sketch(uint64_t seed, int64_t n, int64_t col0, int32_t w, double* out, int64_t ld,
+              void* stream) {
+  if (!out || n < 1 || w < 1 || col0 < 0 || ld < n || col0 + w > (int64_t(1) << 32))
+    return QB_EINVAL;
+  return launch_sketch(seed, n, col0, w, out, ld, static_cast<hipStream_t>(stream)) ? QB_EHIP
+                                                                                    : QB_OK;
+}
+
+size_t qb_orth_workspace_bytes(int64_t m, int32_t w) {
+  if (m < 1 || w < 1 || w > kMaxPanel) return 0;
+  return orth_work_bytes(m, w);
+}
+
+int qb_orth(const double* X, int64_t m, int32_t w, int64_t ldx, double* Q, int64_t ldq,
+            int32_t* kept, void* workspace, size_t ws_bytes, void* stream) {
+  if (kept) *kept = 0;
+  if (!X || !Q || m < 1 || w < 1 || w > kMaxPanel || ldx < m || ldq < m) return QB_EINVAL;
+  if (Q == X && ldq != ldx) return QB_EINVAL;
+  if (!workspace) return QB_EWORKSPACE;
+  Arena a{static_cast<char*>(workspace), ws_bytes, 0};
+  OrthWork ow;
+  if (orth_carve(a, m, w, &ow) != kOk) return QB_EWORKSPACE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (orth_cholqr2(X, ldx, Q, ldq, m, w, ow, st)) return QB_EHIP;
+  int hk = 0;
+  if (hipMemcpyAsync(&hk, ow.kept, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return QB_EHIP;
+  if (kept) *kept = hk;
+  return QB_OK;
+}
+
+size_t qb_gemm_workspace_bytes(int64_t m, int64_t K, int32_t w) {
+  if (m < 1 || K < 0 || w < 1 || w > kMaxPanel) return 0;
+  const int s = choose_split(m, w, K);
+  return (partial_doubles(m, w, s) + 1) * sizeof(double) + 256;
+}
+
+int qb_sample(const double* X, int64_t m, int64_t K, int64_t ldx, const double* W, int32_t w,
+              int64_t ldw, double* Y, int64_t ldy, uint32_t precision, void* workspace,
+              size_t ws_bytes, void* stream) {
+  if (!X || !W || !Y || m < 1 || K < 1 || w < 1 || w > kMaxPanel || ldx < m || ldw < K || ldy < m)
+    return QB_EINVAL;
+  if (precision != QB_SAMPLE_F64 && precision != QB_SAMPLE_F32 && precision != QB_SAMPLE_BF16X3)
+    return QB_EINVAL;
+  if (!workspace || ws_bytes < qb_gemm_workspace_bytes(m, K, w)) return QB_EWORKSPACE;
+  double* part = reinterpret_cast<double*>((reinterpret_cast<uintptr_t>(workspace) + 255) & ~uintptr_t(255));
+  return sample(precision, X, ldx, W, ldw, Y, ldy, m, w, K, part, static_cast<hipStream_t>(stream))
+             ? QB_EHIP : QB_OK;
+}
+
+int qb_project(const double* Qm, int64_t K, int32_t w, int64_t ldq, const double* X, int64_t N,
+               int64_t ldx, double* C, int64_t ldc, uint32_t precision, void* workspace,
+               size_t ws_bytes, void* stream) {
+  if (!Qm || !X || !C || K < 1 || N < 1 || w < 1 || w > kMaxPanel || ldq < K || ldx < K || ldc < w)
+    return QB_EINVAL;
+  if (precision != QB_SAMPLE_F64 && precision != QB_SAMPLE_F32 && precision != QB_SAMPLE_BF16X3)
+    return QB_EINVAL;
+  if (!workspace || ws_bytes < qb_gemm_workspace_bytes(N, K, w)) return QB_EWORKSPACE;
+  double* part = reinterpret_cast<double*>((reinterpret_cast<uintptr_t>(workspace) + 255) & ~uintptr_t(255));
+  return project_t(precision, Qm, ldq, X, ldx, C, ldc, w, N, K, false, part, nullptr, nullptr,
+                   static_cast<hipStream_t>(stream)) ? QB_EHIP : QB_OK;
+}
+
+size_t qb_downdate_workspace_bytes(int64_t m, int64_t n) {
+  if (m < 1 || n < 1) return 0;
+  const size_t v = std::max(downdate_partials(m, n), sumsq_partials_count(m, n)) + 1;
+  return v * (sizeof(double) + sizeof(int)) + 8 * sizeof(double) + 4 * 256;
+}
+
+static int small_scratch(void* workspace, size_t ws_bytes, int64_t m, int64_t n, double** sq,
+                         int** fl, double** scal, int** iscal) {
+  const size_t v = std::max(downdate_partials(m, n), sumsq_partials_count(m, n)) + 1;
+  Arena a{static_cast<char*>(workspace), ws_bytes, 0};
+  *sq = a.take<double>(v);
+  *fl = a.take<int>(v);
+  *scal = a.take<double>(8);
+  *iscal = a.take<int>(4);
+  return a.used > a.cap ? QB_EWORKSPACE : QB_OK;
+}
+
+int qb_downdate(double* R, int64_t m, int64_t n, int64_t ldr, const double* Qm, int32_t w,
+                int64_t ldq, const double* B, int64_t ldb, double* resid2, void* workspace,
+                size_t ws_bytes, void* stream) {
+  if (!R || !Qm || !B || m < 1 || n < 1 || w < 1 || ldr < m || ldq < m || ldb < w)
+    return QB_EINVAL;
+  if (!workspace) return QB_EWORKSPACE;
+  double *sq, *scal;
+  int *fl, *iscal;
+  if (small_scratch(workspace, ws_bytes, m, n, &sq, &fl, &scal, &iscal)) return QB_EWORKSPACE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int cnt = 0;
+  if (downdate(R, ldr, Qm, ldq, B, ldb, m, n, w, sq, &cnt, st)) return QB_EHIP;
+  if (resid2) {
+    if (sum_partials(sq, cnt, scal, st)) return QB_EHIP;
+    double h[2];
+    if (hipMemcpyAsync(h, scal, 2 * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return QB_EHIP;
+    *resid2 = h[0] + h[1];
+  }
+  return QB_OK;
+}
+
+int qb_frob2(const double* X, int64_t m, int64_t n, int64_t ldx, double* out, int32_t* nonfinite,
+             void* workspace, size_t ws_bytes, void* stream) {
+  if (!X || !out || m < 1 || n < 1 || ldx < m) return QB_EINVAL;
+  if (!workspace) return QB_EWORKSPACE;
+  double *sq, *scal;
+  int *fl, *iscal;
+  if (small_scratch(workspace, ws_bytes, m, n, &sq, &fl, &scal, &iscal)) return QB_EWORKSPACE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int cnt = 0;
+  if (sumsq_partials(X, ldx, m, n, sq, &cnt, fl, st)) return QB_EHIP;
+  if (sum_partials_ex(sq, cnt, fl, scal, iscal, st)) return QB_EHIP;
+  double h[2];
+  int bad = 0;
+  if (hipMemcpyAsync(h, scal, 2 * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipMemcpyAsync(&bad, iscal, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return QB_EHIP;
+  *out = h[0] + h[1];
+  if (nonfinite) *nonfinite = bad;
+  return QB_OK;
+}
+
+}  // extern "C"

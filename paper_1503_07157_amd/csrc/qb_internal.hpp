@@ -1,0 +1,143 @@
+// Internal declarations shared by the HIP translation units of the QB
+// library.  Not part of the public C ABI (include/qb.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace qb {
+
+// ---- status codes (mirror include/qb.h) ----------------------------------
+constexpr int kOk = 0;
+constexpr int kEInval = -1;
+constexpr int kENonfinite = -2;
+constexpr int kEWorkspace = -3;
+constexpr int kEHip = -4;
+constexpr int kENoDevice = -5;
+
+#define QB_HIP_TRY(expr)                                 \
+  do {                                                   \
+    hipError_t qb_err_ = (expr);                         \
+    if (qb_err_ != hipSuccess) return ::qb::kEHip;       \
+  } while (0)
+
+// ---- GEMM tiling shared by the FP64 kernels ------------------------------
+constexpr int kTileM = 128;      // workgroup output rows
+constexpr int kTileN = 128;      // workgroup output columns
+constexpr int kTileK = 16;       // reduction depth staged per LDS fill
+constexpr int kGemmThreads = 256;
+constexpr int kMaxSplit = 256;   // split-K partial buffers (upper bound)
+constexpr int64_t kSplitTargetWG = 1024;        // workgroups a split-K launch aims for
+constexpr int64_t kSplitMinDepth = 128;         // smallest reduction depth per workgroup
+constexpr int64_t kPartialCapDoubles = int64_t(16) << 20;  // 128 MiB of partials at most
+constexpr int kMaxPanel = 256;   // widest block (b) supported by orth
+
+// Workspace arena: bump allocator over a caller buffer, 256-byte aligned.
+struct Arena {
+  char* base;
+  size_t cap;
+  size_t used;
+  template <class T>
+  T* take(size_t count) {
+    size_t off = (used + 255) & ~size_t(255);
+    size_t bytes = count * sizeof(T);
+    if (base == nullptr) { used = off + bytes; return nullptr; }  // sizing pass
+    if (off + bytes > cap) { used = off + bytes; return nullptr; }
+    used = off + bytes;
+    return reinterpret_cast<T*>(base + off);
+  }
+};
+
+// ---- optional per-kernel timing -------------------------------------------
+// When enabled, every launch is bracketed by two HIP events on its stream
+// and tagged with the algorithmic flops and bytes of the operation it
+// performs.  Elapsed times are folded in when the counters are read.
+enum KernelId {
+  kKSketch = 0, kKGemmNN, kKGemmTN, kKReduce, kKDowndate, kKChol, kKTrinv, kKNorm, kKCopy,
+  kKGemmNNLowp, kKGemmTNLowp, kKCount
+};
+const char* kernel_name(int id);
+bool prof_enabled();
+// returns an opaque token (or -1 when profiling is off); call prof_end after the launch
+int prof_begin(int id, double flops, double bytes, hipStream_t s);
+void prof_end(int token, hipStream_t s);
+struct ProfScope {
+  int token;
+  hipStream_t s;
+  ProfScope(int id, double flops, double bytes, hipStream_t st)
+      : token(prof_enabled() ? prof_begin(id, flops, bytes, st) : -1), s(st) {}
+  ~ProfScope() { if (token >= 0) prof_end(token, s); }
+};
+
+// ---- kernel launchers (each returns a status code) ------------------------
+
+// sketch columns [col0, col0 + w) -> out (n x w, ld)
+int launch_sketch(uint64_t seed, int64_t n, int64_t col0, int w, double* out, int64_t ld,
+                  hipStream_t s);
+
+// split-K choice for an M x N product with reduction depth K (output tiles of
+// kTileM x kTileN): enough workgroups to fill the chip, at least
+// kSplitMinDepth per workgroup, partial storage bounded by kPartialCapDoubles
+int choose_split(int64_t M, int64_t N, int64_t K);
+// doubles of partial storage for an M x N product split `split` ways
+size_t partial_doubles(int64_t M, int64_t N, int split);
+
+// Y(M x N) = alpha * X(M x K, ldx) * W(K x N, ldw) + beta * Y, FP64.
+// part: split-K partial buffer (partial_doubles(M, N, split) doubles) or
+// nullptr when split == 1.
+int gemm_nn(const double* X, int64_t ldx, const double* W, int64_t ldw, double* Y, int64_t ldy,
+            int64_t M, int64_t N, int64_t K, double alpha, double beta, int split, double* part,
+            hipStream_t s);
+
+// C(P x N) = Q(K x P, ldq)^T * X(K x N, ldx), FP64; written to C (ldc) or,
+// when transpose_out, C^T to an N x P matrix (ldc).  sq_part, if non-null,
+// receives per-workgroup partial sums of squares of C (sq_count out).
+int gemm_tn(const double* Qm, int64_t ldq, const double* X, int64_t ldx, double* C, int64_t ldc,
+            int64_t P, int64_t N, int64_t K, bool transpose_out, int split, double* part,
+            double* sq_part, int* sq_count, hipStream_t s);
+
+// mixed-precision sampling variants (precision: 1 = f32, 2 = bf16x3)
+int gemm_nn_lowp(int precision, const double* X, int64_t ldx, const double* W, int64_t ldw,
+                 double* Y, int64_t ldy, int64_t M, int64_t N, int64_t K, int split,
+                 double* part, hipStream_t s);
+int gemm_tn_lowp(int precision, const double* Qm, int64_t ldq, const double* X, int64_t ldx,
+                 double* C, int64_t ldc, int64_t P, int64_t N, int64_t K, bool transpose_out,
+                 int split, double* part, hipStream_t s);
+
+// R(M x N) -= Q(M x K) * B(K x N); per-workgroup sums of squares of the
+// updated R into sq_part (count returned through sq_count).
+int downdate(double* R, int64_t ldr, const double* Qm, int64_t ldq, const double* B, int64_t ldb,
+             int64_t M, int64_t N, int64_t K, double* sq_part, int* sq_count, hipStream_t s);
+size_t downdate_partials(int64_t M, int64_t N);
+
+// per-workgroup sums of squares of X and a non-finite flag
+int sumsq_partials(const double* X, int64_t ldx, int64_t M, int64_t N, double* sq_part,
+                   int* sq_count, int* nonfinite, hipStream_t s);
+size_t sumsq_partials_count(int64_t M, int64_t N);
+// out[0] = compensated sum of part[0..count) (hi + lo)
+int sum_partials(const double* part, int count, double* out, hipStream_t s);
+
+// Y(M x N, ldy) = X(M x N, ldx)
+int copy_matrix(const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t M, int64_t N,
+                hipStream_t s);
+int zero_matrix(double* Y, int64_t ldy, int64_t M, int64_t N, hipStream_t s);
+
+// orth: CholQR2 with dropping.  X (m x w, ldx) -> Q (m x w, ldq), kept
+// columns first, zero columns after; *kept_dev receives the count.
+struct OrthWork {
+  double* gram;      // w x w
+  double* tfull;     // w x w
+  double* tinv;      // w x w
+  double* qtmp;      // m x w (ld = ldt)
+  int64_t ldt;
+  int* kept;         // device: [0] count, [1..w] kept indices
+  double* part;      // split-K partials for the Gram
+  int split;
+};
+size_t orth_work_bytes(int64_t m, int w);
+int orth_carve(Arena& a, int64_t m, int w, OrthWork* ow);
+int orth_cholqr2(const double* X, int64_t ldx, double* Q, int64_t ldq, int64_t m, int w,
+                 const OrthWork& ow, hipStream_t s);
+
+}  // namespace qb

@@ -1,0 +1,211 @@
+"""Python face of the C ABI: torch tensors in, torch tensors out.
+
+Only argument marshalling happens here: device pointers, sizes, strides and
+the current HIP stream of torch are passed to libqbmi.so, which runs every
+step on the GPU.  Matrices are column-major float64 device tensors, i.e.
+tensors of shape (m, n) with strides (1, ld), ld >= m (use
+`colmajor(x)` to obtain one).
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass, field
+
+import torch
+
+from . import _lib
+from ._lib import QBError, QBInfo, QB_SAMPLE, QB_OVERWRITE_A, QB_STOP
+
+
+def _stream(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def colmajor(x: torch.Tensor) -> torch.Tensor:
+    """Column-major (Fortran-order) float64 copy of a 2-D tensor on its device."""
+    if x.dim() != 2:
+        raise ValueError("expected a matrix")
+    m, n = x.shape
+    out = torch.empty((n, m), dtype=torch.float64, device=x.device).t()
+    out.copy_(x)
+    return out
+
+
+def _ld(x: torch.Tensor, name: str) -> int:
+    if x.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64")
+    if not x.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if x.dim() != 2:
+        raise ValueError(f"{name} must be a matrix")
+    m, n = x.shape
+    if x.stride(0) != 1 and m > 1:
+        raise ValueError(f"{name} must be column-major (stride(0) == 1)")
+    ld = x.stride(1) if n > 1 else max(m, 1)
+    return max(ld, m, 1)
+
+
+def _check(code: int, where: str) -> int:
+    if code < 0:
+        raise QBError(code, where)
+    return code
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 256) + 256, dtype=torch.uint8, device=device)
+
+
+def _aligned_ptr(ws: torch.Tensor) -> int:
+    p = ws.data_ptr()
+    return (p + 255) & ~255
+
+
+@dataclass
+class QBResult:
+    Q: torch.Tensor
+    B: torch.Tensor
+    k: int
+    status: int
+    stop_reason: str
+    normA2: float
+    indicator: float
+    resid2: float
+    blocks: int
+    widths: list = field(default_factory=list)
+    E: list = field(default_factory=list)
+    D: list = field(default_factory=list)
+    R: torch.Tensor | None = None
+
+
+def workspace_bytes(m, n, b, kmax=-1, sample="f64", overwrite=False) -> int:
+    flags = QB_SAMPLE[sample] | (QB_OVERWRITE_A if overwrite else 0)
+    return int(_lib.load().qb_workspace_bytes(m, n, b, kmax, flags))
+
+
+def qb_factor(A: torch.Tensor, eps: float, b: int, power_iters: int = 0, seed: int = 0,
+              kmax: int | None = None, sample: str = "f64", overwrite: bool = False,
+              trace_cap: int = 4096, workspace: torch.Tensor | None = None,
+              Q: torch.Tensor | None = None, B: torch.Tensor | None = None) -> QBResult:
+    """Blocked adaptive randomized QB (randQB_pb) of the column-major float64
+    device matrix A to Frobenius tolerance eps.  Returns Q[:, :k], B[:k, :]."""
+    lib = _lib.load()
+    lda = _ld(A, "A")
+    m, n = A.shape
+    r = min(m, n)
+    kcap = r if kmax is None else int(kmax)
+    dev = A.device
+    if Q is None:
+        Q = torch.empty((max(kcap, 1), m), dtype=torch.float64, device=dev).t()
+    if B is None:
+        B = torch.empty((n, max(kcap, 1)), dtype=torch.float64, device=dev).t()
+    ldq, ldb = _ld(Q, "Q"), _ld(B, "B")
+    flags = QB_SAMPLE[sample] | (QB_OVERWRITE_A if overwrite else 0)
+    need = int(lib.qb_workspace_bytes(m, n, b, kcap, flags))
+    if need == 0:
+        raise QBError(_lib.QB_EINVAL, "qb_workspace_bytes")
+    if workspace is None or workspace.numel() < need + 256:
+        workspace = _workspace(need, dev)
+    info = QBInfo()
+    tw = (ctypes.c_int32 * trace_cap)()
+    tE = (ctypes.c_double * trace_cap)()
+    tD = (ctypes.c_double * trace_cap)()
+    info.trace_cap = trace_cap
+    info.trace_w = ctypes.cast(tw, ctypes.POINTER(ctypes.c_int32))
+    info.trace_E = ctypes.cast(tE, ctypes.POINTER(ctypes.c_double))
+    info.trace_D = ctypes.cast(tD, ctypes.POINTER(ctypes.c_double))
+    k = ctypes.c_int64(0)
+    code = lib.qb_factor(A.data_ptr(), m, n, lda, float(eps), int(b), int(power_iters),
+                         int(seed) & 0xFFFFFFFFFFFFFFFF, Q.data_ptr(), ldq, B.data_ptr(), ldb,
+                         kcap, ctypes.byref(k), ctypes.byref(info), _aligned_ptr(workspace),
+                         need, _stream(dev), flags)
+    _check(code, "qb_factor")
+    kk = int(k.value)
+    L = info.trace_len
+    return QBResult(Q=Q[:, :kk], B=B[:kk, :], k=kk, status=code,
+                    stop_reason=QB_STOP.get(info.stop_reason, str(info.stop_reason)),
+                    normA2=info.normA2, indicator=info.indicator, resid2=info.resid2,
+                    blocks=info.blocks, widths=list(tw[:L]), E=list(tE[:L]), D=list(tD[:L]),
+                    R=A if overwrite else None)
+
+
+def sketch(seed: int, n: int, col0: int, w: int, device="cuda") -> torch.Tensor:
+    """Columns [col0, col0 + w) of the n x inf Gaussian sketch (column-major)."""
+    out = torch.empty((w, n), dtype=torch.float64, device=device).t()
+    _check(_lib.load().qb_sketch(int(seed) & 0xFFFFFFFFFFFFFFFF, n, col0, w, out.data_ptr(),
+                                 max(n, 1), _stream(out.device)), "qb_sketch")
+    return out
+
+
+def orth(X: torch.Tensor):
+    """CholQR2 with dropping.  Returns (Q, kept): Q has the kept columns first."""
+    lib = _lib.load()
+    ldx = _ld(X, "X")
+    m, w = X.shape
+    Qo = torch.empty((w, m), dtype=torch.float64, device=X.device).t()
+    need = int(lib.qb_orth_workspace_bytes(m, w))
+    ws = _workspace(need, X.device)
+    kept = ctypes.c_int32(0)
+    _check(lib.qb_orth(X.data_ptr(), m, w, ldx, Qo.data_ptr(), max(m, 1), ctypes.byref(kept),
+                       _aligned_ptr(ws), need, _stream(X.device)), "qb_orth")
+    return Qo, int(kept.value)
+
+
+def sample_product(X: torch.Tensor, W: torch.Tensor, precision: str = "f64") -> torch.Tensor:
+    """Y = X W with the sampling kernel."""
+    lib = _lib.load()
+    ldx, ldw = _ld(X, "X"), _ld(W, "W")
+    m, K = X.shape
+    K2, w = W.shape
+    assert K == K2
+    Y = torch.empty((w, m), dtype=torch.float64, device=X.device).t()
+    need = int(lib.qb_gemm_workspace_bytes(m, K, w))
+    ws = _workspace(need, X.device)
+    _check(lib.qb_sample(X.data_ptr(), m, K, ldx, W.data_ptr(), w, ldw, Y.data_ptr(), max(m, 1),
+                         QB_SAMPLE[precision], _aligned_ptr(ws), need, _stream(X.device)),
+           "qb_sample")
+    return Y
+
+
+def project(Qm: torch.Tensor, X: torch.Tensor, precision: str = "f64") -> torch.Tensor:
+    """C = Q^T X with the projection kernel."""
+    lib = _lib.load()
+    ldq, ldx = _ld(Qm, "Q"), _ld(X, "X")
+    K, w = Qm.shape
+    K2, N = X.shape
+    assert K == K2
+    C = torch.empty((N, w), dtype=torch.float64, device=X.device).t()
+    need = int(lib.qb_gemm_workspace_bytes(N, K, w))
+    ws = _workspace(need, X.device)
+    _check(lib.qb_project(Qm.data_ptr(), K, w, ldq, X.data_ptr(), N, ldx, C.data_ptr(), max(w, 1),
+                          QB_SAMPLE[precision], _aligned_ptr(ws), need, _stream(X.device)),
+           "qb_project")
+    return C
+
+
+def downdate(R: torch.Tensor, Qm: torch.Tensor, B: torch.Tensor) -> float:
+    """R -= Q B in place; returns ||R||_F^2 after the update."""
+    lib = _lib.load()
+    ldr, ldq, ldb = _ld(R, "R"), _ld(Qm, "Q"), _ld(B, "B")
+    m, n = R.shape
+    w = Qm.shape[1]
+    need = int(lib.qb_downdate_workspace_bytes(m, n))
+    ws = _workspace(need, R.device)
+    out = ctypes.c_double(0.0)
+    _check(lib.qb_downdate(R.data_ptr(), m, n, ldr, Qm.data_ptr(), w, ldq, B.data_ptr(), ldb,
+                           ctypes.byref(out), _aligned_ptr(ws), need, _stream(R.device)),
+           "qb_downdate")
+    return float(out.value)
+
+
+def frob2(X: torch.Tensor):
+    """(||X||_F^2, has_nonfinite)."""
+    lib = _lib.load()
+    ldx = _ld(X, "X")
+    m, n = X.shape
+    need = int(lib.qb_downdate_workspace_bytes(m, n))
+    ws = _workspace(need, X.device)
+    out = ctypes.c_double(0.0)
+    bad = ctypes.c_int32(0)
+    _check(lib.qb_frob2(X.data_ptr(), m, n, ldx, ctypes.byref(out), ctypes.byref(bad),
+                        _aligned_ptr(ws), need, _stream(X.device)), "qb_frob2")
+    return float(out.value), bool(bad.value)

@@ -1,0 +1,136 @@
+"""GPU parity of the component entry points against the CPU oracle / plain
+float64 definitions, called through the C ABI.
+
+  sketch    bit-identical to oracle.gaussian.omega_block
+  products  Y = X W, C = Q^T X, R - Q B agree with float64 products to a
+            tolerance derived from the summation length (gamma_K * |X||W|)
+  norms     ||X||_F^2 against the oracle's sum, non-finite detection
+  orth      CholQR2 with dropping against oracle.cholqr.cholqr2 (same kept
+            columns; Q equal up to rounding amplified by cond(X))
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import paper_1503_07157_amd as qbmi
+from oracle.gaussian import omega_block
+from oracle.cholqr import cholqr2
+from oracle.randqb import sumsq
+
+pytestmark = pytest.mark.gpu
+U = 2.0 ** -53
+
+
+def dev(x: np.ndarray) -> torch.Tensor:
+    return qbmi.colmajor(torch.from_numpy(np.ascontiguousarray(x)).cuda())
+
+
+def host(t: torch.Tensor) -> np.ndarray:
+    return t.cpu().numpy()
+
+
+@pytest.mark.parametrize("seed,n,col0,w", [
+    (1503, 1000, 0, 50), (1503, 1000, 600, 50), (0, 7, 0, 3), (2**64 - 1, 1001, 12345, 17),
+    (42, 10000, 9984, 16), (7, 1, 0, 1), (99, 2, 4000000, 256),
+])
+def test_sketch_bitwise(cuda, seed, n, col0, w):
+    got = host(qbmi.sketch(seed, n, col0, w))
+    want = omega_block(seed, n, col0, w)
+    assert got.shape == want.shape
+    assert np.array_equal(got.view(np.uint64), want.view(np.uint64))
+
+
+def _rng(seed):
+    return np.random.default_rng(seed)
+
+
+@pytest.mark.parametrize("m,K,w", [(300, 500, 50), (129, 1000, 128), (2000, 1000, 50),
+                                   (1, 1, 1), (257, 33, 200), (1000, 4100, 256)])
+def test_sample_product(cuda, m, K, w):
+    r = _rng(m + K + w)
+    X = np.asfortranarray(r.standard_normal((m, K)))
+    W = np.asfortranarray(r.standard_normal((K, w)))
+    Y = host(qbmi.sample_product(dev(X), dev(W)))
+    ref = X @ W
+    bound = 2 * K * U * (np.abs(X) @ np.abs(W))
+    assert np.all(np.abs(Y - ref) <= bound + 1e-300)
+
+
+@pytest.mark.parametrize("K,w,N", [(500, 50, 300), (1000, 128, 129), (2000, 50, 1000),
+                                   (1, 1, 1), (4100, 256, 257), (33, 7, 2000)])
+def test_project(cuda, K, w, N):
+    r = _rng(K * 3 + w + N)
+    Qm = np.asfortranarray(r.standard_normal((K, w)))
+    X = np.asfortranarray(r.standard_normal((K, N)))
+    C = host(qbmi.project(dev(Qm), dev(X)))
+    ref = Qm.T @ X
+    bound = 2 * K * U * (np.abs(Qm).T @ np.abs(X))
+    assert np.all(np.abs(C - ref) <= bound + 1e-300)
+
+
+@pytest.mark.parametrize("m,n,w", [(300, 200, 50), (129, 257, 128), (1, 1, 1), (1000, 900, 256)])
+def test_downdate_and_norm(cuda, m, n, w):
+    r = _rng(m + n * 7 + w)
+    R0 = np.asfortranarray(r.standard_normal((m, n)))
+    Qm = np.asfortranarray(r.standard_normal((m, w)))
+    B = np.asfortranarray(r.standard_normal((w, n)))
+    Rd = dev(R0)
+    d2 = qbmi.downdate(Rd, dev(Qm), dev(B))
+    ref = R0 - Qm @ B
+    got = host(Rd)
+    bound = 2 * (w + 1) * U * (np.abs(R0) + np.abs(Qm) @ np.abs(B))
+    assert np.all(np.abs(got - ref) <= bound)
+    assert abs(d2 - sumsq(got)) <= 1e-13 * sumsq(got)
+
+
+def test_frob2_and_nonfinite(cuda):
+    r = _rng(5)
+    X = np.asfortranarray(r.standard_normal((777, 333)) * 1e100)
+    s, bad = qbmi.frob2(dev(X))
+    assert not bad
+    assert abs(s - sumsq(X)) <= 1e-14 * s
+    for v in (np.nan, np.inf, -np.inf):
+        Y = X.copy(order="F")
+        Y[400, 200] = v
+        assert qbmi.frob2(dev(Y))[1]
+    # huge but finite values do not count as non-finite
+    Z = np.full((10, 10), 1e200, order="F")
+    s, bad = qbmi.frob2(dev(Z))
+    assert not bad and math.isinf(s)
+
+
+def _cond_matrix(m, w, cond, seed):
+    r = _rng(seed)
+    u, _ = np.linalg.qr(r.standard_normal((m, w)))
+    v, _ = np.linalg.qr(r.standard_normal((w, w)))
+    return np.asfortranarray((u * np.logspace(0, -np.log10(cond), w)) @ v.T)
+
+
+@pytest.mark.parametrize("m,w,cond", [(500, 50, 10.0), (2000, 128, 1e4), (3000, 256, 1e5),
+                                      (64, 64, 1e2), (1000, 1, 1.0), (333, 100, 1e6)])
+def test_orth_matches_oracle(cuda, m, w, cond):
+    X = _cond_matrix(m, w, cond, seed=m + w)
+    Qg, kept = qbmi.orth(dev(X))
+    Qo, ko = cholqr2(X)
+    assert kept == len(ko) == w
+    Qg = host(Qg)
+    assert np.linalg.norm(Qg.T @ Qg - np.eye(w)) < 20 * U * w
+    assert np.linalg.norm(Qg - Qo) < 1e-13 * cond * w
+
+
+def test_orth_drops_dependent_and_zero_columns(cuda):
+    r = _rng(6)
+    x = r.standard_normal((400, 5))
+    X = np.asfortranarray(np.column_stack([x[:, 0], x[:, 1], x[:, 0] - 3 * x[:, 1], np.zeros(400),
+                                           x[:, 2], x[:, 3], x[:, 2] + x[:, 3], x[:, 4]]))
+    Qg, kept = qbmi.orth(dev(X))
+    Qo, ko = cholqr2(X)
+    assert ko == [0, 1, 4, 5, 7] and kept == 5
+    Qg = host(Qg)
+    assert np.linalg.norm(Qg[:, :5] - Qo) < 1e-12
+    assert np.all(Qg[:, 5:] == 0.0)
+    Z = np.zeros((50, 4), order="F")
+    Qz, kz = qbmi.orth(dev(Z))
+    assert kz == 0 and np.all(host(Qz) == 0.0)

@@ -1,0 +1,98 @@
+"""GPU checks of the mixed-precision sampling forms (FP32 and bf16x3 MFMA).
+
+The sampling products only choose the subspace (Figure 4 step (3), Figure 6
+steps (5)-(6)); orth, B = Q^T A, the downdate and the stopping rule stay in
+float64.  A sample with relative error delta (2^-24 for f32, about 2^-16 for
+bf16x3) leaves a first-order leftover of relative size ~delta of the captured
+directions in the residual, which later blocks must pick up.  So:
+  * the error bound ||A - QB|| <= eps always holds (float64 downdate and
+    stopping quantity);
+  * the rank equals the float64 oracle's when eps_rel >> delta, and may
+    exceed it by whole blocks when eps_rel is below delta.
+Bars:
+  products   |Y - X W| <= 4 u_p K |X||W| elementwise, u_p = delta
+  factor     rank and widths equal to the oracle's when eps_rel >= 30 delta;
+             otherwise k >= oracle k; always Q orthonormal to float64
+             rounding and ||A - QB|| <= eps checked directly; Q B within
+             2 eps of the oracle's (triangle inequality)
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import paper_1503_07157_amd as qbmi
+import synth
+from oracle import randqb_pb
+from oracle.randqb import sumsq
+
+pytestmark = pytest.mark.gpu
+UNIT = {"f32": 2.0 ** -24, "bf16x3": 2.0 ** -16}
+
+
+def dev(x):
+    return qbmi.colmajor(torch.from_numpy(np.ascontiguousarray(x)).cuda())
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16x3"])
+@pytest.mark.parametrize("m,K,w", [(300, 500, 50), (129, 1000, 128), (1000, 4100, 256), (1, 3, 1)])
+def test_lowp_sample_product(cuda, prec, m, K, w):
+    r = np.random.default_rng(m + K + w)
+    X = np.asfortranarray(r.standard_normal((m, K)))
+    W = np.asfortranarray(r.standard_normal((K, w)))
+    Y = qbmi.sample_product(dev(X), dev(W), prec).cpu().numpy()
+    ref = X @ W
+    bound = 4 * UNIT[prec] * K * (np.abs(X) @ np.abs(W))
+    assert np.all(np.abs(Y - ref) <= bound)
+    # and it is not silently the float64 product
+    if K > 100:
+        assert np.max(np.abs(Y - ref)) > 1e-14 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16x3"])
+@pytest.mark.parametrize("K,w,N", [(500, 50, 300), (4100, 256, 257), (33, 7, 2000)])
+def test_lowp_project(cuda, prec, K, w, N):
+    r = np.random.default_rng(K + w + N)
+    Qm = np.asfortranarray(r.standard_normal((K, w)))
+    X = np.asfortranarray(r.standard_normal((K, N)))
+    C = qbmi.project(dev(Qm), dev(X), prec).cpu().numpy()
+    ref = Qm.T @ X
+    bound = 4 * UNIT[prec] * K * (np.abs(Qm).T @ np.abs(X))
+    assert np.all(np.abs(C - ref) <= bound)
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16x3"])
+@pytest.mark.parametrize("P", [0, 1])
+@pytest.mark.parametrize("eps_rel", [1e-6, 1e-3])
+def test_mixed_factor_small_workload(cuda, prec, P, eps_rel):
+    w = synth.workload("exp40_2000x1000")
+    A = synth.workload_matrix(w.name)
+    nA = math.sqrt(sumsq(A))
+    eps = eps_rel * nA
+    g = qbmi.qb_factor(dev(A), eps, w.b, P, w.seed_omega, sample=prec)
+    o = randqb_pb(A, eps, w.b, P, w.seed_omega)
+    print(f"[case] prec={prec} P={P} eps_rel={eps_rel} k_gpu={g.k} k_oracle={o.k}", flush=True)
+    if eps_rel >= 30 * UNIT[prec]:
+        assert g.k == o.k and g.widths == o.widths
+    else:
+        assert g.k >= o.k
+    Q, B = g.Q.cpu().numpy(), g.B.cpu().numpy()
+    assert np.linalg.norm(Q.T @ Q - np.eye(g.k)) < 1e-12
+    assert np.linalg.norm(A - Q @ B) <= eps * (1 + 1e-9)
+    assert np.linalg.norm(Q @ B - o.Q @ o.B) <= 2 * eps
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16x3"])
+def test_mixed_exact_rank(cuda, prec):
+    A = synth.exact_rank(300, 200, 37, seed=4, cond=1e3)
+    nA = np.linalg.norm(A)
+    # tolerance far above the sampling precision: stops at the true rank
+    g = qbmi.qb_factor(dev(A), 1e-2 * nA, 16, 0, 3, sample=prec)
+    o = randqb_pb(A, 1e-2 * nA, 16, 0, 3)
+    assert g.k == o.k
+    # tolerance below it: accurate, at the cost of extra blocks
+    g = qbmi.qb_factor(dev(A), 1e-10 * nA, 16, 0, 3, sample=prec)
+    Q, B = g.Q.cpu().numpy(), g.B.cpu().numpy()
+    assert g.k >= 37
+    assert np.linalg.norm(A - Q @ B) <= 1e-10 * nA

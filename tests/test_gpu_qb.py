@@ -1,0 +1,133 @@
+"""GPU parity of qb_factor against the CPU oracle (oracle.randqb.randqb_pb),
+called through the C ABI on the same seeded inputs.
+
+Bar (float64): identical rank k and per-block kept widths; Q B and the final
+residual agree with the oracle to 1e-10 relative to ||A||_F; the GPU's own
+Q is orthonormal to rounding level; the tracked and direct stop quantities
+agree with the oracle's per block.  Q itself is compared only through Q B and
+Q Q^T, which do not depend on rounding-level choices inside orth.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import paper_1503_07157_amd as qbmi
+import synth
+from oracle import randqb_pb, STOP
+from oracle.randqb import sumsq
+
+pytestmark = pytest.mark.gpu
+U = 2.0 ** -53
+STATUS_NAMES = {v: k for k, v in STOP.items()}
+
+
+def dev(x):
+    return qbmi.colmajor(torch.from_numpy(np.ascontiguousarray(x)).cuda())
+
+
+def run_both(A, eps, b, P=0, seed=0, kmax=None, tol=1e-10):
+    nA = math.sqrt(sumsq(A))
+    Ad = dev(A)
+    g = qbmi.qb_factor(Ad, eps, b, P, seed, kmax=kmax)
+    o = randqb_pb(A, eps, b, P, seed, kmax=kmax)
+    print(f"[case] m={A.shape[0]} n={A.shape[1]} b={b} P={P} seed={seed} eps={eps:.3e} "
+          f"k_gpu={g.k} k_oracle={o.k} stop={g.stop_reason}/{STATUS_NAMES[o.stop_reason]}", flush=True)
+    assert g.k == o.k
+    assert g.widths == o.widths
+    assert g.stop_reason == STATUS_NAMES[o.stop_reason]
+    assert g.status == o.status
+    Q = g.Q.cpu().numpy()
+    B = g.B.cpu().numpy()
+    if g.k:
+        assert np.linalg.norm(Q.T @ Q - np.eye(g.k)) < 50 * U * math.sqrt(g.k) * b
+        assert np.linalg.norm(Q @ B - o.Q @ o.B) <= tol * nA
+        Rg = A - Q @ B
+        assert np.linalg.norm(Rg - o.R) <= tol * nA
+        for Eg, Eo, Dg, Do in zip(g.E, o.E, g.D, o.D):
+            assert abs(Eg - Eo) <= 1e-12 * nA ** 2
+            assert abs(Dg - Do) <= 1e-12 * nA ** 2 + 1e-6 * Do
+    return g, o
+
+
+@pytest.mark.parametrize("m,n,b,P", [(300, 200, 16, 0), (300, 200, 16, 1), (257, 129, 32, 0),
+                                     (129, 257, 32, 1), (500, 500, 50, 2), (64, 1000, 7, 0)])
+def test_prescribed_spectrum(cuda, m, n, b, P):
+    s = synth.spectrum("exp", min(m, n), scale=12.0)
+    A = synth.prescribed_svd(m, n, s, 10 + m, 20 + n)
+    nA = math.sqrt(sumsq(A))
+    run_both(A, 1e-6 * nA, b, P, seed=m * n + b)
+
+
+def test_small_workload_exp40(cuda):
+    w = synth.workload("exp40_2000x1000")
+    A = synth.workload_matrix(w.name)
+    nA = math.sqrt(sumsq(A))
+    g, o = run_both(A, w.eps_rel * nA, w.b, 0, w.seed_omega)
+    assert g.k == o.k == 650
+    assert math.sqrt(g.D[-1]) <= w.eps_rel * nA
+
+
+@pytest.mark.parametrize("r", [16, 48, 55])
+def test_exact_rank(cuda, r):
+    A = synth.exact_rank(200, 120, r, seed=30 + r, cond=1e3)
+    g, o = run_both(A, 0.0, 16, 0, seed=2)
+    assert g.k == r and g.stop_reason == "EXHAUSTED"
+
+
+def test_sigma_orthonormal_closed_form(cuda):
+    A = synth.orthonormal_scaled(150, 100, 3.0, seed=12)
+    g, _ = run_both(A, 3.0 * math.sqrt(100 - 40 + 0.5), 16, 0, seed=1)
+    assert g.k == 48
+    for i, D in enumerate(g.D):
+        assert abs(D - 9.0 * (100 - 16 * (i + 1))) < 1e-11 * 900
+
+
+def test_kmax_rank_cap_and_tiny(cuda):
+    s = synth.spectrum("power", 60, p=0.5)
+    A = synth.prescribed_svd(80, 60, s, 7, 8)
+    g, _ = run_both(A, 1e-12 * np.linalg.norm(A), 16, 0, seed=1, kmax=40)
+    assert g.k == 40 and g.stop_reason == "KMAX"
+    g, _ = run_both(A, 0.0, 16, 0, seed=1)
+    assert g.k == 60
+    for (m, n, b) in [(1, 1, 1), (3, 5, 2), (8, 3, 8), (2, 7, 3)]:
+        r = np.random.default_rng(m * 10 + n)
+        run_both(np.asfortranarray(r.standard_normal((m, n))), 0.0, b, 0, seed=b)
+
+
+def test_zero_and_large_eps(cuda):
+    Z = np.zeros((10, 7), order="F")
+    g = qbmi.qb_factor(dev(Z), 0.0, 4)
+    assert g.k == 0 and g.stop_reason == "ZERO"
+    A = synth.exact_rank(30, 20, 5, seed=1)
+    g = qbmi.qb_factor(dev(A), np.linalg.norm(A) * 1.01, 4)
+    assert g.k == 0 and g.stop_reason == "ZERO"
+
+
+def test_nonfinite_input_rejected(cuda):
+    A = np.ones((20, 10), order="F")
+    A[3, 4] = np.nan
+    with pytest.raises(qbmi.QBError) as e:
+        qbmi.qb_factor(dev(A), 0.1, 4)
+    assert e.value.code == -2
+
+
+def test_overwrite_leaves_residual(cuda):
+    s = synth.spectrum("exp", 100, scale=8.0)
+    A = synth.prescribed_svd(150, 100, s, 3, 4)
+    Ad = dev(A)
+    g = qbmi.qb_factor(Ad, 1e-8 * np.linalg.norm(A), 16, 0, 5, overwrite=True)
+    R = Ad.cpu().numpy()
+    Q, B = g.Q.cpu().numpy(), g.B.cpu().numpy()
+    assert np.linalg.norm(R - (A - Q @ B)) < 1e-13 * np.linalg.norm(A)
+
+
+def test_deterministic_bitwise(cuda):
+    s = synth.spectrum("power", 400, p=1.0)
+    A = synth.prescribed_svd(600, 400, s, 5, 6)
+    Ad = dev(A)
+    g1 = qbmi.qb_factor(Ad, 1e-3 * np.linalg.norm(A), 32, 1, 9)
+    g2 = qbmi.qb_factor(Ad, 1e-3 * np.linalg.norm(A), 32, 1, 9)
+    assert g1.k == g2.k
+    assert torch.equal(g1.Q, g2.Q) and torch.equal(g1.B, g2.B)
