@@ -98,11 +98,14 @@ def _stop_decision(E: float, D: float, eps2: float, delta: float):
 
 def randqb_pb(A: np.ndarray, eps: float, b: int, power_iters: int = 0, seed: int = 0,
               kmax: int | None = None, omega_fn=None, drop_rel: float = DROP_REL,
-              reorth: bool = True) -> QBResult:
+              reorth: bool = True, power_orth: bool = True) -> QBResult:
     """Blocked adaptive QB of A (m x n) to Frobenius tolerance eps.
 
     omega_fn(n, col0, w) -> n x w, if given, replaces the Philox sketch (used
-    by tests that need a prescribed Omega).  reorth=False skips step (3').
+    by tests that need a prescribed Omega).  reorth=False skips step (3')
+    (Section 4.4).  power_orth=False skips the orthonormalisation between
+    applications of A and A^T (the variant examined in Sections 5.4 and
+    6.4): Y = (A A^T)^P A Omega_i, then Q_i = orth(Y).
     """
     A = np.asarray(A, dtype=np.float64)
     m, n = A.shape
@@ -139,17 +142,22 @@ def randqb_pb(A: np.ndarray, eps: float, b: int, power_iters: int = 0, seed: int
         # (2)-(3): sample the current residual and orthonormalise
         Om = omega_fn(n, k, w)
         Y = R @ Om
-        Qi, kept = cholqr2(Y, drop_rel)
-        # (4)-(7): power iterations on the residual, orth after every product
-        for _ in range(power_iters):
-            if not kept:
-                break
-            Z, kz = cholqr2(R.T @ Qi, drop_rel)
-            if not kz:
-                kept = []
-                break
-            Qi, kq = cholqr2(R @ Z, drop_rel)
-            kept = kq
+        if power_orth:
+            Qi, kept = cholqr2(Y, drop_rel)
+            # (4)-(7): power iterations on the residual, orth after every product
+            for _ in range(power_iters):
+                if not kept:
+                    break
+                Z, kz = cholqr2(R.T @ Qi, drop_rel)
+                if not kz:
+                    kept = []
+                    break
+                Qi, kq = cholqr2(R @ Z, drop_rel)
+                kept = kq
+        else:
+            for _ in range(power_iters):
+                Y = R @ (R.T @ Y)
+            Qi, kept = cholqr2(Y, drop_rel)
         # (3') / (8): re-project against the basis found so far, then orth
         if kept and reorth and k > 0:
             Qbar = np.hstack(Qcols)

@@ -5,17 +5,21 @@
 //   gemm_nn   Y = X W            A Omega_i, A Z, Qbar C, Y T^{-1}   (K = long or b)
 //   gemm_tn   C = Q^T X          Q_i^T A, Q_i^T Qbar, Y^T Y         (K = m, long)
 //   downdate  R = R - Q_i B_i    with the fused residual sum of squares
-// A workgroup of 256 threads (4 waves) owns a 128 x 128 output tile; each
-// wave owns a 64 x 64 sub-tile as 4 x 4 blocks of v_mfma_f64_16x16x4_f64.
-// Operand tiles of depth 16 are staged through LDS with register
-// prefetch of the next depth slice.  Long reductions are split over
-// workgroups (split-K) into partial buffers that a second kernel sums in a
-// fixed order, so results are bitwise reproducible run to run.
+// A workgroup of 256 threads (4 waves, 2 x 2) owns a BM x BN output tile
+// (128 x 128 for the bulk products, 64 x 64 for small outputs); each wave
+// owns a (BM/2) x (BN/2) sub-tile as 16 x 16 blocks of
+// v_mfma_f64_16x16x4_f64.  Operand tiles of depth 16 pass through two LDS
+// stages with register prefetch of the slice after; one LDS-only barrier
+// per slice.  Long reductions are split over workgroups (split-K) into
+// partial buffers that a second kernel sums in a fixed order, so results
+// are bitwise reproducible run to run.
 //
 // MFMA f64 16x16x4 lane layout (measured on gfx950):
 //   A operand  lane l holds A[l % 16][l / 16]        (16 x 4)
 //   B operand  lane l holds B[l / 16][l % 16]        (4 x 16)
 //   result     lane l, element r holds D[l / 16 + 4 r][l % 16]
+#include <cstdlib>
+
 #include "qb_internal.hpp"
 
 namespace qb {
@@ -23,116 +27,192 @@ namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-constexpr int BM = kTileM, BN = kTileN, BK = kTileK, NT = kGemmThreads;
-constexpr int SA_M = BM + 1;  // A stored [k][m] (m contiguous)
-constexpr int SA_K = BK + 1;  // A stored [m][k] (k contiguous)
-constexpr int SB_K = BK + 1;  // B stored [n][k] (k contiguous)
-constexpr int A_LDS = (BK * SA_M > BM * SA_K) ? BK * SA_M : BM * SA_K;
-constexpr int B_LDS = BN * SB_K;
-constexpr int PER_THREAD = (BM * BK) / NT;  // 8 elements of each operand per fill
+constexpr int BK = kTileK, NT = kGemmThreads;
 
-// A is "m-contiguous" when its global layout has consecutive rows adjacent
-// (X column-major, element (m, k) at X[m + k*ld]); "k-contiguous" when
-// element (m, k) lies at X[k + m*ld] (the transposed operand Q^T).
-template <bool A_KCONTIG>
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+template <int BM_, int BN_>
+struct Shape {
+  static constexpr int BM = BM_, BN = BN_;
+  static constexpr int WM = BM / 2, WN = BN / 2;    // wave sub-tile
+  static constexpr int IB = WM / 16, JB = WN / 16;  // MFMA blocks per wave
+  static constexpr int SA_M = BM + 1;               // A stored [k][m] (m contiguous)
+  static constexpr int SA_K = BK + 1;               // A stored [m][k] (k contiguous)
+  static constexpr int SB_K = BK + 1;               // B stored [n][k] (k contiguous)
+  static constexpr int A_LDS = (BK * SA_M > BM * SA_K) ? BK * SA_M : BM * SA_K;
+  static constexpr int B_LDS = BN * SB_K;
+  static constexpr int PA = (BM * BK) / NT, PB = (BN * BK) / NT;  // elements per thread per fill
+};
+// Big: two LDS stages of A and B take 69.6 KB, so two workgroups share a
+// CU's 160 KB.  Small: a quarter of the work per workgroup, for outputs
+// too small to give every CU a 128 x 128 tile.
+using Big = Shape<128, 128>;
+using Small = Shape<64, 64>;
+static_assert(Big::BM == kTileM && Big::BN == kTileN, "tile constants");
+
+// A is "m-contiguous" when element (m, k) lies at X[m + k*ld] (column-major
+// X); "k-contiguous" when it lies at X[k + m*ld] (the transposed operand Q^T).
+// B is always k-contiguous: element (k, n) at B[k + n*ld].
+template <class S, bool A_KCONTIG>
 struct Tile {
-  double ra[PER_THREAD];
-  double rb[PER_THREAD];
+  double ra[S::PA];
+  double rb[S::PB];
 
+  // 32-bit element offsets inside a tile (the launcher checks that 128 * ld
+  // fits); the tile base pointer is uniform across the workgroup.
   __device__ __forceinline__ void load(const double* __restrict__ A, int64_t lda,
                                        const double* __restrict__ Bm, int64_t ldb, int64_t m0,
                                        int64_t n0, int64_t M, int64_t N, int64_t kc,
                                        int64_t kend) {
     const int t = threadIdx.x;
+    const int64_t mlim = M - m0, nlim = N - n0, klim = kend - kc;
+    const uint32_t la = static_cast<uint32_t>(lda), lb = static_cast<uint32_t>(ldb);
+    const double* abase = A_KCONTIG ? A + kc + m0 * lda : A + m0 + kc * lda;
+    const double* bbase = Bm + kc + n0 * ldb;
 #pragma unroll
-    for (int q = 0; q < PER_THREAD; ++q) {
+    for (int q = 0; q < S::PA; ++q) {
       const int e = t + NT * q;
       if (A_KCONTIG) {
         const int kk = e % BK, i = e / BK;
-        const int64_t gm = m0 + i, gk = kc + kk;
-        ra[q] = (gm < M && gk < kend) ? A[gk + gm * lda] : 0.0;
+        ra[q] = (i < mlim && kk < klim)
+                    ? abase[static_cast<uint32_t>(kk) + static_cast<uint32_t>(i) * la] : 0.0;
       } else {
-        const int row = e % BM, col = e / BM;
-        const int64_t gm = m0 + row, gk = kc + col;
-        ra[q] = (gm < M && gk < kend) ? A[gm + gk * lda] : 0.0;
+        const int row = e % S::BM, col = e / S::BM;
+        ra[q] = (row < mlim && col < klim)
+                    ? abase[static_cast<uint32_t>(row) + static_cast<uint32_t>(col) * la] : 0.0;
       }
+    }
+#pragma unroll
+    for (int q = 0; q < S::PB; ++q) {
+      const int e = t + NT * q;
       const int kk = e % BK, nn = e / BK;
-      const int64_t gn = n0 + nn, gk = kc + kk;
-      rb[q] = (gn < N && gk < kend) ? Bm[gk + gn * ldb] : 0.0;
+      rb[q] = (nn < nlim && kk < klim)
+                  ? bbase[static_cast<uint32_t>(kk) + static_cast<uint32_t>(nn) * lb] : 0.0;
     }
   }
 
   __device__ __forceinline__ void store(double* As, double* Bs) const {
     const int t = threadIdx.x;
 #pragma unroll
-    for (int q = 0; q < PER_THREAD; ++q) {
+    for (int q = 0; q < S::PA; ++q) {
       const int e = t + NT * q;
-      if (A_KCONTIG) {
-        As[(e / BK) * SA_K + (e % BK)] = ra[q];
-      } else {
-        As[(e / BM) * SA_M + (e % BM)] = ra[q];
-      }
-      Bs[(e / BK) * SB_K + (e % BK)] = rb[q];
+      if (A_KCONTIG) As[(e / BK) * S::SA_K + (e % BK)] = ra[q];
+      else As[(e / S::BM) * S::SA_M + (e % S::BM)] = ra[q];
+    }
+#pragma unroll
+    for (int q = 0; q < S::PB; ++q) {
+      const int e = t + NT * q;
+      Bs[(e / BK) * S::SB_K + (e % BK)] = rb[q];
     }
   }
 };
 
-// Accumulate the workgroup tile over k in [kbeg, kend).
-template <bool A_KCONTIG>
+// MFMA row permutation: the A operand of lane l carries tile row
+// perm(l % 16), perm(rho) = 4 (rho % 4) + rho / 4.  With the result layout
+// D[l/16 + 4r][l%16] this puts rows 4 (l / 16) + r, r = 0..3, in the four
+// result elements of lane l: every lane holds four consecutive rows of one
+// column, so epilogues move them with 16-byte accesses.
+__device__ __forceinline__ int perm16(int rho) { return 4 * (rho & 3) + (rho >> 2); }
+
+// Accumulate the workgroup tile over k in [kbeg, kend).  As/Bs hold two
+// LDS stages each.
+template <class S, bool A_KCONTIG>
 __device__ __forceinline__ void mma_loop(const double* __restrict__ A, int64_t lda,
                                          const double* __restrict__ Bm, int64_t ldb, int64_t m0,
                                          int64_t n0, int64_t M, int64_t N, int64_t kbeg,
-                                         int64_t kend, double* As, double* Bs, d4 acc[4][4]) {
+                                         int64_t kend, double* As, double* Bs,
+                                         d4 (&acc)[S::IB][S::JB]) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int wm = (wave & 1) * 64, wn = (wave >> 1) * 64;
+  const int wm = (wave & 1) * S::WM, wn = (wave >> 1) * S::WN;
   const int lr = lane & 15, lk = lane >> 4;
+  const int pr = perm16(lr);
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < S::IB; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = (d4){0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < S::JB; ++j) acc[i][j] = (d4){0.0, 0.0, 0.0, 0.0};
   if (kbeg >= kend) return;
 
-  Tile<A_KCONTIG> tl;
+  Tile<S, A_KCONTIG> tl;
   tl.load(A, lda, Bm, ldb, m0, n0, M, N, kbeg, kend);
   tl.store(As, Bs);
-  __syncthreads();
+  if (kbeg + BK < kend) tl.load(A, lda, Bm, ldb, m0, n0, M, N, kbeg + BK, kend);
+  lds_barrier();
+  int stage = 0;
   for (int64_t kc = kbeg; kc < kend; kc += BK) {
-    const bool more = kc + BK < kend;
-    if (more) tl.load(A, lda, Bm, ldb, m0, n0, M, N, kc + BK, kend);
+    // stage the next slice (already in registers) into the other buffer and
+    // start fetching the one after it
+    if (kc + BK < kend) {
+      tl.store(As + (stage ^ 1) * S::A_LDS, Bs + (stage ^ 1) * S::B_LDS);
+      if (kc + 2 * BK < kend) tl.load(A, lda, Bm, ldb, m0, n0, M, N, kc + 2 * BK, kend);
+    }
+    const double* Ac = As + stage * S::A_LDS;
+    const double* Bc = Bs + stage * S::B_LDS;
 #pragma unroll
     for (int k4 = 0; k4 < BK / 4; ++k4) {
-      double a[4], b[4];
+      double a[S::IB], b[S::JB];
       const int kq = 4 * k4 + lk;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int mrow = wm + 16 * i + lr;
-        a[i] = A_KCONTIG ? As[mrow * SA_K + kq] : As[kq * SA_M + mrow];
+      for (int i = 0; i < S::IB; ++i) {
+        const int mrow = wm + 16 * i + pr;
+        a[i] = A_KCONTIG ? Ac[mrow * S::SA_K + kq] : Ac[kq * S::SA_M + mrow];
       }
 #pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = Bs[(wn + 16 * j + lr) * SB_K + kq];
+      for (int j = 0; j < S::JB; ++j) b[j] = Bc[(wn + 16 * j + lr) * S::SB_K + kq];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < S::IB; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < S::JB; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
-    __syncthreads();
-    if (more) {
-      tl.store(As, Bs);
-      __syncthreads();
-    }
+    lds_barrier();
+    stage ^= 1;
   }
 }
 
-// row / column of accumulator element (i, j, r) inside the workgroup tile
-__device__ __forceinline__ int acc_row(int i, int r) {
+// first of the four consecutive tile rows held by this lane for block i,
+// and the tile column for block j
+template <class S>
+__device__ __forceinline__ int acc_row0(int i) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  return (wave & 1) * 64 + 16 * i + (lane >> 4) + 4 * r;
+  return (wave & 1) * S::WM + 16 * i + 4 * (lane >> 4);
 }
+template <class S>
 __device__ __forceinline__ int acc_col(int j) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  return (wave >> 1) * 64 + 16 * j + (lane & 15);
+  return (wave >> 1) * S::WN + 16 * j + (lane & 15);
+}
+
+// four consecutive rows [row0, row0 + 4) of column col of X (ld); vec: X and
+// ld allow 16-byte accesses at even rows
+__device__ __forceinline__ d4 load4(const double* __restrict__ X, int64_t ld, int64_t row0,
+                                    int64_t col, int64_t M, int64_t N, bool vec) {
+  d4 v = (d4){0.0, 0.0, 0.0, 0.0};
+  if (col >= N) return v;
+  const double* p = X + row0 + col * ld;
+  if (vec && row0 + 3 < M) {
+    const double2 lo = *reinterpret_cast<const double2*>(p);
+    const double2 hi = *reinterpret_cast<const double2*>(p + 2);
+    v = (d4){lo.x, lo.y, hi.x, hi.y};
+  } else {
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      if (row0 + r < M) v[r] = p[r];
+  }
+  return v;
+}
+__device__ __forceinline__ void store4(double* __restrict__ X, int64_t ld, int64_t row0,
+                                       int64_t col, int64_t M, int64_t N, bool vec, d4 v) {
+  if (col >= N) return;
+  double* p = X + row0 + col * ld;
+  if (vec && row0 + 3 < M) {
+    *reinterpret_cast<double2*>(p) = make_double2(v[0], v[1]);
+    *reinterpret_cast<double2*>(p + 2) = make_double2(v[2], v[3]);
+  } else {
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      if (row0 + r < M) p[r] = v[r];
+  }
 }
 
 // deterministic workgroup sum; every thread passes its value, thread 0
@@ -152,112 +232,115 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 
 // ---------------------------------------------------------------------------
 // Y = alpha X W + beta Y   (X: M x K m-contiguous, W: K x N, k-contiguous)
-// grid: (M tiles, N tiles, split); split > 1 writes part[z][M x N]
+// grid: (M tiles, N tiles, split); split > 1 writes part[z] (M x N, ld ldp)
+template <class S>
 __global__ __launch_bounds__(NT, 2) void gemm_nn_kernel(const double* __restrict__ X, int64_t ldx,
                                                         const double* __restrict__ W, int64_t ldw,
                                                         double* __restrict__ Y, int64_t ldy,
                                                         int64_t M, int64_t N, int64_t K,
                                                         int64_t kchunk, double alpha, double beta,
-                                                        double* __restrict__ part) {
-  __shared__ double As[A_LDS];
-  __shared__ double Bs[B_LDS];
-  const int64_t m0 = static_cast<int64_t>(blockIdx.x) * BM;
-  const int64_t n0 = static_cast<int64_t>(blockIdx.y) * BN;
+                                                        double* __restrict__ part, int64_t ldp,
+                                                        int vec_y) {
+  __shared__ double As[2 * S::A_LDS];
+  __shared__ double Bs[2 * S::B_LDS];
+  const int64_t m0 = static_cast<int64_t>(blockIdx.x) * S::BM;
+  const int64_t n0 = static_cast<int64_t>(blockIdx.y) * S::BN;
   const int64_t kbeg = static_cast<int64_t>(blockIdx.z) * kchunk;
   const int64_t kend = (kbeg + kchunk < K) ? kbeg + kchunk : K;
-  d4 acc[4][4];
-  mma_loop<false>(X, ldx, W, ldw, m0, n0, M, N, kbeg, kend, As, Bs, acc);
+  d4 acc[S::IB][S::JB];
+  mma_loop<S, false>(X, ldx, W, ldw, m0, n0, M, N, kbeg, kend, As, Bs, acc);
   if (part != nullptr) {
-    double* P = part + static_cast<int64_t>(blockIdx.z) * M * N;
+    double* P = part + static_cast<int64_t>(blockIdx.z) * ldp * N;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < S::IB; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int64_t col = n0 + acc_col(j);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int64_t row = m0 + acc_row(i, r);
-          if (row < M && col < N) P[row + col * M] = acc[i][j][r];
-        }
-      }
+      for (int j = 0; j < S::JB; ++j)
+        store4(P, ldp, m0 + acc_row0<S>(i), n0 + acc_col<S>(j), M, N, true, acc[i][j]);
   } else {
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < S::IB; ++i) {
+      d4 old[S::JB];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int64_t col = n0 + acc_col(j);
+      for (int j = 0; j < S::JB; ++j)
+        old[j] = (beta != 0.0)
+                     ? load4(Y, ldy, m0 + acc_row0<S>(i), n0 + acc_col<S>(j), M, N, vec_y)
+                     : (d4){0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int64_t row = m0 + acc_row(i, r);
-          if (row < M && col < N) {
-            double v = alpha * acc[i][j][r];
-            if (beta != 0.0) v += beta * Y[row + col * ldy];
-            Y[row + col * ldy] = v;
-          }
-        }
-      }
+      for (int j = 0; j < S::JB; ++j)
+        store4(Y, ldy, m0 + acc_row0<S>(i), n0 + acc_col<S>(j), M, N, vec_y,
+               alpha * acc[i][j] + beta * old[j]);
+    }
   }
 }
 
 // C = Q^T X  (Q: K x P so A = Q^T is k-contiguous; X: K x N)
 // grid: (N tiles, P tiles, split)
+template <class S>
 __global__ __launch_bounds__(NT, 2) void gemm_tn_kernel(const double* __restrict__ Qm, int64_t ldq,
                                                         const double* __restrict__ X, int64_t ldx,
                                                         double* __restrict__ C, int64_t ldc,
                                                         int64_t P, int64_t N, int64_t K,
                                                         int64_t kchunk, int transpose_out,
-                                                        double* __restrict__ part,
-                                                        double* __restrict__ sq_part) {
-  __shared__ double As[A_LDS];
-  __shared__ double Bs[B_LDS];
+                                                        double* __restrict__ part, int64_t ldp,
+                                                        double* __restrict__ sq_part, int vec_c) {
+  __shared__ double As[2 * S::A_LDS];
+  __shared__ double Bs[2 * S::B_LDS];
   __shared__ double red[NT / 64];
-  const int64_t n0 = static_cast<int64_t>(blockIdx.x) * BN;
-  const int64_t m0 = static_cast<int64_t>(blockIdx.y) * BM;
+  const int64_t n0 = static_cast<int64_t>(blockIdx.x) * S::BN;
+  const int64_t m0 = static_cast<int64_t>(blockIdx.y) * S::BM;
   const int64_t kbeg = static_cast<int64_t>(blockIdx.z) * kchunk;
   const int64_t kend = (kbeg + kchunk < K) ? kbeg + kchunk : K;
-  d4 acc[4][4];
-  mma_loop<true>(Qm, ldq, X, ldx, m0, n0, P, N, kbeg, kend, As, Bs, acc);
+  d4 acc[S::IB][S::JB];
+  mma_loop<S, true>(Qm, ldq, X, ldx, m0, n0, P, N, kbeg, kend, As, Bs, acc);
+  if (part != nullptr) {
+    double* Pp = part + static_cast<int64_t>(blockIdx.z) * ldp * N;
+#pragma unroll
+    for (int i = 0; i < S::IB; ++i)
+#pragma unroll
+      for (int j = 0; j < S::JB; ++j)
+        store4(Pp, ldp, m0 + acc_row0<S>(i), n0 + acc_col<S>(j), P, N, true, acc[i][j]);
+    return;
+  }
   double sq = 0.0;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < S::IB; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int64_t col = n0 + acc_col(j);
+    for (int j = 0; j < S::JB; ++j) {
+      const int64_t row0 = m0 + acc_row0<S>(i), col = n0 + acc_col<S>(j);
+      if (transpose_out) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t row = m0 + acc_row(i, r);
-        if (row < P && col < N) {
-          const double v = acc[i][j][r];
-          if (part != nullptr) {
-            part[static_cast<int64_t>(blockIdx.z) * P * N + row + col * P] = v;
-          } else {
-            if (transpose_out) C[col + row * ldc] = v; else C[row + col * ldc] = v;
-            sq += v * v;
-          }
-        }
+        for (int r = 0; r < 4; ++r)
+          if (row0 + r < P && col < N) C[col + (row0 + r) * ldc] = acc[i][j][r];
+      } else {
+        store4(C, ldc, row0, col, P, N, vec_c, acc[i][j]);
       }
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (row0 + r < P && col < N) sq += acc[i][j][r] * acc[i][j][r];
     }
-  if (part == nullptr && sq_part != nullptr) {
+  if (sq_part != nullptr) {
     const double tot = block_sum(sq, red);
     if (threadIdx.x == 0) sq_part[blockIdx.x + static_cast<int64_t>(blockIdx.y) * gridDim.x] = tot;
   }
 }
 
-// out(M x N) = alpha * sum_s part[s] + beta * out; transposed store puts
-// element (i, j) at out[j + i*ldo].  Optional per-block sums of squares.
+// out(M x N) = alpha * sum_s part[s] + beta * out; part[s] has ld ldp;
+// transposed store puts element (i, j) at out[j + i*ldo].  Optional
+// per-block sums of squares of the result.
 __global__ __launch_bounds__(256) void reduce_kernel(const double* __restrict__ part, int split,
-                                                     double* __restrict__ out, int64_t ldo,
-                                                     int64_t M, int64_t N, double alpha,
-                                                     double beta, int transpose_out,
+                                                     int64_t ldp, double* __restrict__ out,
+                                                     int64_t ldo, int64_t M, int64_t N,
+                                                     double alpha, double beta, int transpose_out,
                                                      double* __restrict__ sq_part) {
   __shared__ double red[4];
   const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   const int64_t total = M * N;
   double sq = 0.0;
   if (idx < total) {
-    double s = 0.0;
-    for (int z = 0; z < split; ++z) s += part[static_cast<int64_t>(z) * total + idx];
     const int64_t i = idx % M, j = idx / M;
+    const int64_t pidx = i + j * ldp, pstride = ldp * N;
+    double s = 0.0;
+    for (int z = 0; z < split; ++z) s += part[z * pstride + pidx];
     const int64_t o = transpose_out ? (j + i * ldo) : (i + j * ldo);
     double v = alpha * s;
     if (beta != 0.0) v += beta * out[o];
@@ -272,47 +355,93 @@ __global__ __launch_bounds__(256) void reduce_kernel(const double* __restrict__ 
 
 // R -= Q B; per-workgroup sum of squares of the updated tile.
 // grid: (M tiles, N tiles)
+template <class S>
 __global__ __launch_bounds__(NT, 2) void downdate_kernel(double* __restrict__ R, int64_t ldr,
                                                          const double* __restrict__ Qm,
                                                          int64_t ldq,
                                                          const double* __restrict__ B,
                                                          int64_t ldb, int64_t M, int64_t N,
                                                          int64_t K,
-                                                         double* __restrict__ sq_part) {
-  __shared__ double As[A_LDS];
-  __shared__ double Bs[B_LDS];
+                                                         double* __restrict__ sq_part,
+                                                         int vec_r) {
+  __shared__ double As[2 * S::A_LDS];
+  __shared__ double Bs[2 * S::B_LDS];
   __shared__ double red[NT / 64];
-  const int64_t m0 = static_cast<int64_t>(blockIdx.x) * BM;
-  const int64_t n0 = static_cast<int64_t>(blockIdx.y) * BN;
-  d4 acc[4][4];
-  mma_loop<false>(Qm, ldq, B, ldb, m0, n0, M, N, 0, K, As, Bs, acc);
+  const int64_t m0 = static_cast<int64_t>(blockIdx.x) * S::BM;
+  const int64_t n0 = static_cast<int64_t>(blockIdx.y) * S::BN;
+  d4 acc[S::IB][S::JB];
+  mma_loop<S, false>(Qm, ldq, B, ldb, m0, n0, M, N, 0, K, As, Bs, acc);
   double sq = 0.0;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < S::IB; ++i) {
+    const int64_t row0 = m0 + acc_row0<S>(i);
+    d4 rv[S::JB];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int64_t col = n0 + acc_col(j);
+    for (int j = 0; j < S::JB; ++j) rv[j] = load4(R, ldr, row0, n0 + acc_col<S>(j), M, N, vec_r);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t row = m0 + acc_row(i, r);
-        if (row < M && col < N) {
-          const double v = R[row + col * ldr] - acc[i][j][r];
-          R[row + col * ldr] = v;
-          sq += v * v;
-        }
-      }
+    for (int j = 0; j < S::JB; ++j) {
+      const int64_t col = n0 + acc_col<S>(j);
+      const d4 v = rv[j] - acc[i][j];
+      store4(R, ldr, row0, col, M, N, vec_r, v);
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (row0 + r < M && col < N) sq += v[r] * v[r];
     }
+  }
   const double tot = block_sum(sq, red);
   if (threadIdx.x == 0) sq_part[blockIdx.x + static_cast<int64_t>(blockIdx.y) * gridDim.x] = tot;
 }
 
-inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+int64_t part_ld(int64_t M) { return (M + 1) & ~int64_t(1); }
+
+int64_t kchunk_for(int64_t K, int split) {
+  const int64_t c = cdiv(K, split);
+  return cdiv(c, BK) * BK;
+}
+
+int vec_ok(const double* p, int64_t ld) {
+  return ((reinterpret_cast<uintptr_t>(p) & 15) == 0 && (ld & 1) == 0) ? 1 : 0;
+}
+
+// tile loads use 32-bit element offsets: 128 rows/columns times ld must fit
+bool ld_fits(int64_t ld) { return ld >= 0 && ld < (int64_t(1) << 24); }
+
+template <class S>
+void launch_nn(const double* X, int64_t ldx, const double* W, int64_t ldw, double* Y,
+               int64_t ldy, int64_t M, int64_t N, int64_t K, int64_t kc, int nz, double alpha,
+               double beta, double* part, int64_t ldp, hipStream_t s) {
+  const dim3 grid(static_cast<unsigned>(cdiv(M, S::BM)), static_cast<unsigned>(cdiv(N, S::BN)),
+                  static_cast<unsigned>(nz));
+  hipLaunchKernelGGL(gemm_nn_kernel<S>, grid, dim3(NT), 0, s, X, ldx, W, ldw, Y, ldy, M, N, K,
+                     kc, alpha, beta, part, ldp, vec_ok(Y, ldy));
+}
+
+template <class S>
+dim3 launch_tn(const double* Qm, int64_t ldq, const double* X, int64_t ldx, double* C,
+               int64_t ldc, int64_t P, int64_t N, int64_t K, int64_t kc, int nz, bool tr,
+               double* part, int64_t ldp, double* sq_part, hipStream_t s) {
+  const dim3 grid(static_cast<unsigned>(cdiv(N, S::BN)), static_cast<unsigned>(cdiv(P, S::BM)),
+                  static_cast<unsigned>(nz));
+  hipLaunchKernelGGL(gemm_tn_kernel<S>, grid, dim3(NT), 0, s, Qm, ldq, X, ldx, C, ldc, P, N, K,
+                     kc, tr ? 1 : 0, part, ldp, sq_part, vec_ok(C, ldc));
+  return grid;
+}
 
 }  // namespace
 
-int choose_split(int64_t M, int64_t N, int64_t K) {
-  const int64_t tiles = cdiv(M, BM) * cdiv(N, BN);
-  int64_t s = cdiv(kSplitTargetWG, tiles > 0 ? tiles : 1);
+int choose_split(int64_t M, int64_t N, int64_t K, int slots_per_cu) {
+  // Workgroups resident at once: 256 CUs x slots_per_cu.  A split that
+  // leaves a partial second round costs as much as a full one, so take the
+  // largest split that still fits in one round of 128 x 128 tiles
+  // (QB_SPLIT_TARGET overrides the number of resident workgroups).
+  static const int64_t target = [] {
+    const char* e = getenv("QB_SPLIT_TARGET");
+    const long v = e ? atol(e) : 0;
+    return v > 0 ? static_cast<int64_t>(v) : int64_t(0);
+  }();
+  const int64_t slots = target > 0 ? target : int64_t(kNumCU) * slots_per_cu;
+  const int64_t tiles = cdiv(M, kTileM) * cdiv(N, kTileN);
+  int64_t s = tiles > 0 ? slots / tiles : 1;
   const int64_t by_depth = K / kSplitMinDepth;
   if (s > by_depth) s = by_depth;
   const int64_t by_mem = kPartialCapDoubles / ((M * N > 0) ? M * N : 1);
@@ -323,35 +452,38 @@ int choose_split(int64_t M, int64_t N, int64_t K) {
 }
 
 size_t partial_doubles(int64_t M, int64_t N, int split) {
-  return split > 1 ? static_cast<size_t>(M) * N * split : 0;
-}
-
-static int64_t kchunk_for(int64_t K, int split) {
-  int64_t c = cdiv(K, split);
-  return cdiv(c, BK) * BK;
+  return split > 1 ? static_cast<size_t>(part_ld(M)) * N * split : 0;
 }
 
 int gemm_nn(const double* X, int64_t ldx, const double* W, int64_t ldw, double* Y, int64_t ldy,
             int64_t M, int64_t N, int64_t K, double alpha, double beta, int split, double* part,
             hipStream_t s) {
   if (M <= 0 || N <= 0) return kOk;
+  if (!ld_fits(ldx) || !ld_fits(ldw)) return kEInval;
   if (K <= 0) split = 1;
   if (split > 1 && part == nullptr) return kEInval;
   const int64_t kc = split > 1 ? kchunk_for(K, split) : (K > 0 ? K : 0);
   const int nz = split > 1 ? static_cast<int>(cdiv(K, kc)) : 1;
-  dim3 grid(static_cast<unsigned>(cdiv(M, BM)), static_cast<unsigned>(cdiv(N, BN)),
-            static_cast<unsigned>(nz));
+  const int64_t ldp = part_ld(M);
+  // unsplit products with too few 128 x 128 tiles to fill the chip (the
+  // T^{-1} application, short projections) take 64 x 64 tiles
+  const bool small = nz == 1 && cdiv(M, Big::BM) * cdiv(N, Big::BN) < kNumCU;
   {
-    ProfScope ps(kKGemmNN, 2.0 * M * N * K, 8.0 * (M * K + K * N + M * N * (beta != 0.0 ? 2 : 1)), s);
-    hipLaunchKernelGGL(gemm_nn_kernel, grid, dim3(NT), 0, s, X, ldx, W, ldw, Y, ldy, M, N, K,
-                       kc, alpha, beta, split > 1 ? part : nullptr);
+    ProfScope ps(kKGemmNN, 2.0 * M * N * K,
+                 8.0 * (M * K + K * N + M * N * (beta != 0.0 ? 2 : 1)), s);
+    double* pp = nz > 1 ? part : nullptr;
+    if (small)
+      launch_nn<Small>(X, ldx, W, ldw, Y, ldy, M, N, K, kc, nz, alpha, beta, pp, ldp, s);
+    else
+      launch_nn<Big>(X, ldx, W, ldw, Y, ldy, M, N, K, kc, nz, alpha, beta, pp, ldp, s);
   }
   QB_HIP_TRY(hipGetLastError());
-  if (split > 1) {
+  if (nz > 1) {
     const int64_t total = M * N;
     ProfScope ps(kKReduce, double(nz) * total, 8.0 * (nz + (beta != 0.0 ? 2 : 1)) * total, s);
     hipLaunchKernelGGL(reduce_kernel, dim3(static_cast<unsigned>(cdiv(total, 256))), dim3(256), 0,
-                       s, part, nz, Y, ldy, M, N, alpha, beta, 0, static_cast<double*>(nullptr));
+                       s, part, nz, ldp, Y, ldy, M, N, alpha, beta, 0,
+                       static_cast<double*>(nullptr));
     QB_HIP_TRY(hipGetLastError());
   }
   return kOk;
@@ -361,25 +493,34 @@ int gemm_tn(const double* Qm, int64_t ldq, const double* X, int64_t ldx, double*
             int64_t P, int64_t N, int64_t K, bool transpose_out, int split, double* part,
             double* sq_part, int* sq_count, hipStream_t s) {
   if (P <= 0 || N <= 0) { if (sq_count) *sq_count = 0; return kOk; }
+  if (!ld_fits(ldq) || !ld_fits(ldx)) return kEInval;
   if (K <= 0) split = 1;
   if (split > 1 && part == nullptr) return kEInval;
   const int64_t kc = split > 1 ? kchunk_for(K, split) : (K > 0 ? K : 0);
   const int nz = split > 1 ? static_cast<int>(cdiv(K, kc)) : 1;
-  dim3 grid(static_cast<unsigned>(cdiv(N, BN)), static_cast<unsigned>(cdiv(P, BM)),
-            static_cast<unsigned>(nz));
+  const int64_t ldp = part_ld(P);
+  // small outputs (the w x w Gram matrices, Q_i^T Qbar early on) take
+  // 64 x 64 tiles: four times the workgroups for the same split.  Products
+  // that return per-tile sums of squares keep the 128 x 128 tiles the
+  // partial-sum buffers are sized for.
+  const bool small = P * N <= int64_t(256) * 256 && (sq_part == nullptr || nz > 1);
+  dim3 grid;
   {
     ProfScope ps(kKGemmTN, 2.0 * P * N * K, 8.0 * (K * P + K * N + P * N), s);
-    hipLaunchKernelGGL(gemm_tn_kernel, grid, dim3(NT), 0, s, Qm, ldq, X, ldx, C, ldc, P, N, K, kc,
-                       transpose_out ? 1 : 0, split > 1 ? part : nullptr,
-                       split > 1 ? static_cast<double*>(nullptr) : sq_part);
+    double* pp = nz > 1 ? part : nullptr;
+    double* sqp = nz > 1 ? static_cast<double*>(nullptr) : sq_part;
+    grid = small ? launch_tn<Small>(Qm, ldq, X, ldx, C, ldc, P, N, K, kc, nz, transpose_out, pp,
+                                    ldp, sqp, s)
+                 : launch_tn<Big>(Qm, ldq, X, ldx, C, ldc, P, N, K, kc, nz, transpose_out, pp,
+                                  ldp, sqp, s);
   }
   QB_HIP_TRY(hipGetLastError());
-  if (split > 1) {
+  if (nz > 1) {
     const int64_t total = P * N;
     const unsigned nb = static_cast<unsigned>(cdiv(total, 256));
     ProfScope ps(kKReduce, double(nz) * total, 8.0 * (nz + 1) * total, s);
-    hipLaunchKernelGGL(reduce_kernel, dim3(nb), dim3(256), 0, s, part, nz, C, ldc, P, N, 1.0, 0.0,
-                       transpose_out ? 1 : 0, sq_part);
+    hipLaunchKernelGGL(reduce_kernel, dim3(nb), dim3(256), 0, s, part, nz, ldp, C, ldc, P, N, 1.0,
+                       0.0, transpose_out ? 1 : 0, sq_part);
     QB_HIP_TRY(hipGetLastError());
     if (sq_count) *sq_count = sq_part ? static_cast<int>(nb) : 0;
   } else {
@@ -389,17 +530,18 @@ int gemm_tn(const double* Qm, int64_t ldq, const double* X, int64_t ldx, double*
 }
 
 size_t downdate_partials(int64_t M, int64_t N) {
-  return static_cast<size_t>(cdiv(M, BM)) * static_cast<size_t>(cdiv(N, BN));
+  return static_cast<size_t>(cdiv(M, Big::BM)) * static_cast<size_t>(cdiv(N, Big::BN));
 }
 
 int downdate(double* R, int64_t ldr, const double* Qm, int64_t ldq, const double* B, int64_t ldb,
              int64_t M, int64_t N, int64_t K, double* sq_part, int* sq_count, hipStream_t s) {
   if (M <= 0 || N <= 0) { if (sq_count) *sq_count = 0; return kOk; }
-  dim3 grid(static_cast<unsigned>(cdiv(M, BM)), static_cast<unsigned>(cdiv(N, BN)));
+  if (!ld_fits(ldq) || !ld_fits(ldb)) return kEInval;
+  const dim3 grid(static_cast<unsigned>(cdiv(M, Big::BM)), static_cast<unsigned>(cdiv(N, Big::BN)));
   {
     ProfScope ps(kKDowndate, 2.0 * M * N * K, 8.0 * (2 * M * N + M * K + K * N), s);
-    hipLaunchKernelGGL(downdate_kernel, grid, dim3(NT), 0, s, R, ldr, Qm, ldq, B, ldb, M, N, K,
-                       sq_part);
+    hipLaunchKernelGGL(downdate_kernel<Big>, grid, dim3(NT), 0, s, R, ldr, Qm, ldq, B, ldb, M, N,
+                       K, sq_part, vec_ok(R, ldr));
   }
   QB_HIP_TRY(hipGetLastError());
   if (sq_count) *sq_count = static_cast<int>(grid.x * grid.y);

@@ -47,14 +47,17 @@ __device__ __forceinline__ void static_for(F&& f) {
   static_for_impl(f, std::make_integer_sequence<int, N>{});
 }
 
-template <int WMAX, int NW_>
-__global__ __launch_bounds__(64 * NW_) void chol_drop_kernel(
-    const double* __restrict__ G, int w, double* __restrict__ T, int* __restrict__ kept) {
+// Right-looking Cholesky with dropping on the register-resident lower
+// triangle of G (w x w, column-major, ld w).  emit(c, i, v) receives entry
+// T[c][i] for every i < w once column c is final (zero for i < c and for a
+// dropped column); flag[c] (LDS) is 1 for kept columns.  Leaves the kept
+// count and list in kcnt / klist (LDS) when done.
+template <int WMAX, int NW_, class Emit>
+__device__ __forceinline__ void chol_drop_core(const double* __restrict__ G, int w,
+                                               double (*lbuf)[WMAX], double* dsh, int* flag,
+                                               int* klist, int* kcnt, Emit&& emit) {
   using S = CholShape<WMAX, NW_>;
   constexpr int NW = S::NW, RA = S::RA, CB = S::CB;
-  __shared__ double lbuf[2][WMAX];
-  __shared__ double dsh[WMAX];
-  __shared__ int flag[WMAX];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
 
@@ -68,7 +71,7 @@ __global__ __launch_bounds__(64 * NW_) void chol_drop_kernel(
       }
     });
   });
-  __syncthreads();
+  lds_barrier();
   double gmax = 0.0;
   for (int c = 0; c < w; ++c) gmax = fmax(gmax, dsh[c]);
   const double thresh = kDropRel * gmax;
@@ -92,34 +95,192 @@ __global__ __launch_bounds__(64 * NW_) void chol_drop_kernel(
           if constexpr (S::valid(a, cb)) v = (i > c) ? g[a][cb] * inv : 0.0;
           if (i == c) v = sdiag;
           buf[i] = v;
-          if (i < w) T[c + static_cast<int64_t>(i) * w] = (i >= c) ? v : 0.0;
+          if (i < w) emit(c, i, (i >= c) ? v : 0.0);
         });
         if (lane == 0) flag[c] = keep ? 1 : 0;
       }
-      __syncthreads();
+      lds_barrier();
+      // rank-one update of the trailing entries held here; the LDS reads are
+      // issued in groups without branches so their latencies overlap
       double rv[RA];
       static_for<RA>([&](auto a) { rv[a] = buf[lane + 64 * a]; });
-      static_for<CB>([&](auto bb) {
-        const int j = wave + NW * bb;
-        if (j > c) {
-          const double cvb = buf[j];
+      constexpr int GS = (CB >= 32) ? 4 : 8;  // reads in flight per group
+      static_for<CB / GS>([&](auto grp) {
+        double cv[GS];
+        static_for<GS>([&](auto q) { cv[q] = buf[wave + NW * (GS * grp + q)]; });
+        static_for<GS>([&](auto q) {
+          constexpr int bb = GS * grp + q;
+          const int j = wave + NW * bb;
           static_for<RA>([&](auto a) {
             if constexpr (S::valid(a, bb)) {
               const int i = lane + 64 * a;
-              if (i >= j) g[a][bb] -= rv[a] * cvb;
+              const double upd = (j > c && i >= j) ? rv[a] * cv[q] : 0.0;
+              g[a][bb] -= upd;
             }
           });
-        }
+        });
       });
     }
   });
-  __syncthreads();
+  lds_barrier();
   if (threadIdx.x == 0) {
     int cnt = 0;
     for (int c = 0; c < w; ++c)
-      if (flag[c]) kept[1 + cnt++] = c;
-    kept[0] = cnt;
+      if (flag[c]) klist[cnt++] = c;
+    *kcnt = cnt;
   }
+  lds_barrier();
+}
+
+// Cholesky with dropping writing T (w x w, column-major) and the kept list
+// to global memory; used with trinv_kernel for panels wider than 128.
+template <int WMAX, int NW_>
+__global__ __launch_bounds__(64 * NW_) void chol_drop_kernel(
+    const double* __restrict__ G, int w, double* __restrict__ T, int* __restrict__ kept) {
+  __shared__ double lbuf[2][WMAX];
+  __shared__ double dsh[WMAX];
+  __shared__ int flag[WMAX];
+  __shared__ int klist[WMAX];
+  __shared__ int kcnt;
+  chol_drop_core<WMAX, NW_>(G, w, lbuf, dsh, flag, klist, &kcnt,
+                            [&](int c, int i, double v) { T[c + static_cast<int64_t>(i) * w] = v; });
+  for (int i = threadIdx.x; i < kcnt; i += blockDim.x) kept[1 + i] = klist[i];
+  if (threadIdx.x == 0) kept[0] = kcnt;
+}
+
+// ---- fused Cholesky + inverse for panels up to 128 wide -------------------
+//
+// T goes to LDS (row-major, odd row stride).  Dropped columns become unit
+// rows and columns, T' = T_kept (+) I, whose inverse restricted to the kept
+// rows and columns is T_kept^{-1}.  The inverse is formed in place:
+//   * 32 x 32 diagonal blocks by back substitution, one column per lane
+//     (T X = I solved from the bottom row up, register arrays with
+//     compile-time indices, broadcast LDS reads of T);
+//   * pairs of finished blocks joined by X_AB = -X_A (T_AB X_B), the two
+//     products on v_mfma_f64_16x16x4_f64, the intermediate kept in the free
+//     strictly-lower part of the LDS array.
+// Output: Tinv (w x w, column-major): column a < count is column kept[a] of
+// T'^{-1}; columns a >= count are zero.
+template <int WMAX>
+struct LdsInvShape {
+  static constexpr int TS = WMAX + 1;  // LDS row stride (odd: conflict-free MFMA fragment reads)
+  static constexpr int NW = 8;
+  static constexpr int THREADS = 64 * NW;
+};
+
+// C = alpha * A B for s x s blocks stored in LDS (row stride TS); one 16 x 16
+// output block per (wave, job) round.  Rows of A start at ra, columns of A
+// (= rows of B) at ka, columns of B at cb; output at (rc, cc).
+template <int TS>
+__device__ __forceinline__ void lds_block_product(double* M, int s, int ra, int ka, int cb, int rc,
+                                                  int cc, double alpha, int job0, int jobstep) {
+  typedef double d4 __attribute__((ext_vector_type(4)));
+  const int lane = threadIdx.x & 63;
+  const int nb = s / 16;
+  for (int job = job0; job < nb * nb; job += jobstep) {
+    const int bi = job / nb, bj = job % nb;
+    d4 acc = (d4){0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < s; k0 += 4) {
+      const double a = M[(ra + 16 * bi + (lane & 15)) * TS + ka + k0 + (lane >> 4)];
+      const double b = M[(ka + k0 + (lane >> 4)) * TS + cb + 16 * bj + (lane & 15)];
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      M[(rc + 16 * bi + (lane >> 4) + 4 * r) * TS + cc + 16 * bj + (lane & 15)] = alpha * acc[r];
+  }
+}
+
+template <int WMAX>
+__global__ __launch_bounds__(512) void chol_inv_lds_kernel(const double* __restrict__ G, int w,
+                                                           int* __restrict__ kept,
+                                                           double* __restrict__ Tinv) {
+  using L = LdsInvShape<WMAX>;
+  constexpr int TS = L::TS, NW = L::NW;
+  __shared__ double Ts[WMAX * TS];
+  __shared__ double lbuf[2][WMAX];
+  __shared__ double dsh[WMAX];
+  __shared__ int flag[WMAX];
+  __shared__ int klist[WMAX];
+  __shared__ int kcnt;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+
+  chol_drop_core<WMAX, NW>(G, w, lbuf, dsh, flag, klist, &kcnt,
+                           [&](int c, int i, double v) { Ts[c * TS + i] = v; });
+  // pad to the full WMAX x WMAX upper triangle with an identity block and
+  // turn dropped columns into unit rows/columns
+  for (int idx = threadIdx.x; idx < WMAX * WMAX; idx += blockDim.x) {
+    const int r = idx / WMAX, c = idx % WMAX;
+    if (c < r) continue;
+    const bool rpad = r >= w, cpad = c >= w;
+    const bool rdrop = !rpad && !flag[r], cdrop = !cpad && !flag[c];
+    if (rpad || cpad || rdrop || cdrop) Ts[r * TS + c] = (r == c) ? 1.0 : 0.0;
+  }
+  lds_barrier();
+
+  // 32 x 32 diagonal blocks: lanes 0..31 of waves 0..WMAX/32-1, one column each
+  if (wave < WMAX / 32 && lane < 32) {
+    const int o = 32 * wave, j = lane;
+    double x[32];
+    static_for<32>([&](auto ii) {
+      constexpr int i = 31 - ii;
+      double acc = (i == j) ? 1.0 : 0.0;
+      static_for<31 - i>([&](auto ll) {
+        constexpr int l = i + 1 + ll;
+        acc -= Ts[(o + i) * TS + o + l] * x[l];
+      });
+      x[i] = acc / Ts[(o + i) * TS + o + i];
+    });
+    static_for<32>([&](auto i) { Ts[(o + i) * TS + o + j] = x[i]; });
+  }
+  lds_barrier();
+
+  // join pairs of inverted blocks: X_AB = -X_A (T_AB X_B)
+  for (int s = 32; s < WMAX; s *= 2) {
+    const int pairs = WMAX / (2 * s);
+    // M = T_AB X_B, stored at rows [ob, ob + s), columns [oa, oa + s)
+    for (int p = 0; p < pairs; ++p) {
+      const int oa = 2 * s * p, ob = oa + s;
+      lds_block_product<TS>(Ts, s, oa, ob, ob, ob, oa, 1.0, wave, NW);
+    }
+    lds_barrier();
+    // X_AB = -X_A M, written over T_AB
+    for (int p = 0; p < pairs; ++p) {
+      const int oa = 2 * s * p, ob = oa + s;
+      // A = X_A at (oa, oa); B = M at (ob, oa); out at (oa, ob)
+      const int nb = s / 16;
+      for (int job = wave; job < nb * nb; job += NW) {
+        typedef double d4 __attribute__((ext_vector_type(4)));
+        const int bi = job / nb, bj = job % nb;
+        d4 acc = (d4){0.0, 0.0, 0.0, 0.0};
+        for (int k0 = 0; k0 < s; k0 += 4) {
+          const double a = Ts[(oa + 16 * bi + (lane & 15)) * TS + oa + k0 + (lane >> 4)];
+          const double b = Ts[(ob + k0 + (lane >> 4)) * TS + oa + 16 * bj + (lane & 15)];
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          Ts[(oa + 16 * bi + (lane >> 4) + 4 * r) * TS + ob + 16 * bj + (lane & 15)] = -acc[r];
+      }
+    }
+    lds_barrier();
+    // clear M: the joined 2s x 2s block must be upper triangular for the next level
+    for (int p = 0; p < pairs; ++p) {
+      const int oa = 2 * s * p, ob = oa + s;
+      for (int idx = threadIdx.x; idx < s * s; idx += blockDim.x)
+        Ts[(ob + idx / s) * TS + oa + idx % s] = 0.0;
+    }
+    lds_barrier();
+  }
+
+  // expanded inverse: column a <- column kept[a] of T'^{-1}
+  const int wk = kcnt;
+  for (int idx = threadIdx.x; idx < w * w; idx += blockDim.x) {
+    const int r = idx % w, a = idx / w;
+    Tinv[idx] = (a < wk) ? Ts[r * TS + klist[a]] : 0.0;
+  }
+  for (int i = threadIdx.x; i < wk; i += blockDim.x) kept[1 + i] = klist[i];
+  if (threadIdx.x == 0) kept[0] = wk;
 }
 
 // Column `a` of the inverse of the kept part Tc = T[kept][:, kept]; written
@@ -180,6 +341,15 @@ __global__ __launch_bounds__(64) void trinv_kernel(const double* __restrict__ T,
   }
 }
 
+template <int WMAX>
+int launch_chol_inv_lds(const double* G, int w, int* kept, double* Tinv, hipStream_t s) {
+  ProfScope ps(kKChol, 2.0 * double(w) * w * w / 3.0, 16.0 * w * w, s);
+  hipLaunchKernelGGL(chol_inv_lds_kernel<WMAX>, dim3(1), dim3(LdsInvShape<WMAX>::THREADS), 0, s,
+                     G, w, kept, Tinv);
+  QB_HIP_TRY(hipGetLastError());
+  return kOk;
+}
+
 template <int WMAX, int NW>
 int launch_chol_inv(const double* G, int w, double* T, int* kept, double* Tinv, hipStream_t s) {
   const double w3 = double(w) * w * w / 3.0, w2b = 16.0 * w * w;
@@ -199,9 +369,9 @@ int launch_chol_inv(const double* G, int w, double* T, int* kept, double* Tinv, 
 }
 
 int chol_inv(const double* G, int w, double* T, int* kept, double* Tinv, hipStream_t s) {
-  if (w <= 64) return launch_chol_inv<64, 4>(G, w, T, kept, Tinv, s);
-  if (w <= 128) return launch_chol_inv<128, 8>(G, w, T, kept, Tinv, s);
-  if (w <= 256) return launch_chol_inv<256, 8>(G, w, T, kept, Tinv, s);
+  if (w <= 64) return launch_chol_inv_lds<64>(G, w, kept, Tinv, s);
+  if (w <= 128) return launch_chol_inv_lds<128>(G, w, kept, Tinv, s);
+  if (w <= 256) return launch_chol_inv<256, 16>(G, w, T, kept, Tinv, s);
   return kEInval;
 }
 

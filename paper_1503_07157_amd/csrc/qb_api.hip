@@ -124,7 +124,8 @@ bool valid_sizes(int64_t m, int64_t n, int32_t b) {
 
 int sample(uint32_t prec, const double* X, int64_t ldx, const double* W, int64_t ldw, double* Y,
            int64_t ldy, int64_t M, int64_t N, int64_t K, double* part, hipStream_t s) {
-  const int split = choose_split(M, N, K);
+  // the bf16x3 form of this product runs one workgroup per CU
+  const int split = choose_split(M, N, K, prec == QB_SAMPLE_BF16X3 ? 1 : 2);
   if (prec == QB_SAMPLE_F64) return gemm_nn(X, ldx, W, ldw, Y, ldy, M, N, K, 1.0, 0.0, split, part, s);
   return gemm_nn_lowp(prec == QB_SAMPLE_F32 ? 1 : 2, X, ldx, W, ldw, Y, ldy, M, N, K, split,
                       part, s);

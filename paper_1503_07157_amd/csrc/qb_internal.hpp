@@ -22,13 +22,22 @@ constexpr int kENoDevice = -5;
     if (qb_err_ != hipSuccess) return ::qb::kEHip;       \
   } while (0)
 
+// Workgroup barrier that orders LDS traffic only.  __syncthreads() also
+// waits for every outstanding global store of the thread, which a kernel
+// that streams results to global memory between barriers does not need.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // ---- GEMM tiling shared by the FP64 kernels ------------------------------
 constexpr int kTileM = 128;      // workgroup output rows
 constexpr int kTileN = 128;      // workgroup output columns
 constexpr int kTileK = 16;       // reduction depth staged per LDS fill
 constexpr int kGemmThreads = 256;
 constexpr int kMaxSplit = 256;   // split-K partial buffers (upper bound)
-constexpr int64_t kSplitTargetWG = 1024;        // workgroups a split-K launch aims for
+constexpr int kNumCU = 256;                     // MI355X compute units
 constexpr int64_t kSplitMinDepth = 128;         // smallest reduction depth per workgroup
 constexpr int64_t kPartialCapDoubles = int64_t(16) << 20;  // 128 MiB of partials at most
 constexpr int kMaxPanel = 256;   // widest block (b) supported by orth
@@ -79,7 +88,7 @@ int launch_sketch(uint64_t seed, int64_t n, int64_t col0, int w, double* out, in
 // split-K choice for an M x N product with reduction depth K (output tiles of
 // kTileM x kTileN): enough workgroups to fill the chip, at least
 // kSplitMinDepth per workgroup, partial storage bounded by kPartialCapDoubles
-int choose_split(int64_t M, int64_t N, int64_t K);
+int choose_split(int64_t M, int64_t N, int64_t K, int slots_per_cu = 2);
 // doubles of partial storage for an M x N product split `split` ways
 size_t partial_doubles(int64_t M, int64_t N, int split);
 
