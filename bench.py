@@ -119,6 +119,10 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-blocks", type=int, default=16)
+    ap.add_argument("--matrix", default="workload", choices=["workload", "gaussian"],
+                    help="gaussian: i.i.d. N(0, 1/m) entries of the workload's shape instead of "
+                         "the prescribed spectrum (no QR in the process; used for hardware-counter "
+                         "passes, where only the launch shapes matter)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
@@ -133,8 +137,15 @@ def main():
     wl = synth.workload(args.workload)
     m, n = wl.m, wl.n
     r = min(m, n)
-    log(f"[bench] generating {wl.name} on the GPU")
-    A = synth.workload_matrix_gpu(wl.name)
+    if args.matrix == "gaussian":
+        log(f"[bench] generating a Gaussian {m}x{n} matrix on the GPU")
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(wl.seed_u)
+        A = torch.randn((n, m), generator=gen, dtype=torch.float64, device="cuda").t()
+        A.mul_(1.0 / math.sqrt(m))
+    else:
+        log(f"[bench] generating {wl.name} on the GPU")
+        A = synth.workload_matrix_gpu(wl.name)
     torch.cuda.synchronize()
     nA2, bad = qbmi.frob2(A)
     assert not bad
@@ -200,7 +211,8 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if args.sample == "f64" else f"f64+{args.sample}-sampling",
         "data": "synthetic",
-        "config": {"workload": wl.name, "m": m, "n": n, "b": wl.b, "power_iters": P,
+        "config": {"workload": wl.name if args.matrix == "workload" else f"gaussian_{m}x{n}",
+                   "m": m, "n": n, "b": wl.b, "power_iters": P,
                    "eps_rel": wl.eps_rel, "sample": args.sample, "k": k, "solve_s": ms / 1e3,
                    "rel_err": rel, "stop": res.stop_reason, "blocks": res.blocks,
                    "seeds": {"U": wl.seed_u, "V": wl.seed_v, "omega": wl.seed_omega}},

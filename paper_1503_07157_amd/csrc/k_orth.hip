@@ -8,15 +8,18 @@
 // kept columns of Q come first, in their original order, followed by zero
 // columns, and the kept count is left on the device.
 //
-// Cholesky: one workgroup, the lower triangle of G held in registers.  Row i
-// of G lives in lane i % 64 (slot i / 64), column j in wave j % NW (slot
-// j / NW).  Column c is finished by its owning wave alone (a lane shuffle
-// broadcasts the pivot), written to a double-buffered LDS row, and after a
-// single barrier every thread applies the rank-one update to the part of
-// the trailing matrix it holds.  One barrier per column.
+// Cholesky, panels up to 128 wide: one workgroup, G in LDS, right-looking
+// and blocked by 16 columns.  One wave factors a 16-column panel in
+// registers, exchanging values across lanes with readlane (no barrier
+// inside the panel); then all waves apply the trailing update
+// G22 -= L21 L21^T with v_mfma_f64_16x16x4_f64.  Pivots use the hardware
+// reciprocal square root refined by two Newton steps, so each column costs
+// one short dependent chain.  Wider panels (up to 256) keep the lower
+// triangle in registers with a rank-one update per column.
 //
-// Inverse: T^{-1} of the kept part, one workgroup (one wave) per output
-// column, by back substitution in column-oriented form.
+// Inverse: T^{-1} of the kept part, blocked in LDS (32 x 32 diagonal blocks
+// by substitution, joined with MFMA products) for panels up to 128; one
+// wave per output column by back substitution for wider panels.
 #include <utility>
 
 #include "qb_internal.hpp"
@@ -148,6 +151,164 @@ __global__ __launch_bounds__(64 * NW_) void chol_drop_kernel(
   if (threadIdx.x == 0) kept[0] = kcnt;
 }
 
+// value of v in lane l (l uniform)
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const unsigned long long u = static_cast<unsigned long long>(__double_as_longlong(v));
+  const unsigned lo = static_cast<unsigned>(
+      __builtin_amdgcn_readlane(static_cast<int>(static_cast<unsigned>(u)), l));
+  const unsigned hi = static_cast<unsigned>(
+      __builtin_amdgcn_readlane(static_cast<int>(static_cast<unsigned>(u >> 32)), l));
+  return __longlong_as_double(
+      static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
+}
+
+// 1 / sqrt(d) for d > 0: hardware estimate and two Newton steps
+// y <- y + (y/2)(1 - d y^2), accurate to a few ulps.  Arguments below
+// 2^-1000 (where the estimate loses range) take the IEEE path.
+__device__ __forceinline__ double rsqrt_refined(double d) {
+  if (d < 0x1p-1000) return 1.0 / sqrt(d);
+  double y = __builtin_amdgcn_rsq(d);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double e = fma(-(d * y), y, 1.0);
+    y = fma(0.5 * y, e, y);
+  }
+  return y;
+}
+
+constexpr int kPanel = 16;  // Cholesky panel width
+
+// Factor panel columns [p, p + 16) of the LDS matrix (Ts[j * TS + i] holds
+// L[i][j], i >= j; rows p.. hold the updated trailing part).  Run by one
+// wave: lane l holds rows p + l + 64 a.  Column c is kept when its pivot
+// exceeds thresh; a dropped column becomes zero.  Sets flag[c] and
+// rdiag[c] = 1 / L[c][c] (1 for a dropped or padding column).
+template <int WMAX>
+__device__ __forceinline__ void chol_panel(double* Ts, int p, int w, double thresh, bool gpos,
+                                           int* flag, double* rdiag) {
+  constexpr int TS = WMAX + 1, RA = WMAX / 64;
+  const int lane = threadIdx.x & 63;
+  double x[RA][kPanel];
+  static_for<kPanel>([&](auto jj) {
+    static_for<RA>([&](auto a) {
+      const int i = p + lane + 64 * a;
+      x[a][jj] = (i < WMAX) ? Ts[(p + jj) * TS + i] : 0.0;
+    });
+  });
+  static_for<kPanel>([&](auto jj) {
+    constexpr int J = decltype(jj)::value;
+    const int c = p + J;
+    const double d = readlane_d(x[0][J], J);  // row c lives in lane J, slot 0
+    const bool keep = (c < w) && gpos && (d > thresh);
+    const double r = keep ? rsqrt_refined(d) : 0.0;
+    static_for<RA>([&](auto a) {
+      const int i = p + lane + 64 * a;
+      const double v = x[a][J] * r;
+      x[a][J] = (i > c) ? v : ((i == c) ? d * r : 0.0);
+    });
+    // update the panel's later columns with this one
+    static_for<kPanel - 1 - J>([&](auto t) {
+      constexpr int K = J + 1 + decltype(t)::value;
+      const double lk = readlane_d(x[0][J], K);  // L[p + K][c]
+      static_for<RA>([&](auto a) { x[a][K] = fma(-x[a][J], lk, x[a][K]); });
+    });
+    if (lane == 0) {
+      flag[c] = keep ? 1 : 0;
+      rdiag[c] = keep ? r : 1.0;
+    }
+  });
+  static_for<kPanel>([&](auto jj) {
+    static_for<RA>([&](auto a) {
+      const int i = p + lane + 64 * a;
+      if (i < WMAX) Ts[(p + jj) * TS + i] = x[a][jj];
+    });
+  });
+}
+
+// Trailing update after panel p: L[i][j] -= sum_t L[i][p + t] L[j][p + t]
+// for p + 16 <= j <= i < 16 ceil(w / 16), as 16 x 16 MFMA blocks spread
+// over the waves (diagonal blocks are updated whole; their upper halves are
+// cleared when their own panel is written).
+template <int WMAX, int NW>
+__device__ __forceinline__ void chol_trailing(double* Ts, int p, int w) {
+  typedef double d4 __attribute__((ext_vector_type(4)));
+  constexpr int TS = WMAX + 1;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int q = p + kPanel;
+  if (q >= w) return;
+  const int nb = (w - q + 15) / 16;
+  const int jobs = nb * (nb + 1) / 2;
+  const int lr = lane & 15, lk = lane >> 4;
+  for (int job = wave; job < jobs; job += NW) {
+    int bi = static_cast<int>((sqrtf(8.0f * job + 1.0f) - 1.0f) * 0.5f);
+    while ((bi + 1) * (bi + 2) / 2 <= job) ++bi;
+    while (bi * (bi + 1) / 2 > job) --bi;
+    const int bj = job - bi * (bi + 1) / 2;
+    double a[4], b[4];
+#pragma unroll
+    for (int k4 = 0; k4 < 4; ++k4) {
+      a[k4] = Ts[(p + 4 * k4 + lk) * TS + q + 16 * bi + lr];
+      b[k4] = Ts[(p + 4 * k4 + lk) * TS + q + 16 * bj + lr];
+    }
+    d4 acc = (d4){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k4 = 0; k4 < 4; ++k4) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[k4], b[k4], acc, 0, 0, 0);
+    double* col = Ts + (q + 16 * bj + lr) * TS + q + 16 * bi + lk;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) col[4 * r] -= acc[r];
+  }
+}
+
+// Blocked Cholesky with dropping of the w x w matrix G (column-major, ld w).
+// Result in LDS: Ts[c * TS + i] = T[c][i] = L[i][c] (T = L^T upper
+// triangular, zero for i < c and in the padding up to WMAX); flag, rdiag,
+// the kept list and count.
+template <int WMAX, int NW>
+__device__ __forceinline__ void chol_blocked(const double* __restrict__ G, int w, double* Ts,
+                                             int* flag, double* rdiag, int* klist, int* kcnt) {
+  constexpr int TS = WMAX + 1;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // lower triangle of G into Ts, everything else zero
+#pragma unroll 8
+  for (int idx = threadIdx.x; idx < WMAX * WMAX; idx += 64 * NW) {
+    const int i = idx % WMAX, j = idx / WMAX;
+    Ts[j * TS + i] = (i < w && j < w && i >= j) ? G[i + static_cast<int64_t>(j) * w] : 0.0;
+  }
+  lds_barrier();
+  double gmax = 0.0;
+  if (wave == 0) {
+    for (int c = lane; c < w; c += 64) gmax = fmax(gmax, Ts[c * TS + c]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) gmax = fmax(gmax, __shfl_xor(gmax, off));
+  }
+  const double thresh = kDropRel * gmax;
+  for (int p = 0; p < w; p += kPanel) {
+    if (wave == 0) chol_panel<WMAX>(Ts, p, w, thresh, gmax > 0.0, flag, rdiag);
+    lds_barrier();
+    chol_trailing<WMAX, NW>(Ts, p, w);
+    lds_barrier();
+  }
+  // padding columns: dropped, unit pivots
+  for (int c = (w + kPanel - 1) / kPanel * kPanel + threadIdx.x; c < WMAX; c += 64 * NW) {
+    flag[c] = 0;
+    rdiag[c] = 1.0;
+  }
+  // kept list in column order: ballot + prefix count by wave 0
+  if (wave == 0) {
+    int base = 0;
+    for (int c0 = 0; c0 < w; c0 += 64) {
+      const int c = c0 + lane;
+      const bool f = (c < w) && flag[c];
+      const unsigned long long m = __ballot(f);
+      const int pos = base + __popcll(m & ((1ull << lane) - 1ull));
+      if (f) klist[pos] = c;
+      base += __popcll(m);
+    }
+    if (lane == 0) *kcnt = base;
+  }
+  lds_barrier();
+}
+
 // ---- fused Cholesky + inverse for panels up to 128 wide -------------------
 //
 // T goes to LDS (row-major, odd row stride).  Dropped columns become unit
@@ -168,23 +329,29 @@ struct LdsInvShape {
   static constexpr int THREADS = 64 * NW;
 };
 
-// C = alpha * A B for s x s blocks stored in LDS (row stride TS); one 16 x 16
-// output block per (wave, job) round.  Rows of A start at ra, columns of A
-// (= rows of B) at ka, columns of B at cb; output at (rc, cc).
-template <int TS>
-__device__ __forceinline__ void lds_block_product(double* M, int s, int ra, int ka, int cb, int rc,
-                                                  int cc, double alpha, int job0, int jobstep) {
+// C = alpha * A B for S x S blocks stored in LDS (row stride TS); one 16 x 16
+// output block per (wave, job) round.  A starts at row ra, column ka; B at
+// row kb (default ka), column cb; the output goes to (rc, cc).
+template <int TS, int S>
+__device__ __forceinline__ void lds_block_product(double* M, int ra, int ka, int cb, int rc, int cc,
+                                                  double alpha, int job0, int jobstep,
+                                                  int kb = -1) {
   typedef double d4 __attribute__((ext_vector_type(4)));
   const int lane = threadIdx.x & 63;
-  const int nb = s / 16;
+  constexpr int nb = S / 16;
+  if (kb < 0) kb = ka;
   for (int job = job0; job < nb * nb; job += jobstep) {
     const int bi = job / nb, bj = job % nb;
-    d4 acc = (d4){0.0, 0.0, 0.0, 0.0};
-    for (int k0 = 0; k0 < s; k0 += 4) {
-      const double a = M[(ra + 16 * bi + (lane & 15)) * TS + ka + k0 + (lane >> 4)];
-      const double b = M[(ka + k0 + (lane >> 4)) * TS + cb + 16 * bj + (lane & 15)];
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    double a[S / 4], b[S / 4];
+#pragma unroll
+    for (int k4 = 0; k4 < S / 4; ++k4) {
+      a[k4] = M[(ra + 16 * bi + (lane & 15)) * TS + ka + 4 * k4 + (lane >> 4)];
+      b[k4] = M[(kb + 4 * k4 + (lane >> 4)) * TS + cb + 16 * bj + (lane & 15)];
     }
+    d4 acc = (d4){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k4 = 0; k4 < S / 4; ++k4)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[k4], b[k4], acc, 0, 0, 0);
 #pragma unroll
     for (int r = 0; r < 4; ++r)
       M[(rc + 16 * bi + (lane >> 4) + 4 * r) * TS + cc + 16 * bj + (lane & 15)] = alpha * acc[r];
@@ -198,15 +365,13 @@ __global__ __launch_bounds__(512) void chol_inv_lds_kernel(const double* __restr
   using L = LdsInvShape<WMAX>;
   constexpr int TS = L::TS, NW = L::NW;
   __shared__ double Ts[WMAX * TS];
-  __shared__ double lbuf[2][WMAX];
-  __shared__ double dsh[WMAX];
+  __shared__ double rdiag[WMAX];
   __shared__ int flag[WMAX];
   __shared__ int klist[WMAX];
   __shared__ int kcnt;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 
-  chol_drop_core<WMAX, NW>(G, w, lbuf, dsh, flag, klist, &kcnt,
-                           [&](int c, int i, double v) { Ts[c * TS + i] = v; });
+  chol_blocked<WMAX, NW>(G, w, Ts, flag, rdiag, klist, &kcnt);
   // pad to the full WMAX x WMAX upper triangle with an identity block and
   // turn dropped columns into unit rows/columns
   for (int idx = threadIdx.x; idx < WMAX * WMAX; idx += blockDim.x) {
@@ -218,50 +383,35 @@ __global__ __launch_bounds__(512) void chol_inv_lds_kernel(const double* __restr
   }
   lds_barrier();
 
-  // 32 x 32 diagonal blocks: lanes 0..31 of waves 0..WMAX/32-1, one column each
+  // 32 x 32 diagonal blocks: lanes 0..31 of waves 0..WMAX/32-1, one column
+  // each, T X = I solved from the bottom row up in axpy form
   if (wave < WMAX / 32 && lane < 32) {
     const int o = 32 * wave, j = lane;
     double x[32];
+    static_for<32>([&](auto r) { x[r] = (r == j) ? 1.0 : 0.0; });
     static_for<32>([&](auto ii) {
-      constexpr int i = 31 - ii;
-      double acc = (i == j) ? 1.0 : 0.0;
-      static_for<31 - i>([&](auto ll) {
-        constexpr int l = i + 1 + ll;
-        acc -= Ts[(o + i) * TS + o + l] * x[l];
-      });
-      x[i] = acc / Ts[(o + i) * TS + o + i];
+      constexpr int i = 31 - decltype(ii)::value;
+      x[i] *= rdiag[o + i];
+      static_for<i>([&](auto r) { x[r] = fma(-Ts[(o + r) * TS + o + i], x[i], x[r]); });
     });
     static_for<32>([&](auto i) { Ts[(o + i) * TS + o + j] = x[i]; });
   }
   lds_barrier();
 
   // join pairs of inverted blocks: X_AB = -X_A (T_AB X_B)
-  for (int s = 32; s < WMAX; s *= 2) {
-    const int pairs = WMAX / (2 * s);
+  static_for<(WMAX == 128) ? 2 : 1>([&](auto lev) {
+    constexpr int s = 32 << decltype(lev)::value;
+    constexpr int pairs = WMAX / (2 * s);
     // M = T_AB X_B, stored at rows [ob, ob + s), columns [oa, oa + s)
     for (int p = 0; p < pairs; ++p) {
       const int oa = 2 * s * p, ob = oa + s;
-      lds_block_product<TS>(Ts, s, oa, ob, ob, ob, oa, 1.0, wave, NW);
+      lds_block_product<TS, s>(Ts, oa, ob, ob, ob, oa, 1.0, wave, NW);
     }
     lds_barrier();
-    // X_AB = -X_A M, written over T_AB
+    // X_AB = -X_A M, written over T_AB: A = X_A at (oa, oa), B = M at (ob, oa)
     for (int p = 0; p < pairs; ++p) {
       const int oa = 2 * s * p, ob = oa + s;
-      // A = X_A at (oa, oa); B = M at (ob, oa); out at (oa, ob)
-      const int nb = s / 16;
-      for (int job = wave; job < nb * nb; job += NW) {
-        typedef double d4 __attribute__((ext_vector_type(4)));
-        const int bi = job / nb, bj = job % nb;
-        d4 acc = (d4){0.0, 0.0, 0.0, 0.0};
-        for (int k0 = 0; k0 < s; k0 += 4) {
-          const double a = Ts[(oa + 16 * bi + (lane & 15)) * TS + oa + k0 + (lane >> 4)];
-          const double b = Ts[(ob + k0 + (lane >> 4)) * TS + oa + 16 * bj + (lane & 15)];
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
-        }
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          Ts[(oa + 16 * bi + (lane >> 4) + 4 * r) * TS + ob + 16 * bj + (lane & 15)] = -acc[r];
-      }
+      lds_block_product<TS, s>(Ts, oa, oa, oa, oa, ob, -1.0, wave, NW, ob);
     }
     lds_barrier();
     // clear M: the joined 2s x 2s block must be upper triangular for the next level
@@ -271,10 +421,11 @@ __global__ __launch_bounds__(512) void chol_inv_lds_kernel(const double* __restr
         Ts[(ob + idx / s) * TS + oa + idx % s] = 0.0;
     }
     lds_barrier();
-  }
+  });
 
   // expanded inverse: column a <- column kept[a] of T'^{-1}
   const int wk = kcnt;
+#pragma unroll 8
   for (int idx = threadIdx.x; idx < w * w; idx += blockDim.x) {
     const int r = idx % w, a = idx / w;
     Tinv[idx] = (a < wk) ? Ts[r * TS + klist[a]] : 0.0;
