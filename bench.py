@@ -83,6 +83,32 @@ def run_variant(qbmi, lib, torch, A, eps, wl, P, sample, steps, warmup, bufs, pr
     return res, ms, prof
 
 
+def committed_traffic(kernel):
+    """HBM bytes per launch of `kernel` from a committed rocprofv3 counter
+    summary under profiles/ (FETCH_SIZE + WRITE_SIZE, copy-kernel scaled).
+    None unless the summary's kernel source hash matches the current file:
+    counters taken on an older kernel say nothing about this one."""
+    import glob
+    import hashlib
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        with open(path) as f:
+            for line in f:
+                parts = line.split()
+                if len(parts) < 2 or parts[0] != "traffic":
+                    continue
+                kv = dict(p.split("=", 1) for p in parts[1:] if "=" in p)
+                if kv.get("kernel") != kernel:
+                    continue
+                src = os.path.join(ROOT, kv.get("source", ""))
+                if not os.path.isfile(src):
+                    continue
+                with open(src, "rb") as g:
+                    if hashlib.sha256(g.read()).hexdigest() != kv.get("sha256"):
+                        continue
+                return float(kv["bytes_per_launch"]), os.path.relpath(path, ROOT)
+    return None, None
+
+
 def residual_rel(torch, A, res):
     # independent check of ||A - Q B||_F / ||A||_F (verification only)
     R = A - res.Q @ res.B
@@ -169,9 +195,12 @@ def main():
     # dominant kernel by total time inside the timed steps
     dom_name, dom = max(prof.items(), key=lambda kv: kv[1]["ms"])
     dom_tflops = dom["flops"] / (dom["ms"] * 1e-3) / 1e12 if dom["ms"] > 0 else 0.0
+    traffic, traffic_src = committed_traffic(dom_name)
     roofline = {"bound": "mfma", "kernel": dom_name, "achieved": dom_tflops,
                 "peak": PEAK["f64_mfma"], "unit": "TFLOP/s", "frac": dom_tflops / PEAK["f64_mfma"],
-                "traffic": None, "avg_launch_ms": dom["ms"] / dom["launches"],
+                "traffic": traffic, "traffic_source": traffic_src,
+                "algorithmic_bytes": dom["bytes"] / dom["launches"],
+                "avg_launch_ms": dom["ms"] / dom["launches"],
                 "launches": dom["launches"],
                 "note": "achieved = algorithmic flops of this kernel class (2 x rows x cols x depth "
                         "per product) over its summed launch durations (HIP events on the launch "

@@ -61,6 +61,16 @@ extern "C" {
 #define QB_SAMPLE_F32     (1u << 4)
 #define QB_SAMPLE_BF16X3  (2u << 4)
 #define QB_SAMPLE_MASK    (3u << 4)
+/* precision of the projection B_i = Q_i^T A^(i-1) (Fig. 4 (4), Fig. 6 (9)).
+ * The downdate, the residual norm and the stopping rule stay float64, so
+ * ||A - QB||_F <= eps still holds when the call returns QB_OK; but a B below
+ * float64 leaves its own rounding error in the residual, so the attainable
+ * error floors near 1e-7 (f32) and 1e-5 (bf16x3) of ||A||_F.  Sweep
+ * variants: they report that floor; they do not reach tight tolerances. */
+#define QB_BGEMM_F64      (0u << 6)
+#define QB_BGEMM_F32      (1u << 6)
+#define QB_BGEMM_BF16X3   (2u << 6)
+#define QB_BGEMM_MASK     (3u << 6)
 
 /* Per-call report.  The trace arrays are optional HOST arrays owned by the
  * caller (set the pointers to NULL or trace_cap to 0 to skip).  Entry i

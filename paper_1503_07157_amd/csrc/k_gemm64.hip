@@ -107,6 +107,81 @@ struct Tile {
   }
 };
 
+// Interior tiles: 16-byte buffer loads.  The workgroup builds one buffer
+// resource per operand at its tile origin; each lane keeps loop-invariant
+// 32-bit byte offsets and the advance along k goes into the scalar offset,
+// so a load costs no address arithmetic and no bounds test.  Used only when
+// the whole tile, every depth slice, 16-byte alignment (base and even ld)
+// and a byte extent below 2^31 are guaranteed (checked per workgroup).
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+constexpr int kBufDword3 = 0x00020000;  // raw (untyped) buffer, gfx9 family
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const double* base, int64_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(base), 0,
+                                           static_cast<int>(bytes), kBufDword3);
+}
+
+__device__ __forceinline__ double2 buf_load2(__amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                             uint32_t soff) {
+  const i32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, static_cast<int>(voff),
+                                                        static_cast<int>(soff), 0);
+  return __builtin_bit_cast(double2, v);
+}
+
+template <class S, bool A_KCONTIG>
+struct FastTile {
+  static constexpr int QA = S::PA / 2, QB = S::PB / 2;  // 16-byte loads per operand
+  double2 ra[QA], rb[QB];
+  uint32_t oa[QA], ob[QB];    // global byte offsets from the tile origin
+  uint32_t la[QA], lb[QB];    // LDS element offsets
+
+  __device__ __forceinline__ void setup(int64_t lda, int64_t ldb) {
+    const int t = threadIdx.x;
+    const uint32_t ua = static_cast<uint32_t>(lda), ub = static_cast<uint32_t>(ldb);
+#pragma unroll
+    for (int q = 0; q < QA; ++q) {
+      const int e2 = t + NT * q;
+      if (A_KCONTIG) {  // pairs along k: element (i, 2kp .. 2kp+1)
+        const int kp = e2 % (BK / 2), i = e2 / (BK / 2);
+        oa[q] = 8u * (2u * kp + static_cast<uint32_t>(i) * ua);
+        la[q] = i * S::SA_K + 2 * kp;
+      } else {          // pairs along m: element (2rp .. 2rp+1, col)
+        const int rp = e2 % (S::BM / 2), col = e2 / (S::BM / 2);
+        oa[q] = 8u * (2u * rp + static_cast<uint32_t>(col) * ua);
+        la[q] = col * S::SA_M + 2 * rp;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < QB; ++q) {
+      const int e2 = t + NT * q;
+      const int kp = e2 % (BK / 2), nn = e2 / (BK / 2);
+      ob[q] = 8u * (2u * kp + static_cast<uint32_t>(nn) * ub);
+      lb[q] = nn * S::SB_K + 2 * kp;
+    }
+  }
+
+  __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t rA, uint32_t sa,
+                                       __amdgpu_buffer_rsrc_t rB, uint32_t sb) {
+#pragma unroll
+    for (int q = 0; q < QA; ++q) ra[q] = buf_load2(rA, oa[q], sa);
+#pragma unroll
+    for (int q = 0; q < QB; ++q) rb[q] = buf_load2(rB, ob[q], sb);
+  }
+
+  __device__ __forceinline__ void store(double* As, double* Bs) const {
+#pragma unroll
+    for (int q = 0; q < QA; ++q) {
+      As[la[q]] = ra[q].x;
+      As[la[q] + 1] = ra[q].y;
+    }
+#pragma unroll
+    for (int q = 0; q < QB; ++q) {
+      Bs[lb[q]] = rb[q].x;
+      Bs[lb[q] + 1] = rb[q].y;
+    }
+  }
+};
+
 // MFMA row permutation: the A operand of lane l carries tile row
 // perm(l % 16), perm(rho) = 4 (rho % 4) + rho / 4.  With the result layout
 // D[l/16 + 4r][l%16] this puts rows 4 (l / 16) + r, r = 0..3, in the four
@@ -114,24 +189,81 @@ struct Tile {
 // column, so epilogues move them with 16-byte accesses.
 __device__ __forceinline__ int perm16(int rho) { return 4 * (rho & 3) + (rho >> 2); }
 
-// Accumulate the workgroup tile over k in [kbeg, kend).  As/Bs hold two
-// LDS stages each.
+// MFMA work of one depth slice held in LDS
 template <class S, bool A_KCONTIG>
-__device__ __forceinline__ void mma_loop(const double* __restrict__ A, int64_t lda,
-                                         const double* __restrict__ Bm, int64_t ldb, int64_t m0,
-                                         int64_t n0, int64_t M, int64_t N, int64_t kbeg,
-                                         int64_t kend, double* As, double* Bs,
-                                         d4 (&acc)[S::IB][S::JB]) {
+__device__ __forceinline__ void mma_slice(const double* Ac, const double* Bc,
+                                          d4 (&acc)[S::IB][S::JB]) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int wm = (wave & 1) * S::WM, wn = (wave >> 1) * S::WN;
   const int lr = lane & 15, lk = lane >> 4;
   const int pr = perm16(lr);
 #pragma unroll
+  for (int k4 = 0; k4 < BK / 4; ++k4) {
+    double a[S::IB], b[S::JB];
+    const int kq = 4 * k4 + lk;
+#pragma unroll
+    for (int i = 0; i < S::IB; ++i) {
+      const int mrow = wm + 16 * i + pr;
+      a[i] = A_KCONTIG ? Ac[mrow * S::SA_K + kq] : Ac[kq * S::SA_M + mrow];
+    }
+#pragma unroll
+    for (int j = 0; j < S::JB; ++j) b[j] = Bc[(wn + 16 * j + lr) * S::SB_K + kq];
+#pragma unroll
+    for (int i = 0; i < S::IB; ++i)
+#pragma unroll
+      for (int j = 0; j < S::JB; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+  }
+}
+
+// Accumulate the workgroup tile over k in [kbeg, kend).  As/Bs hold two
+// LDS stages each: slice s + 1 is written to the free stage and slice s + 2
+// is in flight in registers while slice s is multiplied.
+template <class S, bool A_KCONTIG>
+__device__ __forceinline__ void mma_loop(const double* __restrict__ A, int64_t lda,
+                                         const double* __restrict__ Bm, int64_t ldb, int64_t m0,
+                                         int64_t n0, int64_t M, int64_t N, int64_t kbeg,
+                                         int64_t kend, bool vec, double* As, double* Bs,
+                                         d4 (&acc)[S::IB][S::JB]) {
+#pragma unroll
   for (int i = 0; i < S::IB; ++i)
 #pragma unroll
     for (int j = 0; j < S::JB; ++j) acc[i][j] = (d4){0.0, 0.0, 0.0, 0.0};
   if (kbeg >= kend) return;
+
+  const int64_t klen = kend - kbeg;
+  const int64_t ext_a = A_KCONTIG ? klen + (S::BM - 1) * lda : S::BM + (klen - 1) * lda;
+  const int64_t ext_b = klen + (S::BN - 1) * ldb;
+  const bool fast = vec && m0 + S::BM <= M && n0 + S::BN <= N && klen % BK == 0 &&
+                    8 * ext_a < (int64_t(1) << 31) && 8 * ext_b < (int64_t(1) << 31);
+  if (fast) {
+    const double* a0 = A_KCONTIG ? A + kbeg + m0 * lda : A + m0 + kbeg * lda;
+    const double* b0 = Bm + kbeg + n0 * ldb;
+    const __amdgpu_buffer_rsrc_t rA = make_rsrc(a0, 8 * ext_a);
+    const __amdgpu_buffer_rsrc_t rB = make_rsrc(b0, 8 * ext_b);
+    // byte advance of one depth slice
+    const uint32_t da = static_cast<uint32_t>(8 * (A_KCONTIG ? BK : BK * lda));
+    const uint32_t db = static_cast<uint32_t>(8 * BK);
+    const int nslice = static_cast<int>(klen / BK);
+    FastTile<S, A_KCONTIG> tl;
+    tl.setup(lda, ldb);
+    tl.load(rA, 0u, rB, 0u);
+    tl.store(As, Bs);
+    if (nslice > 1) tl.load(rA, da, rB, db);
+    lds_barrier();
+    int stage = 0;
+    for (int sl = 0; sl < nslice; ++sl) {
+      if (sl + 1 < nslice) {
+        tl.store(As + (stage ^ 1) * S::A_LDS, Bs + (stage ^ 1) * S::B_LDS);
+        if (sl + 2 < nslice) tl.load(rA, (sl + 2) * da, rB, (sl + 2) * db);
+      }
+      mma_slice<S, A_KCONTIG>(As + stage * S::A_LDS, Bs + stage * S::B_LDS, acc);
+      lds_barrier();
+      stage ^= 1;
+    }
+    return;
+  }
 
   Tile<S, A_KCONTIG> tl;
   tl.load(A, lda, Bm, ldb, m0, n0, M, N, kbeg, kend);
@@ -140,31 +272,11 @@ __device__ __forceinline__ void mma_loop(const double* __restrict__ A, int64_t l
   lds_barrier();
   int stage = 0;
   for (int64_t kc = kbeg; kc < kend; kc += BK) {
-    // stage the next slice (already in registers) into the other buffer and
-    // start fetching the one after it
     if (kc + BK < kend) {
       tl.store(As + (stage ^ 1) * S::A_LDS, Bs + (stage ^ 1) * S::B_LDS);
       if (kc + 2 * BK < kend) tl.load(A, lda, Bm, ldb, m0, n0, M, N, kc + 2 * BK, kend);
     }
-    const double* Ac = As + stage * S::A_LDS;
-    const double* Bc = Bs + stage * S::B_LDS;
-#pragma unroll
-    for (int k4 = 0; k4 < BK / 4; ++k4) {
-      double a[S::IB], b[S::JB];
-      const int kq = 4 * k4 + lk;
-#pragma unroll
-      for (int i = 0; i < S::IB; ++i) {
-        const int mrow = wm + 16 * i + pr;
-        a[i] = A_KCONTIG ? Ac[mrow * S::SA_K + kq] : Ac[kq * S::SA_M + mrow];
-      }
-#pragma unroll
-      for (int j = 0; j < S::JB; ++j) b[j] = Bc[(wn + 16 * j + lr) * S::SB_K + kq];
-#pragma unroll
-      for (int i = 0; i < S::IB; ++i)
-#pragma unroll
-        for (int j = 0; j < S::JB; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
-    }
+    mma_slice<S, A_KCONTIG>(As + stage * S::A_LDS, Bs + stage * S::B_LDS, acc);
     lds_barrier();
     stage ^= 1;
   }
@@ -240,7 +352,7 @@ __global__ __launch_bounds__(NT, 2) void gemm_nn_kernel(const double* __restrict
                                                         int64_t M, int64_t N, int64_t K,
                                                         int64_t kchunk, double alpha, double beta,
                                                         double* __restrict__ part, int64_t ldp,
-                                                        int vec_y) {
+                                                        int vec_y, int vec_ab) {
   __shared__ double As[2 * S::A_LDS];
   __shared__ double Bs[2 * S::B_LDS];
   const int64_t m0 = static_cast<int64_t>(blockIdx.x) * S::BM;
@@ -248,7 +360,7 @@ __global__ __launch_bounds__(NT, 2) void gemm_nn_kernel(const double* __restrict
   const int64_t kbeg = static_cast<int64_t>(blockIdx.z) * kchunk;
   const int64_t kend = (kbeg + kchunk < K) ? kbeg + kchunk : K;
   d4 acc[S::IB][S::JB];
-  mma_loop<S, false>(X, ldx, W, ldw, m0, n0, M, N, kbeg, kend, As, Bs, acc);
+  mma_loop<S, false>(X, ldx, W, ldw, m0, n0, M, N, kbeg, kend, vec_ab != 0, As, Bs, acc);
   if (part != nullptr) {
     double* P = part + static_cast<int64_t>(blockIdx.z) * ldp * N;
 #pragma unroll
@@ -282,7 +394,8 @@ __global__ __launch_bounds__(NT, 2) void gemm_tn_kernel(const double* __restrict
                                                         int64_t P, int64_t N, int64_t K,
                                                         int64_t kchunk, int transpose_out,
                                                         double* __restrict__ part, int64_t ldp,
-                                                        double* __restrict__ sq_part, int vec_c) {
+                                                        double* __restrict__ sq_part, int vec_c,
+                                                        int vec_ab) {
   __shared__ double As[2 * S::A_LDS];
   __shared__ double Bs[2 * S::B_LDS];
   __shared__ double red[NT / 64];
@@ -291,7 +404,7 @@ __global__ __launch_bounds__(NT, 2) void gemm_tn_kernel(const double* __restrict
   const int64_t kbeg = static_cast<int64_t>(blockIdx.z) * kchunk;
   const int64_t kend = (kbeg + kchunk < K) ? kbeg + kchunk : K;
   d4 acc[S::IB][S::JB];
-  mma_loop<S, true>(Qm, ldq, X, ldx, m0, n0, P, N, kbeg, kend, As, Bs, acc);
+  mma_loop<S, true>(Qm, ldq, X, ldx, m0, n0, P, N, kbeg, kend, vec_ab != 0, As, Bs, acc);
   if (part != nullptr) {
     double* Pp = part + static_cast<int64_t>(blockIdx.z) * ldp * N;
 #pragma unroll
@@ -363,14 +476,14 @@ __global__ __launch_bounds__(NT, 2) void downdate_kernel(double* __restrict__ R,
                                                          int64_t ldb, int64_t M, int64_t N,
                                                          int64_t K,
                                                          double* __restrict__ sq_part,
-                                                         int vec_r) {
+                                                         int vec_r, int vec_ab) {
   __shared__ double As[2 * S::A_LDS];
   __shared__ double Bs[2 * S::B_LDS];
   __shared__ double red[NT / 64];
   const int64_t m0 = static_cast<int64_t>(blockIdx.x) * S::BM;
   const int64_t n0 = static_cast<int64_t>(blockIdx.y) * S::BN;
   d4 acc[S::IB][S::JB];
-  mma_loop<S, false>(Qm, ldq, B, ldb, m0, n0, M, N, 0, K, As, Bs, acc);
+  mma_loop<S, false>(Qm, ldq, B, ldb, m0, n0, M, N, 0, K, vec_ab != 0, As, Bs, acc);
   double sq = 0.0;
 #pragma unroll
   for (int i = 0; i < S::IB; ++i) {
@@ -413,7 +526,7 @@ void launch_nn(const double* X, int64_t ldx, const double* W, int64_t ldw, doubl
   const dim3 grid(static_cast<unsigned>(cdiv(M, S::BM)), static_cast<unsigned>(cdiv(N, S::BN)),
                   static_cast<unsigned>(nz));
   hipLaunchKernelGGL(gemm_nn_kernel<S>, grid, dim3(NT), 0, s, X, ldx, W, ldw, Y, ldy, M, N, K,
-                     kc, alpha, beta, part, ldp, vec_ok(Y, ldy));
+                     kc, alpha, beta, part, ldp, vec_ok(Y, ldy), vec_ok(X, ldx) & vec_ok(W, ldw));
 }
 
 template <class S>
@@ -423,7 +536,8 @@ dim3 launch_tn(const double* Qm, int64_t ldq, const double* X, int64_t ldx, doub
   const dim3 grid(static_cast<unsigned>(cdiv(N, S::BN)), static_cast<unsigned>(cdiv(P, S::BM)),
                   static_cast<unsigned>(nz));
   hipLaunchKernelGGL(gemm_tn_kernel<S>, grid, dim3(NT), 0, s, Qm, ldq, X, ldx, C, ldc, P, N, K,
-                     kc, tr ? 1 : 0, part, ldp, sq_part, vec_ok(C, ldc));
+                     kc, tr ? 1 : 0, part, ldp, sq_part, vec_ok(C, ldc),
+                     vec_ok(Qm, ldq) & vec_ok(X, ldx));
   return grid;
 }
 
@@ -469,7 +583,7 @@ int gemm_nn(const double* X, int64_t ldx, const double* W, int64_t ldw, double* 
   // T^{-1} application, short projections) take 64 x 64 tiles
   const bool small = nz == 1 && cdiv(M, Big::BM) * cdiv(N, Big::BN) < kNumCU;
   {
-    ProfScope ps(kKGemmNN, 2.0 * M * N * K,
+    ProfScope ps(small ? kKGemmNNSmall : kKGemmNN, 2.0 * M * N * K,
                  8.0 * (M * K + K * N + M * N * (beta != 0.0 ? 2 : 1)), s);
     double* pp = nz > 1 ? part : nullptr;
     if (small)
@@ -506,7 +620,7 @@ int gemm_tn(const double* Qm, int64_t ldq, const double* X, int64_t ldx, double*
   const bool small = P * N <= int64_t(256) * 256 && (sq_part == nullptr || nz > 1);
   dim3 grid;
   {
-    ProfScope ps(kKGemmTN, 2.0 * P * N * K, 8.0 * (K * P + K * N + P * N), s);
+    ProfScope ps(small ? kKGemmTNSmall : kKGemmTN, 2.0 * P * N * K, 8.0 * (K * P + K * N + P * N), s);
     double* pp = nz > 1 ? part : nullptr;
     double* sqp = nz > 1 ? static_cast<double*>(nullptr) : sq_part;
     grid = small ? launch_tn<Small>(Qm, ldq, X, ldx, C, ldc, P, N, K, kc, nz, transpose_out, pp,
@@ -541,7 +655,7 @@ int downdate(double* R, int64_t ldr, const double* Qm, int64_t ldq, const double
   {
     ProfScope ps(kKDowndate, 2.0 * M * N * K, 8.0 * (2 * M * N + M * K + K * N), s);
     hipLaunchKernelGGL(downdate_kernel<Big>, grid, dim3(NT), 0, s, R, ldr, Qm, ldq, B, ldb, M, N,
-                       K, sq_part, vec_ok(R, ldr));
+                       K, sq_part, vec_ok(R, ldr), vec_ok(Qm, ldq) & vec_ok(B, ldb));
   }
   QB_HIP_TRY(hipGetLastError());
   if (sq_count) *sq_count = static_cast<int>(grid.x * grid.y);

@@ -29,6 +29,8 @@ int sum_partials_ex(const double* part, int count, const int* flags, double* out
 namespace {
 
 constexpr double kDeltaRel = 1e-13;               // hybrid band, relative to ||A||_F^2
+constexpr double kDeltaRelF32 = 1e-6;             // same, B_i = Q_i^T A in f32
+constexpr double kDeltaRelBf16x3 = 1e-4;          // same, B_i in bf16x3
 constexpr double kFloorRel = 0x1p-46;             // rounding floor of the residual, rel. ||A||_F
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -182,6 +184,9 @@ int qb_factor(const double* A, int64_t m, int64_t n, int64_t lda, double eps, in
     return QB_EINVAL;
   const uint32_t prec = flags & QB_SAMPLE_MASK;
   if (prec == QB_SAMPLE_MASK) return QB_EINVAL;
+  // the B precision in the sampling encoding (QB_BGEMM_x >> 2 == QB_SAMPLE_x)
+  const uint32_t bprec = (flags & QB_BGEMM_MASK) >> 2;
+  if (bprec == QB_SAMPLE_MASK) return QB_EINVAL;
   const int64_t r = std::min(m, n);
   if (kmax > r) return QB_EINVAL;
   const int64_t kcap = (kmax < 0) ? r : kmax;
@@ -210,7 +215,11 @@ int qb_factor(const double* A, int64_t m, int64_t n, int64_t lda, double eps, in
   const DD sA{hsA[0], hsA[1]};
   const double sAv = dd_val(sA);
   const double eps2 = eps * eps;
-  const double delta = kDeltaRel * sAv;
+  // hybrid band half-width: |E_i - D_i| grows to about 2 u ||A||^2 with the
+  // unit roundoff u of the B product
+  const double delta = (bprec == QB_SAMPLE_F64   ? kDeltaRel
+                        : bprec == QB_SAMPLE_F32 ? kDeltaRelF32
+                                                 : kDeltaRelBf16x3) * sAv;
   const double floor2 = (kFloorRel * std::sqrt(sAv)) * (kFloorRel * std::sqrt(sAv));
 
   int64_t k = 0;
@@ -277,10 +286,15 @@ int qb_factor(const double* A, int64_t m, int64_t n, int64_t lda, double eps, in
     }
     // (4) B_i = Q_i^T A with ||B_i||^2;  (5) downdate with ||A^(i)||^2
     int nb = 0, nd = 0;
-    {
+    if (bprec == QB_SAMPLE_F64) {
       const int sp = choose_split(w, n, m);
       if (gemm_tn(Qout, ldq, R, ldr, B + k, ldb, w, n, m, false, sp, wk.part, wk.sq1, &nb, st))
         return QB_EHIP;
+    } else {
+      if (project_t(bprec, Qout, ldq, R, ldr, B + k, ldb, w, n, m, false, wk.part, nullptr,
+                    nullptr, st))
+        return QB_EHIP;
+      if (sumsq_partials(B + k, ldb, w, n, wk.sq1, &nb, wk.flags, st)) return QB_EHIP;
     }
     if (sum_partials(wk.sq1, nb, wk.scal + 2, st)) return QB_EHIP;
     if (downdate(R, ldr, Qout, ldq, B + k, ldb, m, n, w, wk.sq2, &nd, st)) return QB_EHIP;

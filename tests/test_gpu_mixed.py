@@ -96,3 +96,47 @@ def test_mixed_exact_rank(cuda, prec):
     Q, B = g.Q.cpu().numpy(), g.B.cpu().numpy()
     assert g.k >= 37
     assert np.linalg.norm(A - Q @ B) <= 1e-10 * nA
+
+
+# ---- B_i = Q_i^T A in reduced precision (sweep variants) -------------------
+# The downdate, residual norm and stopping rule stay float64, so the returned
+# factorisation satisfies ||A - QB|| <= eps whenever the call reports QB_OK.
+# The leftover Q_i (B~_i - Q_i^T A) lies in the span of Qbar and is never
+# sampled again, so the attainable error floors near the product's rounding:
+# below that the run goes to full rank and reports the floor.
+FLOOR = {"f32": 1e-5, "bf16x3": 1e-2}
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16x3"])
+def test_bgemm_variant_matches_oracle_above_floor(cuda, prec):
+    w = synth.workload("exp40_2000x1000")
+    A = synth.workload_matrix(w.name)
+    nA = math.sqrt(sumsq(A))
+    eps = 1e-2 * nA
+    g = qbmi.qb_factor(dev(A), eps, w.b, 0, w.seed_omega, bgemm=prec)
+    o = randqb_pb(A, eps, w.b, 0, w.seed_omega)
+    print(f"[case] bgemm={prec} k_gpu={g.k} k_oracle={o.k}", flush=True)
+    assert g.k == o.k and g.widths == o.widths and g.stop_reason in ("TOL_TRACKED", "TOL_DIRECT")
+    Q, B = g.Q.cpu().numpy(), g.B.cpu().numpy()
+    assert np.linalg.norm(Q.T @ Q - np.eye(g.k)) < 1e-12
+    assert np.linalg.norm(A - Q @ B) <= eps * (1 + 1e-9)
+    # B differs from Q^T A by the product's rounding only (elementwise bound)
+    Qd = g.Q.cpu().numpy()
+    bound = 4 * UNIT[prec] * w.m * (np.abs(Qd).T @ np.abs(A))
+    assert np.all(np.abs(B - Qd.T @ A) <= bound)
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16x3"])
+def test_bgemm_variant_reports_its_floor(cuda, prec):
+    w = synth.workload("exp40_2000x1000")
+    A = synth.workload_matrix(w.name)
+    nA = math.sqrt(sumsq(A))
+    g = qbmi.qb_factor(dev(A), 1e-12 * nA, w.b, 0, w.seed_omega, bgemm=prec)
+    Q, B = g.Q.cpu().numpy(), g.B.cpu().numpy()
+    err = np.linalg.norm(A - Q @ B) / nA
+    print(f"[case] bgemm={prec} k={g.k} stop={g.stop_reason} floor={err:.3e}", flush=True)
+    # the tolerance is out of reach: full rank, no false success
+    assert g.k == min(A.shape) and g.stop_reason == "RANK_CAP"
+    assert 1e-12 < err <= FLOOR[prec]
+    # the reported direct residual is the true one
+    assert abs(math.sqrt(g.resid2) / nA - err) <= 1e-3 * err
