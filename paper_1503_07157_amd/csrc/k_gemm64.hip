@@ -466,6 +466,63 @@ __global__ __launch_bounds__(256) void reduce_kernel(const double* __restrict__ 
   }
 }
 
+// The same sum for small outputs with many partials (the w x w Gram
+// matrices): a workgroup covers 256 / G outputs with G threads each; thread
+// g adds partials g, g + G, g + 2G, ... in increasing order and the G
+// partial sums are added in the order g = 0 .. G-1.  A fixed order, so the
+// result is the same on every run.
+template <int G>
+__global__ __launch_bounds__(256) void reduce_wide_kernel(const double* __restrict__ part,
+                                                          int split, int64_t ldp,
+                                                          double* __restrict__ out, int64_t ldo,
+                                                          int64_t M, int64_t N, double alpha,
+                                                          double beta, int transpose_out) {
+  constexpr int OPB = 256 / G;
+  __shared__ double buf[G][OPB];
+  const int o = threadIdx.x % OPB, g = threadIdx.x / OPB;
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * OPB + o;
+  const int64_t total = M * N;
+  const int64_t i = idx % M, j = idx / M;
+  double s = 0.0;
+  if (idx < total) {
+    const int64_t pstride = ldp * N;
+    const double* pp = part + i + j * ldp;
+#pragma unroll 4
+    for (int z = g; z < split; z += G) s += pp[z * pstride];
+  }
+  buf[g][o] = s;
+  __syncthreads();
+  if (g == 0 && idx < total) {
+    double v = buf[0][o];
+#pragma unroll
+    for (int q = 1; q < G; ++q) v += buf[q][o];
+    v *= alpha;
+    const int64_t oi = transpose_out ? (j + i * ldo) : (i + j * ldo);
+    if (beta != 0.0) v += beta * out[oi];
+    out[oi] = v;
+  }
+}
+
+constexpr int kWideG = 8;  // threads per output in reduce_wide_kernel
+
+// launch the split-K sum; the wide form serves small outputs with many
+// partials when no per-block sums of squares are asked for
+void launch_reduce(const double* part, int nz, int64_t ldp, double* out, int64_t ldo, int64_t M,
+                   int64_t N, double alpha, double beta, bool tr, double* sq_part, unsigned* nb,
+                   hipStream_t s) {
+  const int64_t total = M * N;
+  if (sq_part == nullptr && nz >= 2 * kWideG && total <= (int64_t(1) << 18)) {
+    constexpr int OPB = 256 / kWideG;
+    *nb = static_cast<unsigned>(cdiv(total, OPB));
+    hipLaunchKernelGGL(reduce_wide_kernel<kWideG>, dim3(*nb), dim3(256), 0, s, part, nz, ldp, out,
+                       ldo, M, N, alpha, beta, tr ? 1 : 0);
+    return;
+  }
+  *nb = static_cast<unsigned>(cdiv(total, 256));
+  hipLaunchKernelGGL(reduce_kernel, dim3(*nb), dim3(256), 0, s, part, nz, ldp, out, ldo, M, N,
+                     alpha, beta, tr ? 1 : 0, sq_part);
+}
+
 // R -= Q B; per-workgroup sum of squares of the updated tile.
 // grid: (M tiles, N tiles)
 template <class S>
@@ -595,9 +652,8 @@ int gemm_nn(const double* X, int64_t ldx, const double* W, int64_t ldw, double* 
   if (nz > 1) {
     const int64_t total = M * N;
     ProfScope ps(kKReduce, double(nz) * total, 8.0 * (nz + (beta != 0.0 ? 2 : 1)) * total, s);
-    hipLaunchKernelGGL(reduce_kernel, dim3(static_cast<unsigned>(cdiv(total, 256))), dim3(256), 0,
-                       s, part, nz, ldp, Y, ldy, M, N, alpha, beta, 0,
-                       static_cast<double*>(nullptr));
+    unsigned nb = 0;
+    launch_reduce(part, nz, ldp, Y, ldy, M, N, alpha, beta, false, nullptr, &nb, s);
     QB_HIP_TRY(hipGetLastError());
   }
   return kOk;
@@ -631,10 +687,9 @@ int gemm_tn(const double* Qm, int64_t ldq, const double* X, int64_t ldx, double*
   QB_HIP_TRY(hipGetLastError());
   if (nz > 1) {
     const int64_t total = P * N;
-    const unsigned nb = static_cast<unsigned>(cdiv(total, 256));
+    unsigned nb = 0;
     ProfScope ps(kKReduce, double(nz) * total, 8.0 * (nz + 1) * total, s);
-    hipLaunchKernelGGL(reduce_kernel, dim3(nb), dim3(256), 0, s, part, nz, ldp, C, ldc, P, N, 1.0,
-                       0.0, transpose_out ? 1 : 0, sq_part);
+    launch_reduce(part, nz, ldp, C, ldc, P, N, 1.0, 0.0, transpose_out, sq_part, &nb, s);
     QB_HIP_TRY(hipGetLastError());
     if (sq_count) *sq_count = sq_part ? static_cast<int>(nb) : 0;
   } else {

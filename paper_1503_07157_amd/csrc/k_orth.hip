@@ -17,9 +17,9 @@
 // one short dependent chain.  Wider panels (up to 256) keep the lower
 // triangle in registers with a rank-one update per column.
 //
-// Inverse: T^{-1} of the kept part, blocked in LDS (32 x 32 diagonal blocks
-// by substitution, joined with MFMA products) for panels up to 128; one
-// wave per output column by back substitution for wider panels.
+// Inverse: T^{-1} of the kept part, blocked in LDS (16 x 16 diagonal blocks
+// by substitution, joined pairwise with MFMA products) for panels up to 128;
+// one wave per output column by back substitution for wider panels.
 #include <utility>
 
 #include "qb_internal.hpp"
@@ -183,11 +183,17 @@ constexpr int kPanel = 16;  // Cholesky panel width
 // wave: lane l holds rows p + l + 64 a.  Column c is kept when its pivot
 // exceeds thresh; a dropped column becomes zero.  Sets flag[c] and
 // rdiag[c] = 1 / L[c][c] (1 for a dropped or padding column).
+//
+// The column loop needs no per-lane tests: scaling a whole column by
+// 1/sqrt(d) leaves sqrt(d) on the diagonal lane, and lanes above the
+// diagonal only carry values nobody reads (cleared when written back).
 template <int WMAX>
 __device__ __forceinline__ void chol_panel(double* Ts, int p, int w, double thresh, bool gpos,
                                            int* flag, double* rdiag) {
   constexpr int TS = WMAX + 1, RA = WMAX / 64;
-  const int lane = threadIdx.x & 63;
+  // opaque per call, so per-lane values are not hoisted out of the panel loop
+  int lane = threadIdx.x & 63;
+  asm volatile("" : "+v"(lane));
   double x[RA][kPanel];
   static_for<kPanel>([&](auto jj) {
     static_for<RA>([&](auto a) {
@@ -201,16 +207,17 @@ __device__ __forceinline__ void chol_panel(double* Ts, int p, int w, double thre
     const double d = readlane_d(x[0][J], J);  // row c lives in lane J, slot 0
     const bool keep = (c < w) && gpos && (d > thresh);
     const double r = keep ? rsqrt_refined(d) : 0.0;
-    static_for<RA>([&](auto a) {
-      const int i = p + lane + 64 * a;
-      const double v = x[a][J] * r;
-      x[a][J] = (i > c) ? v : ((i == c) ? d * r : 0.0);
-    });
-    // update the panel's later columns with this one
+    static_for<RA>([&](auto a) { x[a][J] *= r; });
+    // rank-one update of the panel's later columns
     static_for<kPanel - 1 - J>([&](auto t) {
       constexpr int K = J + 1 + decltype(t)::value;
       const double lk = readlane_d(x[0][J], K);  // L[p + K][c]
-      static_for<RA>([&](auto a) { x[a][K] = fma(-x[a][J], lk, x[a][K]); });
+      static_for<RA>([&](auto a) {
+        x[a][K] = fma(-x[a][J], lk, x[a][K]);
+        // keep the update here; left to itself the compiler sinks it to the
+        // use of column K and holds every broadcast value in scalar registers
+        asm volatile("" : "+v"(x[a][K]));
+      });
     });
     if (lane == 0) {
       flag[c] = keep ? 1 : 0;
@@ -220,7 +227,7 @@ __device__ __forceinline__ void chol_panel(double* Ts, int p, int w, double thre
   static_for<kPanel>([&](auto jj) {
     static_for<RA>([&](auto a) {
       const int i = p + lane + 64 * a;
-      if (i < WMAX) Ts[(p + jj) * TS + i] = x[a][jj];
+      if (i < WMAX) Ts[(p + jj) * TS + i] = (a > 0 || lane >= jj) ? x[a][jj] : 0.0;
     });
   });
 }
@@ -262,17 +269,29 @@ __device__ __forceinline__ void chol_trailing(double* Ts, int p, int w) {
 // Blocked Cholesky with dropping of the w x w matrix G (column-major, ld w).
 // Result in LDS: Ts[c * TS + i] = T[c][i] = L[i][c] (T = L^T upper
 // triangular, zero for i < c and in the padding up to WMAX); flag, rdiag,
-// the kept list and count.
+// the kept list and count, and the list of dropped or padding columns.
 template <int WMAX, int NW>
 __device__ __forceinline__ void chol_blocked(const double* __restrict__ G, int w, double* Ts,
-                                             int* flag, double* rdiag, int* klist, int* kcnt) {
+                                             int* flag, double* rdiag, int* klist, int* kcnt,
+                                             int* ulist, int* ucnt) {
   constexpr int TS = WMAX + 1;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  // lower triangle of G into Ts, everything else zero
-#pragma unroll 8
-  for (int idx = threadIdx.x; idx < WMAX * WMAX; idx += 64 * NW) {
-    const int i = idx % WMAX, j = idx / WMAX;
-    Ts[j * TS + i] = (i < w && j < w && i >= j) ? G[i + static_cast<int64_t>(j) * w] : 0.0;
+  // lower triangle of G into Ts, everything else zero; every load of a
+  // thread is issued before the first store
+  {
+    constexpr int PER = WMAX * WMAX / (64 * NW);
+    double v[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int idx = threadIdx.x + 64 * NW * q;
+      const int i = idx % WMAX, j = idx / WMAX;
+      v[q] = (i < w && j < w && i >= j) ? G[i + static_cast<int64_t>(j) * w] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int idx = threadIdx.x + 64 * NW * q;
+      Ts[(idx / WMAX) * TS + idx % WMAX] = v[q];
+    }
   }
   lds_barrier();
   double gmax = 0.0;
@@ -293,18 +312,25 @@ __device__ __forceinline__ void chol_blocked(const double* __restrict__ G, int w
     flag[c] = 0;
     rdiag[c] = 1.0;
   }
-  // kept list in column order: ballot + prefix count by wave 0
+  // kept list in column order (ballot + prefix count by wave 0), and the
+  // list of the other columns up to WMAX (dropped or padding) after it
   if (wave == 0) {
-    int base = 0;
-    for (int c0 = 0; c0 < w; c0 += 64) {
+    int base = 0, ubase = 0;
+    for (int c0 = 0; c0 < WMAX; c0 += 64) {
       const int c = c0 + lane;
       const bool f = (c < w) && flag[c];
       const unsigned long long m = __ballot(f);
-      const int pos = base + __popcll(m & ((1ull << lane) - 1ull));
-      if (f) klist[pos] = c;
+      const unsigned long long mu = __ballot(!f);
+      const unsigned long long below = (1ull << lane) - 1ull;
+      if (f) klist[base + __popcll(m & below)] = c;
+      else ulist[ubase + __popcll(mu & below)] = c;
       base += __popcll(m);
+      ubase += __popcll(mu);
     }
-    if (lane == 0) *kcnt = base;
+    if (lane == 0) {
+      *kcnt = base;
+      *ucnt = ubase;
+    }
   }
   lds_barrier();
 }
@@ -314,7 +340,7 @@ __device__ __forceinline__ void chol_blocked(const double* __restrict__ G, int w
 // T goes to LDS (row-major, odd row stride).  Dropped columns become unit
 // rows and columns, T' = T_kept (+) I, whose inverse restricted to the kept
 // rows and columns is T_kept^{-1}.  The inverse is formed in place:
-//   * 32 x 32 diagonal blocks by back substitution, one column per lane
+//   * 16 x 16 diagonal blocks by back substitution, one column per lane
 //     (T X = I solved from the bottom row up, register arrays with
 //     compile-time indices, broadcast LDS reads of T);
 //   * pairs of finished blocks joined by X_AB = -X_A (T_AB X_B), the two
@@ -329,33 +355,26 @@ struct LdsInvShape {
   static constexpr int THREADS = 64 * NW;
 };
 
-// C = alpha * A B for S x S blocks stored in LDS (row stride TS); one 16 x 16
-// output block per (wave, job) round.  A starts at row ra, column ka; B at
-// row kb (default ka), column cb; the output goes to (rc, cc).
+// One 16 x 16 output block (bi, bj) of C = alpha * A B with S x S operands
+// in LDS (row stride TS): A at (ra, ka), B at (kb, cb), C at (rc, cc).
 template <int TS, int S>
-__device__ __forceinline__ void lds_block_product(double* M, int ra, int ka, int cb, int rc, int cc,
-                                                  double alpha, int job0, int jobstep,
-                                                  int kb = -1) {
+__device__ __forceinline__ void lds_block16(double* M, int ra, int ka, int kb, int cb, int rc,
+                                            int cc, double alpha, int bi, int bj) {
   typedef double d4 __attribute__((ext_vector_type(4)));
   const int lane = threadIdx.x & 63;
-  constexpr int nb = S / 16;
-  if (kb < 0) kb = ka;
-  for (int job = job0; job < nb * nb; job += jobstep) {
-    const int bi = job / nb, bj = job % nb;
-    double a[S / 4], b[S / 4];
+  double a[S / 4], b[S / 4];
 #pragma unroll
-    for (int k4 = 0; k4 < S / 4; ++k4) {
-      a[k4] = M[(ra + 16 * bi + (lane & 15)) * TS + ka + 4 * k4 + (lane >> 4)];
-      b[k4] = M[(kb + 4 * k4 + (lane >> 4)) * TS + cb + 16 * bj + (lane & 15)];
-    }
-    d4 acc = (d4){0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int k4 = 0; k4 < S / 4; ++k4)
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[k4], b[k4], acc, 0, 0, 0);
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-      M[(rc + 16 * bi + (lane >> 4) + 4 * r) * TS + cc + 16 * bj + (lane & 15)] = alpha * acc[r];
+  for (int k4 = 0; k4 < S / 4; ++k4) {
+    a[k4] = M[(ra + 16 * bi + (lane & 15)) * TS + ka + 4 * k4 + (lane >> 4)];
+    b[k4] = M[(kb + 4 * k4 + (lane >> 4)) * TS + cb + 16 * bj + (lane & 15)];
   }
+  d4 acc = (d4){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k4 = 0; k4 < S / 4; ++k4)
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[k4], b[k4], acc, 0, 0, 0);
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+    M[(rc + 16 * bi + (lane >> 4) + 4 * r) * TS + cc + 16 * bj + (lane & 15)] = alpha * acc[r];
 }
 
 template <int WMAX>
@@ -368,67 +387,81 @@ __global__ __launch_bounds__(512) void chol_inv_lds_kernel(const double* __restr
   __shared__ double rdiag[WMAX];
   __shared__ int flag[WMAX];
   __shared__ int klist[WMAX];
-  __shared__ int kcnt;
+  __shared__ int ulist[WMAX];
+  __shared__ int kcnt, ucnt;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 
-  chol_blocked<WMAX, NW>(G, w, Ts, flag, rdiag, klist, &kcnt);
-  // pad to the full WMAX x WMAX upper triangle with an identity block and
-  // turn dropped columns into unit rows/columns
-  for (int idx = threadIdx.x; idx < WMAX * WMAX; idx += blockDim.x) {
-    const int r = idx / WMAX, c = idx % WMAX;
-    if (c < r) continue;
-    const bool rpad = r >= w, cpad = c >= w;
-    const bool rdrop = !rpad && !flag[r], cdrop = !cpad && !flag[c];
-    if (rpad || cpad || rdrop || cdrop) Ts[r * TS + c] = (r == c) ? 1.0 : 0.0;
+  chol_blocked<WMAX, NW>(G, w, Ts, flag, rdiag, klist, &kcnt, ulist, &ucnt);
+  // T' = T with every dropped or padding index u turned into a unit row and
+  // column (its inverse restricted to the kept indices is T_kept^{-1})
+  const int nu = ucnt;
+  if (nu > 0) {
+    for (int job = wave; job < nu; job += NW) {
+      const int u = ulist[job];
+      for (int c = lane; c < WMAX; c += 64) {
+        if (c >= u) Ts[u * TS + c] = (c == u) ? 1.0 : 0.0;
+        if (c <= u) Ts[c * TS + u] = (c == u) ? 1.0 : 0.0;
+      }
+    }
+    lds_barrier();
   }
-  lds_barrier();
 
-  // 32 x 32 diagonal blocks: lanes 0..31 of waves 0..WMAX/32-1, one column
-  // each, T X = I solved from the bottom row up in axpy form
-  if (wave < WMAX / 32 && lane < 32) {
-    const int o = 32 * wave, j = lane;
-    double x[32];
-    static_for<32>([&](auto r) { x[r] = (r == j) ? 1.0 : 0.0; });
-    static_for<32>([&](auto ii) {
-      constexpr int i = 31 - decltype(ii)::value;
+  // 16 x 16 diagonal blocks, one per wave, lanes 0..15 one column each:
+  // T X = I from the bottom row up in axpy form, with the stored pivot
+  // reciprocals instead of divisions
+  if (wave < WMAX / 16 && lane < 16) {
+    const int o = 16 * wave, j = lane;
+    double x[16];
+    static_for<16>([&](auto r) { x[r] = (r == j) ? 1.0 : 0.0; });
+    static_for<16>([&](auto ii) {
+      constexpr int i = 15 - decltype(ii)::value;
       x[i] *= rdiag[o + i];
       static_for<i>([&](auto r) { x[r] = fma(-Ts[(o + r) * TS + o + i], x[i], x[r]); });
     });
-    static_for<32>([&](auto i) { Ts[(o + i) * TS + o + j] = x[i]; });
+    static_for<16>([&](auto i) { Ts[(o + i) * TS + o + j] = x[i]; });
   }
   lds_barrier();
 
-  // join pairs of inverted blocks: X_AB = -X_A (T_AB X_B)
-  static_for<(WMAX == 128) ? 2 : 1>([&](auto lev) {
-    constexpr int s = 32 << decltype(lev)::value;
+  // join pairs of inverted s x s blocks, s = 16, 32, ...: X_AB = -X_A (T_AB X_B);
+  // the 16 x 16 output blocks of all pairs of a level are spread over the waves
+  static_for<(WMAX == 128) ? 3 : 2>([&](auto lev) {
+    constexpr int s = 16 << decltype(lev)::value;
     constexpr int pairs = WMAX / (2 * s);
+    constexpr int nb = s / 16;
+    constexpr int jobs = pairs * nb * nb;
     // M = T_AB X_B, stored at rows [ob, ob + s), columns [oa, oa + s)
-    for (int p = 0; p < pairs; ++p) {
-      const int oa = 2 * s * p, ob = oa + s;
-      lds_block_product<TS, s>(Ts, oa, ob, ob, ob, oa, 1.0, wave, NW);
+    for (int job = wave; job < jobs; job += NW) {
+      const int pr = job / (nb * nb), q = job % (nb * nb);
+      const int oa = 2 * s * pr, ob = oa + s;
+      lds_block16<TS, s>(Ts, oa, ob, ob, ob, ob, oa, 1.0, q / nb, q % nb);
     }
     lds_barrier();
-    // X_AB = -X_A M, written over T_AB: A = X_A at (oa, oa), B = M at (ob, oa)
-    for (int p = 0; p < pairs; ++p) {
-      const int oa = 2 * s * p, ob = oa + s;
-      lds_block_product<TS, s>(Ts, oa, oa, oa, oa, ob, -1.0, wave, NW, ob);
+    // X_AB = -X_A M over T_AB: A = X_A at (oa, oa), B = M at (ob, oa)
+    for (int job = wave; job < jobs; job += NW) {
+      const int pr = job / (nb * nb), q = job % (nb * nb);
+      const int oa = 2 * s * pr, ob = oa + s;
+      lds_block16<TS, s>(Ts, oa, oa, ob, oa, oa, ob, -1.0, q / nb, q % nb);
     }
     lds_barrier();
-    // clear M: the joined 2s x 2s block must be upper triangular for the next level
-    for (int p = 0; p < pairs; ++p) {
-      const int oa = 2 * s * p, ob = oa + s;
-      for (int idx = threadIdx.x; idx < s * s; idx += blockDim.x)
-        Ts[(ob + idx / s) * TS + oa + idx % s] = 0.0;
+    // clear M: the joined 2s x 2s block must be upper triangular again
+    for (int idx = threadIdx.x; idx < pairs * s * s; idx += blockDim.x) {
+      const int pr = idx / (s * s), e = idx % (s * s);
+      const int oa = 2 * s * pr, ob = oa + s;
+      Ts[(ob + e / s) * TS + oa + e % s] = 0.0;
     }
     lds_barrier();
   });
 
-  // expanded inverse: column a <- column kept[a] of T'^{-1}
+  // expanded inverse: column a <- column kept[a] of T'^{-1}, zero for a >= count
   const int wk = kcnt;
-#pragma unroll 8
-  for (int idx = threadIdx.x; idx < w * w; idx += blockDim.x) {
-    const int r = idx % w, a = idx / w;
-    Tinv[idx] = (a < wk) ? Ts[r * TS + klist[a]] : 0.0;
+  for (int a = wave; a < w; a += NW) {
+    double* col = Tinv + static_cast<int64_t>(a) * w;
+    if (a < wk) {
+      const int kc = klist[a];
+      for (int r = lane; r < w; r += 64) col[r] = Ts[r * TS + kc];
+    } else {
+      for (int r = lane; r < w; r += 64) col[r] = 0.0;
+    }
   }
   for (int i = threadIdx.x; i < wk; i += blockDim.x) kept[1 + i] = klist[i];
   if (threadIdx.x == 0) kept[0] = wk;

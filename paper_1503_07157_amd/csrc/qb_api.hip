@@ -124,6 +124,34 @@ bool valid_sizes(int64_t m, int64_t n, int32_t b) {
          n < (int64_t(1) << 31);
 }
 
+// Per-thread pinned host mailbox for the per-block scalars and an event that
+// marks their arrival.  Pinned memory makes the device-to-host copy truly
+// asynchronous, so work queued after it (the next block's sketch and
+// sample) runs while the host waits only for the copy.  Allocated on first
+// use and kept for the life of the thread (a few dozen bytes).
+struct Mailbox {
+  double* scal = nullptr;   // [0..1] resid^2 (hi, lo), [2..3] ||B_i||^2 (hi, lo)
+  int* kept = nullptr;
+  hipEvent_t ev = nullptr;
+  bool ok = false;
+};
+
+Mailbox* mailbox() {
+  thread_local Mailbox mb;
+  if (!mb.ok) {
+    void* p = nullptr;
+    if (hipHostMalloc(&p, 64, hipHostMallocDefault) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&mb.ev, hipEventDisableTiming) != hipSuccess) {
+      (void)hipHostFree(p);
+      return nullptr;
+    }
+    mb.scal = static_cast<double*>(p);
+    mb.kept = reinterpret_cast<int*>(static_cast<char*>(p) + 4 * sizeof(double));
+    mb.ok = true;
+  }
+  return &mb;
+}
+
 int sample(uint32_t prec, const double* X, int64_t ldx, const double* W, int64_t ldw, double* Y,
            int64_t ldy, int64_t M, int64_t N, int64_t K, double* part, hipStream_t s) {
   // the bf16x3 form of this product runs one workgroup per CU
@@ -254,14 +282,23 @@ int qb_factor(const double* A, int64_t m, int64_t n, int64_t lda, double eps, in
     if (copy_matrix(A, lda, R, ldr, m, n, st)) return QB_EHIP;
   }
 
+  Mailbox* mb = mailbox();
+  if (mb == nullptr) return QB_EHIP;
   DD sigB{0.0, 0.0};
   const int64_t ldm = wk.ldm;
+  // sketch and sample of a block already queued behind the previous block's
+  // scalars (started before the stop decision was known), as (k, w)
+  int64_t spec_k = -1;
+  int spec_w = 0;
   for (;;) {
     const int w = static_cast<int>(std::min<int64_t>(bw, kcap - k));
     if (w <= 0) { reason = (kcap < r) ? QB_STOP_KMAX : QB_STOP_RANK_CAP; break; }
     // (2)-(3) sample the residual and orthonormalise
-    if (launch_sketch(seed, n, k, w, wk.omega, n, st)) return QB_EHIP;
-    if (sample(prec, R, ldr, wk.omega, n, wk.Y, ldm, m, w, n, wk.part, st)) return QB_EHIP;
+    if (spec_k != k || spec_w != w) {
+      if (launch_sketch(seed, n, k, w, wk.omega, n, st)) return QB_EHIP;
+      if (sample(prec, R, ldr, wk.omega, n, wk.Y, ldm, m, w, n, wk.part, st)) return QB_EHIP;
+    }
+    spec_k = -1;
     if (orth_cholqr2(wk.Y, ldm, wk.Qi, ldm, m, w, wk.ow, st)) return QB_EHIP;
     // (4)-(7) power iterations on the residual
     for (int p = 0; p < power_iters; ++p) {
@@ -299,12 +336,29 @@ int qb_factor(const double* A, int64_t m, int64_t n, int64_t lda, double eps, in
     if (sum_partials(wk.sq1, nb, wk.scal + 2, st)) return QB_EHIP;
     if (downdate(R, ldr, Qout, ldq, B + k, ldb, m, n, w, wk.sq2, &nd, st)) return QB_EHIP;
     if (sum_partials(wk.sq2, nd, wk.scal + 0, st)) return QB_EHIP;
-    double hs[4];
-    int wkept = 0;
-    if (hipMemcpyAsync(hs, wk.scal, 4 * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
-        hipMemcpyAsync(&wkept, wk.ow.kept, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
-        hipStreamSynchronize(st) != hipSuccess)
+    if (hipMemcpyAsync(mb->scal, wk.scal, 4 * sizeof(double), hipMemcpyDeviceToHost, st) !=
+            hipSuccess ||
+        hipMemcpyAsync(mb->kept, wk.ow.kept, sizeof(int), hipMemcpyDeviceToHost, st) !=
+            hipSuccess ||
+        hipEventRecord(mb->ev, st) != hipSuccess)
       return QB_EHIP;
+    // Queue the next block's sketch and sample (they read only R, already
+    // downdated, and write only Omega and Y) assuming no column is dropped;
+    // the host decides meanwhile.  After a stop they are left unused.
+    {
+      const int64_t kn = k + w;
+      const int wn = static_cast<int>(std::min<int64_t>(bw, kcap - kn));
+      if (wn > 0) {
+        if (launch_sketch(seed, n, kn, wn, wk.omega, n, st)) return QB_EHIP;
+        if (sample(prec, R, ldr, wk.omega, n, wk.Y, ldm, m, wn, n, wk.part, st)) return QB_EHIP;
+        spec_k = kn;
+        spec_w = wn;
+      }
+    }
+    if (hipEventSynchronize(mb->ev) != hipSuccess) return QB_EHIP;
+    double hs[4];
+    std::memcpy(hs, mb->scal, sizeof(hs));
+    const int wkept = *mb->kept;
     if (wkept <= 0) { reason = QB_STOP_EXHAUSTED; break; }
     k += wkept;
     ++blocks;
