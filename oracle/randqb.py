@@ -98,19 +98,26 @@ def _stop_decision(E: float, D: float, eps2: float, delta: float):
 
 def randqb_pb(A: np.ndarray, eps: float, b: int, power_iters: int = 0, seed: int = 0,
               kmax: int | None = None, omega_fn=None, drop_rel: float = DROP_REL,
-              reorth: bool = True, power_orth: bool = True) -> QBResult:
+              reorth: bool = True, power_orth: bool = True,
+              max_blocks: int | None = None) -> QBResult:
     """Blocked adaptive QB of A (m x n) to Frobenius tolerance eps.
 
     omega_fn(n, col0, w) -> n x w, if given, replaces the Philox sketch (used
     by tests that need a prescribed Omega).  reorth=False skips step (3')
     (Section 4.4).  power_orth=False skips the orthonormalisation between
     applications of A and A^T (the variant examined in Sections 5.4 and
-    6.4): Y = (A A^T)^P A Omega_i, then Q_i = orth(Y).
+    6.4): Y = (A A^T)^P A Omega_i, then Q_i = orth(Y).  max_blocks=1 with
+    b = l is the unblocked scheme: randQB (Figure 3) for P = 0 and randQB_p
+    (Figure 5) for P >= 1, one pass of width l with no continuation when
+    orth drops columns; the run then ends with stop reason KMAX unless the
+    tolerance was met.
     """
     A = np.asarray(A, dtype=np.float64)
     m, n = A.shape
     r = min(m, n)
     if not (np.isfinite(eps) and eps >= 0) or b < 1 or power_iters < 0:
+        raise ValueError("invalid argument")
+    if max_blocks is not None and max_blocks < 1:
         raise ValueError("invalid argument")
     if not np.all(np.isfinite(A)):
         raise FloatingPointError("non-finite entry in A")
@@ -187,6 +194,9 @@ def randqb_pb(A: np.ndarray, eps: float, b: int, power_iters: int = 0, seed: int
             break
         if D <= floor2:
             reason = "EXHAUSTED"
+            break
+        if max_blocks is not None and res.blocks >= max_blocks:
+            reason = "KMAX"
             break
         if k >= kcap:
             reason = "KMAX" if kcap < r else "RANK_CAP"

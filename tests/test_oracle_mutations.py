@@ -147,3 +147,35 @@ def test_philox_constant_mutation_is_caught():
     real = oracle.philox.philox4x32_10(12345, 678, 0, 0, 1503, 0)
     fake = mod.philox4x32_10(12345, 678, 0, 0, 1503, 0)
     assert tuple(int(x) for x in real) != tuple(int(x) for x in fake)
+
+
+def _single_pass_pins_hold(randqb_pb) -> bool:
+    """Pins of test_oracle_skip_reorth: one pass without re-orthonormalisation
+    spans (A A^T) A Omega; max_blocks=1 stops after one block."""
+    from oracle.gaussian import omega_block
+    s = 1.0 / (1.0 + np.arange(200)) ** 0.5
+    A = synth.prescribed_svd(300, 200, s, 3, 4)
+    try:
+        r = randqb_pb(A, 0.0, 30, 1, 6, kmax=60, max_blocks=1, power_orth=False)
+    except Exception:
+        return False
+    Y = A @ omega_block(6, 200, 0, 30)
+    Y = A @ (A.T @ Y)
+    Q = np.linalg.qr(Y)[0]
+    return (r.blocks == 1 and r.k == 30
+            and np.linalg.norm(r.Q @ r.Q.T - Q @ Q.T) < 1e-9)
+
+
+def test_real_oracle_passes_the_single_pass_pins():
+    assert _single_pass_pins_hold(oracle.randqb_pb)
+
+
+@pytest.mark.parametrize("old,new", [
+    ("            for _ in range(power_iters):\n                Y = R @ (R.T @ Y)",
+     "            for _ in range(power_iters - 1):\n                Y = R @ (R.T @ Y)"),  # one power too few
+    ("if max_blocks is not None and res.blocks >= max_blocks:",
+     "if max_blocks is not None and res.blocks > max_blocks:"),           # block cap off by one
+])
+def test_single_pass_mutations_are_caught(old, new):
+    mod = mutant("randqb", old, new)
+    assert not _single_pass_pins_hold(mod.randqb_pb)
