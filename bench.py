@@ -56,12 +56,13 @@ def profile_snapshot(lib):
     return out
 
 
-def run_variant(qbmi, lib, torch, A, eps, wl, P, sample, steps, warmup, bufs, profile):
+def run_variant(qbmi, lib, torch, A, eps, wl, P, sample, steps, warmup, bufs, profile,
+                power_orth=True):
     Q, B, ws = bufs
 
     def one():
         return qbmi.qb_factor(A, eps, wl.b, P, wl.seed_omega, sample=sample, workspace=ws,
-                              Q=Q, B=B)
+                              Q=Q, B=B, power_orth=power_orth)
 
     for _ in range(warmup):
         one()
@@ -141,6 +142,45 @@ def cpu_baseline(A_host, eps, wl, P, blocks):
                       f"same nominal count as the GPU value"}
 
 
+def skip_reorth_experiment():
+    """Section 6.4 / Figure 8 on the GPU: Matrix 1 (800 x 600, singular values
+    from 0.59 down to 1e-18), error of the single pass (randQB_p, l columns)
+    and of the blocked scheme (b = 10), with and without orthonormalisation
+    between applications of A and A^T.  Prints one JSON line."""
+    import numpy as np
+    import torch
+    import paper_1503_07157_amd as qbmi
+    import synth
+
+    A = synth.paper_matrix1(800, 600, seed=1)
+    s = np.linalg.svd(A, compute_uv=False)
+    nA = float(np.linalg.norm(A))
+    Ad = qbmi.colmajor(torch.from_numpy(np.ascontiguousarray(A)).cuda())
+    tau = 2.0 ** -20
+
+    def err(res):
+        R = Ad - res.Q @ res.B
+        return float(torch.linalg.norm(R)) / float(s[0])
+
+    rows = []
+    for P in (1, 2):
+        for l in (20, 40, 60, 80):
+            ey = float(np.sqrt(np.sum(s[l:] ** 2))) / float(s[0])
+            row = {"P": P, "l": l, "eckart_young": ey}
+            for orth in (True, False):
+                r = qbmi.qb_factor(Ad, 0.0, l, P, 7, kmax=l, power_orth=orth, single_block=True)
+                row["single_" + ("orth" if orth else "no_orth")] = {"err": err(r), "k": r.k}
+            rows.append(row)
+        for orth in (True, False):
+            r = qbmi.qb_factor(Ad, 1e-13 * nA, 10, P, 7, power_orth=orth)
+            rows.append({"P": P, "blocked_b10": "orth" if orth else "no_orth", "err": err(r),
+                         "k": r.k, "stop": r.stop_reason})
+    print(json.dumps({"experiment": "skip-reorth", "matrix": "paper Matrix 1, 800x600, seed 1",
+                      "sigma1": float(s[0]), "tau": tau,
+                      "floor_single_no_orth": {str(P): tau ** (1 / (2 * P + 1)) for P in (1, 2)},
+                      "floor_single_orth": tau, "rows": rows}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -152,6 +192,8 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-blocks", type=int, default=16)
+    ap.add_argument("--experiment", default=None, choices=["skip-reorth"],
+                    help="run the Section 6.4 comparison instead of the benchmark")
     ap.add_argument("--matrix", default="workload", choices=["workload", "gaussian"],
                     help="gaussian: i.i.d. N(0, 1/m) entries of the workload's shape instead of "
                          "the prescribed spectrum (no QR in the process; used for hardware-counter "
@@ -161,6 +203,9 @@ def main():
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
               f"(this build has no multi-GPU path)", file=sys.stderr)
         sys.exit(2)
+    if args.experiment == "skip-reorth":
+        skip_reorth_experiment()
+        return
 
     import torch
     import paper_1503_07157_amd as qbmi
@@ -219,20 +264,25 @@ def main():
 
     variants = []
     if not args.no_variants:
-        for (vp, vs) in [(0, "f64"), (P, "f32"), (P, "bf16x3"), (0, "f32"), (0, "bf16x3")]:
-            if (vp, vs) == (P, args.sample):
+        todo = [(0, "f64", True), (P, "f32", True), (P, "bf16x3", True), (0, "f32", True),
+                (0, "bf16x3", True)]
+        if P > 0:
+            todo.append((P, "f64", False))   # no orth between A and A^T (Section 5.4)
+        for (vp, vs, vo) in todo:
+            if (vp, vs, vo) == (P, args.sample, True):
                 continue
             try:
                 vres, vms, _ = run_variant(qbmi, lib, torch, A, eps, wl, vp, vs, args.steps,
-                                           args.warmup, bufs, profile=False)
+                                           args.warmup, bufs, profile=False, power_orth=vo)
             except qbmi.QBError as e:
-                variants.append({"power_iters": vp, "sample": vs, "error": str(e)})
+                variants.append({"power_iters": vp, "sample": vs, "power_orth": vo,
+                                 "error": str(e)})
                 continue
             vfl = nominal_flops(m, n, vres.k, vp)
-            variants.append({"power_iters": vp, "sample": vs, "k": vres.k, "solve_s": vms / 1e3,
-                             "gflops": vfl / (vms * 1e-3) / 1e9,
+            variants.append({"power_iters": vp, "sample": vs, "power_orth": vo, "k": vres.k,
+                             "solve_s": vms / 1e3, "gflops": vfl / (vms * 1e-3) / 1e9,
                              "rel_err": residual_rel(torch, A, vres), "stop": vres.stop_reason})
-            log(f"[bench] variant P={vp} {vs}: k={vres.k} {vms:.1f} ms")
+            log(f"[bench] variant P={vp} {vs}{'' if vo else ' no-orth'}: k={vres.k} {vms:.1f} ms")
 
     cpu = None
     if not args.no_cpu:

@@ -71,6 +71,16 @@ extern "C" {
 #define QB_BGEMM_F32      (1u << 6)
 #define QB_BGEMM_BF16X3   (2u << 6)
 #define QB_BGEMM_MASK     (3u << 6)
+/* Section 5.4 / Figure 8 comparison: skip the orthonormalisation between
+ * applications of A and A^T, i.e. Y = (A A^T)^P A Omega_i, then Q_i = orth(Y).
+ * Without it a pass resolves nothing below sigma_1 tau^(1/(2P+1)), tau = 2^-20
+ * the relative column size orth can separate; the blocked scheme recovers
+ * the rest in later blocks. */
+#define QB_POWER_NO_ORTH  (1u << 8)
+/* Stop after the first block whatever its kept width: the unblocked randQB
+ * (Figure 3) and randQB_p (Figure 5) with l = b.  Returns QB_KMAX (stop
+ * reason QB_STOP_KMAX) unless the tolerance was met. */
+#define QB_SINGLE_BLOCK   (1u << 9)
 
 /* Per-call report.  The trace arrays are optional HOST arrays owned by the
  * caller (set the pointers to NULL or trace_cap to 0 to skip).  Entry i

@@ -35,6 +35,8 @@ QB_STOP = {0: "TOL_TRACKED", 1: "TOL_DIRECT", 2: "RANK_CAP", 3: "EXHAUSTED", 4: 
 QB_OVERWRITE_A = 1 << 0
 QB_SAMPLE = {"f64": 0 << 4, "f32": 1 << 4, "bf16x3": 2 << 4}
 QB_BGEMM = {"f64": 0 << 6, "f32": 1 << 6, "bf16x3": 2 << 6}
+QB_POWER_NO_ORTH = 1 << 8
+QB_SINGLE_BLOCK = 1 << 9
 
 
 class QBInfo(ctypes.Structure):

@@ -36,14 +36,19 @@ struct Shape {
   static constexpr int BM = BM_, BN = BN_;
   static constexpr int WM = BM / 2, WN = BN / 2;    // wave sub-tile
   static constexpr int IB = WM / 16, JB = WN / 16;  // MFMA blocks per wave
-  static constexpr int SA_M = BM + 1;               // A stored [k][m] (m contiguous)
-  static constexpr int SA_K = BK + 1;               // A stored [m][k] (k contiguous)
-  static constexpr int SB_K = BK + 1;               // B stored [n][k] (k contiguous)
+  // LDS row strides (doubles).  MFMA fragment reads touch 16 rows x 4 depth
+  // indices per instruction; with 32 eight-byte banks, a stride of BM + 16
+  // (= 16 mod 32) puts the second group of 16 lanes on the other half of
+  // the banks, and 18 (even) keeps the k-contiguous fragments conflict-free
+  // while leaving every element pair 16-byte aligned for vector stores.
+  static constexpr int SA_M = BM + 16;              // A stored [k][m] (m contiguous)
+  static constexpr int SA_K = BK + 2;               // A stored [m][k] (k contiguous)
+  static constexpr int SB_K = BK + 2;               // B stored [n][k] (k contiguous)
   static constexpr int A_LDS = (BK * SA_M > BM * SA_K) ? BK * SA_M : BM * SA_K;
   static constexpr int B_LDS = BN * SB_K;
   static constexpr int PA = (BM * BK) / NT, PB = (BN * BK) / NT;  // elements per thread per fill
 };
-// Big: two LDS stages of A and B take 69.6 KB, so two workgroups share a
+// Big: two LDS stages of A and B take 73.7 KB, so two workgroups share a
 // CU's 160 KB.  Small: a quarter of the work per workgroup, for outputs
 // too small to give every CU a 128 x 128 tile.
 using Big = Shape<128, 128>;
@@ -168,17 +173,12 @@ struct FastTile {
     for (int q = 0; q < QB; ++q) rb[q] = buf_load2(rB, ob[q], sb);
   }
 
+  // every pair starts at an even LDS element (even strides, even offsets)
   __device__ __forceinline__ void store(double* As, double* Bs) const {
 #pragma unroll
-    for (int q = 0; q < QA; ++q) {
-      As[la[q]] = ra[q].x;
-      As[la[q] + 1] = ra[q].y;
-    }
+    for (int q = 0; q < QA; ++q) *reinterpret_cast<double2*>(As + la[q]) = ra[q];
 #pragma unroll
-    for (int q = 0; q < QB; ++q) {
-      Bs[lb[q]] = rb[q].x;
-      Bs[lb[q] + 1] = rb[q].y;
-    }
+    for (int q = 0; q < QB; ++q) *reinterpret_cast<double2*>(Bs + lb[q]) = rb[q];
   }
 };
 
@@ -353,8 +353,8 @@ __global__ __launch_bounds__(NT, 2) void gemm_nn_kernel(const double* __restrict
                                                         int64_t kchunk, double alpha, double beta,
                                                         double* __restrict__ part, int64_t ldp,
                                                         int vec_y, int vec_ab) {
-  __shared__ double As[2 * S::A_LDS];
-  __shared__ double Bs[2 * S::B_LDS];
+  __shared__ __attribute__((aligned(16))) double As[2 * S::A_LDS];
+  __shared__ __attribute__((aligned(16))) double Bs[2 * S::B_LDS];
   const int64_t m0 = static_cast<int64_t>(blockIdx.x) * S::BM;
   const int64_t n0 = static_cast<int64_t>(blockIdx.y) * S::BN;
   const int64_t kbeg = static_cast<int64_t>(blockIdx.z) * kchunk;
@@ -396,8 +396,8 @@ __global__ __launch_bounds__(NT, 2) void gemm_tn_kernel(const double* __restrict
                                                         double* __restrict__ part, int64_t ldp,
                                                         double* __restrict__ sq_part, int vec_c,
                                                         int vec_ab) {
-  __shared__ double As[2 * S::A_LDS];
-  __shared__ double Bs[2 * S::B_LDS];
+  __shared__ __attribute__((aligned(16))) double As[2 * S::A_LDS];
+  __shared__ __attribute__((aligned(16))) double Bs[2 * S::B_LDS];
   __shared__ double red[NT / 64];
   const int64_t n0 = static_cast<int64_t>(blockIdx.x) * S::BN;
   const int64_t m0 = static_cast<int64_t>(blockIdx.y) * S::BM;
@@ -534,8 +534,8 @@ __global__ __launch_bounds__(NT, 2) void downdate_kernel(double* __restrict__ R,
                                                          int64_t K,
                                                          double* __restrict__ sq_part,
                                                          int vec_r, int vec_ab) {
-  __shared__ double As[2 * S::A_LDS];
-  __shared__ double Bs[2 * S::B_LDS];
+  __shared__ __attribute__((aligned(16))) double As[2 * S::A_LDS];
+  __shared__ __attribute__((aligned(16))) double Bs[2 * S::B_LDS];
   __shared__ double red[NT / 64];
   const int64_t m0 = static_cast<int64_t>(blockIdx.x) * S::BM;
   const int64_t n0 = static_cast<int64_t>(blockIdx.y) * S::BN;

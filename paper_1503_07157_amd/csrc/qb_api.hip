@@ -215,6 +215,8 @@ int qb_factor(const double* A, int64_t m, int64_t n, int64_t lda, double eps, in
   // the B precision in the sampling encoding (QB_BGEMM_x >> 2 == QB_SAMPLE_x)
   const uint32_t bprec = (flags & QB_BGEMM_MASK) >> 2;
   if (bprec == QB_SAMPLE_MASK) return QB_EINVAL;
+  const bool power_orth = (flags & QB_POWER_NO_ORTH) == 0;
+  const bool single_block = (flags & QB_SINGLE_BLOCK) != 0;
   const int64_t r = std::min(m, n);
   if (kmax > r) return QB_EINVAL;
   const int64_t kcap = (kmax < 0) ? r : kmax;
@@ -299,13 +301,25 @@ int qb_factor(const double* A, int64_t m, int64_t n, int64_t lda, double eps, in
       if (sample(prec, R, ldr, wk.omega, n, wk.Y, ldm, m, w, n, wk.part, st)) return QB_EHIP;
     }
     spec_k = -1;
-    if (orth_cholqr2(wk.Y, ldm, wk.Qi, ldm, m, w, wk.ow, st)) return QB_EHIP;
-    // (4)-(7) power iterations on the residual
-    for (int p = 0; p < power_iters; ++p) {
-      if (project_t(prec, wk.Qi, ldm, R, ldr, wk.Z, n, w, n, m, true, wk.part, nullptr, nullptr, st))
-        return QB_EHIP;
-      if (orth_cholqr2(wk.Z, n, wk.Z, n, n, w, wk.ow, st)) return QB_EHIP;
-      if (sample(prec, R, ldr, wk.Z, n, wk.Y, ldm, m, w, n, wk.part, st)) return QB_EHIP;
+    if (power_orth) {
+      if (orth_cholqr2(wk.Y, ldm, wk.Qi, ldm, m, w, wk.ow, st)) return QB_EHIP;
+      // (4)-(7) power iterations on the residual
+      for (int p = 0; p < power_iters; ++p) {
+        if (project_t(prec, wk.Qi, ldm, R, ldr, wk.Z, n, w, n, m, true, wk.part, nullptr,
+                      nullptr, st))
+          return QB_EHIP;
+        if (orth_cholqr2(wk.Z, n, wk.Z, n, n, w, wk.ow, st)) return QB_EHIP;
+        if (sample(prec, R, ldr, wk.Z, n, wk.Y, ldm, m, w, n, wk.part, st)) return QB_EHIP;
+        if (orth_cholqr2(wk.Y, ldm, wk.Qi, ldm, m, w, wk.ow, st)) return QB_EHIP;
+      }
+    } else {
+      // Section 5.4: Y = (R R^T)^P R Omega_i without intermediate orth
+      for (int p = 0; p < power_iters; ++p) {
+        if (project_t(prec, wk.Y, ldm, R, ldr, wk.Z, n, w, n, m, true, wk.part, nullptr, nullptr,
+                      st))
+          return QB_EHIP;
+        if (sample(prec, R, ldr, wk.Z, n, wk.Y, ldm, m, w, n, wk.part, st)) return QB_EHIP;
+      }
       if (orth_cholqr2(wk.Y, ldm, wk.Qi, ldm, m, w, wk.ow, st)) return QB_EHIP;
     }
     double* Qout = Q + k * ldq;
@@ -348,7 +362,7 @@ int qb_factor(const double* A, int64_t m, int64_t n, int64_t lda, double eps, in
     {
       const int64_t kn = k + w;
       const int wn = static_cast<int>(std::min<int64_t>(bw, kcap - kn));
-      if (wn > 0) {
+      if (wn > 0 && !single_block) {
         if (launch_sketch(seed, n, kn, wn, wk.omega, n, st)) return QB_EHIP;
         if (sample(prec, R, ldr, wk.omega, n, wk.Y, ldm, m, wn, n, wk.part, st)) return QB_EHIP;
         spec_k = kn;
@@ -376,6 +390,7 @@ int qb_factor(const double* A, int64_t m, int64_t n, int64_t lda, double eps, in
     if (lastE <= eps2 - delta) { reason = QB_STOP_TOL_TRACKED; break; }
     if (!(lastE > eps2 + delta) && lastD <= eps2) { reason = QB_STOP_TOL_DIRECT; break; }
     if (lastD <= floor2) { reason = QB_STOP_EXHAUSTED; break; }
+    if (single_block) { reason = QB_STOP_KMAX; break; }
     if (k >= kcap) { reason = (kcap < r) ? QB_STOP_KMAX : QB_STOP_RANK_CAP; break; }
   }
   return finish(reason);
