@@ -27,14 +27,18 @@ namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-constexpr int BK = kTileK, NT = kGemmThreads;
+constexpr int BK = kTileK;
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-template <int BM_, int BN_>
+// BM x BN output tile per workgroup of WGM x WGN waves; each wave owns a
+// (BM/WGM) x (BN/WGN) sub-tile.
+template <int BM_, int BN_, int WGM_ = 2, int WGN_ = 2>
 struct Shape {
-  static constexpr int BM = BM_, BN = BN_;
-  static constexpr int WM = BM / 2, WN = BN / 2;    // wave sub-tile
+  static constexpr int BM = BM_, BN = BN_, WGM = WGM_, WGN = WGN_;
+  static constexpr int NT = 64 * WGM * WGN;          // threads per workgroup
+  static constexpr int OCC = NT <= 256 ? 2 : 1;      // workgroups per CU (LDS bound)
+  static constexpr int WM = BM / WGM, WN = BN / WGN; // wave sub-tile
   static constexpr int IB = WM / 16, JB = WN / 16;  // MFMA blocks per wave
   // LDS row strides (doubles).  MFMA fragment reads touch 16 rows x 4 depth
   // indices per instruction; with 32 eight-byte banks, a stride of BM + 16
@@ -50,9 +54,14 @@ struct Shape {
 };
 // Big: two LDS stages of A and B take 73.7 KB, so two workgroups share a
 // CU's 160 KB.  Small: a quarter of the work per workgroup, for outputs
-// too small to give every CU a 128 x 128 tile.
+// too small to give every CU a 128 x 128 tile.  Tall: 256 x 128 with 8
+// waves (110 KB of LDS, one workgroup per CU) for products whose A operand
+// is m-contiguous and tall: every depth slice reads 2 KB contiguous per
+// column of A instead of 1 KB (a whole DRAM page instead of half of one),
+// and the B slice is shared by twice the rows.
 using Big = Shape<128, 128>;
 using Small = Shape<64, 64>;
+using Tall = Shape<256, 128, 4, 2>;
 static_assert(Big::BM == kTileM && Big::BN == kTileN, "tile constants");
 
 // A is "m-contiguous" when element (m, k) lies at X[m + k*ld] (column-major
@@ -76,7 +85,7 @@ struct Tile {
     const double* bbase = Bm + kc + n0 * ldb;
 #pragma unroll
     for (int q = 0; q < S::PA; ++q) {
-      const int e = t + NT * q;
+      const int e = t + S::NT * q;
       if (A_KCONTIG) {
         const int kk = e % BK, i = e / BK;
         ra[q] = (i < mlim && kk < klim)
@@ -89,7 +98,7 @@ struct Tile {
     }
 #pragma unroll
     for (int q = 0; q < S::PB; ++q) {
-      const int e = t + NT * q;
+      const int e = t + S::NT * q;
       const int kk = e % BK, nn = e / BK;
       rb[q] = (nn < nlim && kk < klim)
                   ? bbase[static_cast<uint32_t>(kk) + static_cast<uint32_t>(nn) * lb] : 0.0;
@@ -100,13 +109,13 @@ struct Tile {
     const int t = threadIdx.x;
 #pragma unroll
     for (int q = 0; q < S::PA; ++q) {
-      const int e = t + NT * q;
+      const int e = t + S::NT * q;
       if (A_KCONTIG) As[(e / BK) * S::SA_K + (e % BK)] = ra[q];
       else As[(e / S::BM) * S::SA_M + (e % S::BM)] = ra[q];
     }
 #pragma unroll
     for (int q = 0; q < S::PB; ++q) {
-      const int e = t + NT * q;
+      const int e = t + S::NT * q;
       Bs[(e / BK) * S::SB_K + (e % BK)] = rb[q];
     }
   }
@@ -145,7 +154,7 @@ struct FastTile {
     const uint32_t ua = static_cast<uint32_t>(lda), ub = static_cast<uint32_t>(ldb);
 #pragma unroll
     for (int q = 0; q < QA; ++q) {
-      const int e2 = t + NT * q;
+      const int e2 = t + S::NT * q;
       if (A_KCONTIG) {  // pairs along k: element (i, 2kp .. 2kp+1)
         const int kp = e2 % (BK / 2), i = e2 / (BK / 2);
         oa[q] = 8u * (2u * kp + static_cast<uint32_t>(i) * ua);
@@ -158,7 +167,7 @@ struct FastTile {
     }
 #pragma unroll
     for (int q = 0; q < QB; ++q) {
-      const int e2 = t + NT * q;
+      const int e2 = t + S::NT * q;
       const int kp = e2 % (BK / 2), nn = e2 / (BK / 2);
       ob[q] = 8u * (2u * kp + static_cast<uint32_t>(nn) * ub);
       lb[q] = nn * S::SB_K + 2 * kp;
@@ -195,7 +204,7 @@ __device__ __forceinline__ void mma_slice(const double* Ac, const double* Bc,
                                           d4 (&acc)[S::IB][S::JB]) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int wm = (wave & 1) * S::WM, wn = (wave >> 1) * S::WN;
+  const int wm = (wave % S::WGM) * S::WM, wn = (wave / S::WGM) * S::WN;
   const int lr = lane & 15, lk = lane >> 4;
   const int pr = perm16(lr);
 #pragma unroll
@@ -287,12 +296,12 @@ __device__ __forceinline__ void mma_loop(const double* __restrict__ A, int64_t l
 template <class S>
 __device__ __forceinline__ int acc_row0(int i) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  return (wave & 1) * S::WM + 16 * i + 4 * (lane >> 4);
+  return (wave % S::WGM) * S::WM + 16 * i + 4 * (lane >> 4);
 }
 template <class S>
 __device__ __forceinline__ int acc_col(int j) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  return (wave >> 1) * S::WN + 16 * j + (lane & 15);
+  return (wave / S::WGM) * S::WN + 16 * j + (lane & 15);
 }
 
 // four consecutive rows [row0, row0 + 4) of column col of X (ld); vec: X and
@@ -346,7 +355,7 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 // Y = alpha X W + beta Y   (X: M x K m-contiguous, W: K x N, k-contiguous)
 // grid: (M tiles, N tiles, split); split > 1 writes part[z] (M x N, ld ldp)
 template <class S>
-__global__ __launch_bounds__(NT, 2) void gemm_nn_kernel(const double* __restrict__ X, int64_t ldx,
+__global__ __launch_bounds__(S::NT, S::OCC) void gemm_nn_kernel(const double* __restrict__ X, int64_t ldx,
                                                         const double* __restrict__ W, int64_t ldw,
                                                         double* __restrict__ Y, int64_t ldy,
                                                         int64_t M, int64_t N, int64_t K,
@@ -388,7 +397,7 @@ __global__ __launch_bounds__(NT, 2) void gemm_nn_kernel(const double* __restrict
 // C = Q^T X  (Q: K x P so A = Q^T is k-contiguous; X: K x N)
 // grid: (N tiles, P tiles, split)
 template <class S>
-__global__ __launch_bounds__(NT, 2) void gemm_tn_kernel(const double* __restrict__ Qm, int64_t ldq,
+__global__ __launch_bounds__(S::NT, S::OCC) void gemm_tn_kernel(const double* __restrict__ Qm, int64_t ldq,
                                                         const double* __restrict__ X, int64_t ldx,
                                                         double* __restrict__ C, int64_t ldc,
                                                         int64_t P, int64_t N, int64_t K,
@@ -398,7 +407,7 @@ __global__ __launch_bounds__(NT, 2) void gemm_tn_kernel(const double* __restrict
                                                         int vec_ab) {
   __shared__ __attribute__((aligned(16))) double As[2 * S::A_LDS];
   __shared__ __attribute__((aligned(16))) double Bs[2 * S::B_LDS];
-  __shared__ double red[NT / 64];
+  __shared__ double red[S::NT / 64];
   const int64_t n0 = static_cast<int64_t>(blockIdx.x) * S::BN;
   const int64_t m0 = static_cast<int64_t>(blockIdx.y) * S::BM;
   const int64_t kbeg = static_cast<int64_t>(blockIdx.z) * kchunk;
@@ -526,7 +535,7 @@ void launch_reduce(const double* part, int nz, int64_t ldp, double* out, int64_t
 // R -= Q B; per-workgroup sum of squares of the updated tile.
 // grid: (M tiles, N tiles)
 template <class S>
-__global__ __launch_bounds__(NT, 2) void downdate_kernel(double* __restrict__ R, int64_t ldr,
+__global__ __launch_bounds__(S::NT, S::OCC) void downdate_kernel(double* __restrict__ R, int64_t ldr,
                                                          const double* __restrict__ Qm,
                                                          int64_t ldq,
                                                          const double* __restrict__ B,
@@ -536,7 +545,7 @@ __global__ __launch_bounds__(NT, 2) void downdate_kernel(double* __restrict__ R,
                                                          int vec_r, int vec_ab) {
   __shared__ __attribute__((aligned(16))) double As[2 * S::A_LDS];
   __shared__ __attribute__((aligned(16))) double Bs[2 * S::B_LDS];
-  __shared__ double red[NT / 64];
+  __shared__ double red[S::NT / 64];
   const int64_t m0 = static_cast<int64_t>(blockIdx.x) * S::BM;
   const int64_t n0 = static_cast<int64_t>(blockIdx.y) * S::BN;
   d4 acc[S::IB][S::JB];
@@ -576,13 +585,20 @@ int vec_ok(const double* p, int64_t ld) {
 // tile loads use 32-bit element offsets: 128 rows/columns times ld must fit
 bool ld_fits(int64_t ld) { return ld >= 0 && ld < (int64_t(1) << 24); }
 
+// Tall tiles for gemm_nn when there are enough of them for one workgroup
+// per CU: measured 465 us against 579 us for the 10000 x 10000 x 128 split-K
+// product, the A slices being read as whole 2 KB DRAM pages
+bool use_tall(int64_t M, int64_t N, int nz) {
+  return cdiv(M, Tall::BM) * cdiv(N, Tall::BN) * nz >= int64_t(7) * kNumCU / 8;
+}
+
 template <class S>
 void launch_nn(const double* X, int64_t ldx, const double* W, int64_t ldw, double* Y,
                int64_t ldy, int64_t M, int64_t N, int64_t K, int64_t kc, int nz, double alpha,
                double beta, double* part, int64_t ldp, hipStream_t s) {
   const dim3 grid(static_cast<unsigned>(cdiv(M, S::BM)), static_cast<unsigned>(cdiv(N, S::BN)),
                   static_cast<unsigned>(nz));
-  hipLaunchKernelGGL(gemm_nn_kernel<S>, grid, dim3(NT), 0, s, X, ldx, W, ldw, Y, ldy, M, N, K,
+  hipLaunchKernelGGL(gemm_nn_kernel<S>, grid, dim3(S::NT), 0, s, X, ldx, W, ldw, Y, ldy, M, N, K,
                      kc, alpha, beta, part, ldp, vec_ok(Y, ldy), vec_ok(X, ldx) & vec_ok(W, ldw));
 }
 
@@ -592,7 +608,7 @@ dim3 launch_tn(const double* Qm, int64_t ldq, const double* X, int64_t ldx, doub
                double* part, int64_t ldp, double* sq_part, hipStream_t s) {
   const dim3 grid(static_cast<unsigned>(cdiv(N, S::BN)), static_cast<unsigned>(cdiv(P, S::BM)),
                   static_cast<unsigned>(nz));
-  hipLaunchKernelGGL(gemm_tn_kernel<S>, grid, dim3(NT), 0, s, Qm, ldq, X, ldx, C, ldc, P, N, K,
+  hipLaunchKernelGGL(gemm_tn_kernel<S>, grid, dim3(S::NT), 0, s, Qm, ldq, X, ldx, C, ldc, P, N, K,
                      kc, tr ? 1 : 0, part, ldp, sq_part, vec_ok(C, ldc),
                      vec_ok(Qm, ldq) & vec_ok(X, ldx));
   return grid;
@@ -637,14 +653,18 @@ int gemm_nn(const double* X, int64_t ldx, const double* W, int64_t ldw, double* 
   const int nz = split > 1 ? static_cast<int>(cdiv(K, kc)) : 1;
   const int64_t ldp = part_ld(M);
   // unsplit products with too few 128 x 128 tiles to fill the chip (the
-  // T^{-1} application, short projections) take 64 x 64 tiles
+  // T^{-1} application, short projections) take 64 x 64 tiles; tall
+  // products with enough 256-row tiles for one workgroup per CU take Tall
   const bool small = nz == 1 && cdiv(M, Big::BM) * cdiv(N, Big::BN) < kNumCU;
+  const bool tall = !small && use_tall(M, N, nz);
   {
-    ProfScope ps(small ? kKGemmNNSmall : kKGemmNN, 2.0 * M * N * K,
+    ProfScope ps(small ? kKGemmNNSmall : tall ? kKGemmNNTall : kKGemmNN, 2.0 * M * N * K,
                  8.0 * (M * K + K * N + M * N * (beta != 0.0 ? 2 : 1)), s);
     double* pp = nz > 1 ? part : nullptr;
     if (small)
       launch_nn<Small>(X, ldx, W, ldw, Y, ldy, M, N, K, kc, nz, alpha, beta, pp, ldp, s);
+    else if (tall)
+      launch_nn<Tall>(X, ldx, W, ldw, Y, ldy, M, N, K, kc, nz, alpha, beta, pp, ldp, s);
     else
       launch_nn<Big>(X, ldx, W, ldw, Y, ldy, M, N, K, kc, nz, alpha, beta, pp, ldp, s);
   }
@@ -706,11 +726,14 @@ int downdate(double* R, int64_t ldr, const double* Qm, int64_t ldq, const double
              int64_t M, int64_t N, int64_t K, double* sq_part, int* sq_count, hipStream_t s) {
   if (M <= 0 || N <= 0) { if (sq_count) *sq_count = 0; return kOk; }
   if (!ld_fits(ldq) || !ld_fits(ldb)) return kEInval;
+  // 128 x 128 tiles, two workgroups per CU: the read-modify-write of R in
+  // one workgroup's epilogue overlaps the other's MFMA work (measured: the
+  // 256-row tile with one workgroup per CU is 16 % slower here)
   const dim3 grid(static_cast<unsigned>(cdiv(M, Big::BM)), static_cast<unsigned>(cdiv(N, Big::BN)));
   {
     ProfScope ps(kKDowndate, 2.0 * M * N * K, 8.0 * (2 * M * N + M * K + K * N), s);
-    hipLaunchKernelGGL(downdate_kernel<Big>, grid, dim3(NT), 0, s, R, ldr, Qm, ldq, B, ldb, M, N,
-                       K, sq_part, vec_ok(R, ldr), vec_ok(Qm, ldq) & vec_ok(B, ldb));
+    hipLaunchKernelGGL(downdate_kernel<Big>, grid, dim3(Big::NT), 0, s, R, ldr, Qm, ldq, B, ldb,
+                       M, N, K, sq_part, vec_ok(R, ldr), vec_ok(Qm, ldq) & vec_ok(B, ldb));
   }
   QB_HIP_TRY(hipGetLastError());
   if (sq_count) *sq_count = static_cast<int>(grid.x * grid.y);

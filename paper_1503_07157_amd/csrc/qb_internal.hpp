@@ -64,7 +64,7 @@ struct Arena {
 // performs.  Elapsed times are folded in when the counters are read.
 enum KernelId {
   kKSketch = 0, kKGemmNN, kKGemmTN, kKReduce, kKDowndate, kKChol, kKTrinv, kKNorm, kKCopy,
-  kKGemmNNLowp, kKGemmTNLowp, kKGemmNNSmall, kKGemmTNSmall, kKCount
+  kKGemmNNLowp, kKGemmTNLowp, kKGemmNNSmall, kKGemmTNSmall, kKGemmNNTall, kKCount
 };
 const char* kernel_name(int id);
 bool prof_enabled();
