@@ -179,3 +179,33 @@ def test_real_oracle_passes_the_single_pass_pins():
 def test_single_pass_mutations_are_caught(old, new):
     mod = mutant("randqb", old, new)
     assert not _single_pass_pins_hold(mod.randqb_pb)
+
+
+def _cpqr_pins_hold(mod) -> bool:
+    try:
+        Qt, R, perm = mod.pivoted_qr(np.array([[3.0, 1.0], [4.0, 2.0]]))
+        ok = list(perm) == [0, 1] and abs(R[0, 0] + 5.0) < 1e-14
+        B = np.random.default_rng(2800).standard_normal((40, 70))
+        Qt, R, perm = mod.pivoted_qr(B)
+        ok &= np.linalg.norm(B[:, perm] - Qt @ R) < 1e-13 * np.linalg.norm(B)
+        for j in range(40):
+            trail = np.sum(R[j:, j + 1:] ** 2, axis=0)
+            ok &= bool(np.all(R[j, j] ** 2 >= trail * (1 - 1e-12)))
+        return bool(ok)
+    except Exception:
+        return False
+
+
+def test_real_oracle_passes_the_cpqr_pins():
+    import oracle.postprocess as pp
+    assert _cpqr_pins_hold(pp)
+
+
+@pytest.mark.parametrize("old,new", [
+    ("norms = np.sum(W[j:, j:] * W[j:, j:], axis=0)",
+     "norms = np.sum(W[:, j:] * W[:, j:], axis=0)"),                    # norms over all rows
+    ("beta = -nrm if x[0] >= 0.0 else nrm", "beta = nrm if x[0] >= 0.0 else -nrm"),  # reflector sign
+    ("for j in reversed(range(steps)):", "for j in range(steps):"),     # wrong accumulation order
+])
+def test_cpqr_mutations_are_caught(old, new):
+    assert not _cpqr_pins_hold(mutant("postprocess", old, new))
