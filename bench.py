@@ -181,6 +181,54 @@ def skip_reorth_experiment():
                       "floor_single_orth": tau, "rows": rows}), flush=True)
 
 
+def post_experiment():
+    """Section 3.3 on the GPU: time the low-rank SVD and the partial pivoted
+    QR computed from the QB factors, for the 2000 x 1000 exp(-j/40) workload
+    (eps = 1e-6 ||A||) and the 10000 x 10000 j^-2 workload at eps = 1e-5
+    ||A||.  Prints one JSON line."""
+    import numpy as np
+    import torch
+    import paper_1503_07157_amd as qbmi
+    import synth
+
+    out = []
+    for name, eps_rel, P in (("exp40_2000x1000", 1e-6, 0), ("pow2_10000x10000", 1e-5, 1)):
+        wl = synth.workload(name)
+        if wl.m * wl.n > 4e7:
+            A = synth.workload_matrix_gpu(name)
+        else:
+            A = qbmi.colmajor(torch.from_numpy(np.ascontiguousarray(
+                synth.workload_matrix(name))).cuda())
+        nA = float(torch.linalg.norm(A))
+        res = qbmi.qb_factor(A, eps_rel * nA, wl.b, P, wl.seed_omega)
+        Q, B = res.Q, res.B
+        times = {}
+        for what, fn in (("svd", lambda: qbmi.svd(Q, B)), ("pivoted_qr", lambda: qbmi.pivoted_qr(Q, B))):
+            fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = fn()
+            torch.cuda.synchronize()
+            times[what] = time.perf_counter() - t0
+            if what == "svd":
+                U, S, V, sweeps = r
+                k = min(int((S > 1e-14 * S[0]).sum()), S.numel())
+                err = float(torch.linalg.norm(A - (U[:, :k] * S[:k]) @ V[:, :k].t())) / nA
+                times["svd_sweeps"] = sweeps
+                times["svd_rel_err"] = err
+            else:
+                Qh, R, perm = r
+                err = float(torch.linalg.norm(A[:, perm] - Qh @ R)) / nA
+                times["qr_rel_err"] = err
+        out.append({"workload": name, "eps_rel": eps_rel, "power_iters": P, "k": res.k,
+                    "n": wl.n, "m": wl.m, **times})
+        log(f"[bench] post {name}: k={res.k} svd {times['svd']*1e3:.1f} ms "
+            f"({times['svd_sweeps']} sweeps), pivoted qr {times['pivoted_qr']*1e3:.1f} ms")
+        del A, Q, B, res
+        torch.cuda.empty_cache()
+    print(json.dumps({"experiment": "post", "rows": out}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -192,7 +240,7 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-blocks", type=int, default=16)
-    ap.add_argument("--experiment", default=None, choices=["skip-reorth"],
+    ap.add_argument("--experiment", default=None, choices=["skip-reorth", "post"],
                     help="run the Section 6.4 comparison instead of the benchmark")
     ap.add_argument("--matrix", default="workload", choices=["workload", "gaussian"],
                     help="gaussian: i.i.d. N(0, 1/m) entries of the workload's shape instead of "
@@ -205,6 +253,9 @@ def main():
         sys.exit(2)
     if args.experiment == "skip-reorth":
         skip_reorth_experiment()
+        return
+    if args.experiment == "post":
+        post_experiment()
         return
 
     import torch

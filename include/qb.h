@@ -39,6 +39,9 @@ extern "C" {
 #define QB_RANK_EXHAUSTED   2   /* the residual is at the rounding level of
                                    the downdate, or k = min(m, n), or a
                                    block kept no column, before eps        */
+#define QB_NOT_CONVERGED    3   /* qb_svd: the Jacobi sweeps reached their
+                                   cap (60) before every column pair was
+                                   orthogonal to 1e-15; outputs valid      */
 #define QB_EINVAL          -1   /* invalid argument                        */
 #define QB_ENONFINITE      -2   /* A holds a NaN or an infinity            */
 #define QB_EWORKSPACE      -3   /* workspace NULL or smaller than required */
@@ -188,6 +191,37 @@ int qb_downdate(double* R, int64_t m, int64_t n, int64_t ldr,
 int qb_frob2(const double* X, int64_t m, int64_t n, int64_t ldx,
              double* out, int32_t* nonfinite,
              void* workspace, size_t ws_bytes, void* stream);
+
+/* ---- standard factorisations from Q B (Section 3.3) ------------------------
+ * Inputs: Q (m x k, orthonormal columns, ldq >= m) and B (k x n, ldb >= k)
+ * as produced by qb_factor, device, column-major; 1 <= k <= min(m, 4096).
+ * Outputs are caller-owned device arrays; workspaces come from the
+ * *_workspace_bytes calls (0 = invalid sizes), 256-byte aligned.  Errors:
+ * QB_EINVAL (sizes, leading dimensions, NULL), QB_EWORKSPACE, QB_EHIP. */
+
+/* Low-rank SVD (Section 3.3.1): Q B = U diag(S) V^T with U (m x k, ldu >= m)
+ * and V (n x k, ldv >= n) orthonormal and S (k) non-increasing.  The SVD of
+ * B is computed by one-sided Jacobi on B^T (high relative accuracy); a
+ * zero singular value gets a zero column in V.  *sweeps (HOST, may be NULL)
+ * receives the number of Jacobi sweeps.  Truncation to a rank is left to
+ * the caller (S is sorted).  Returns QB_OK or QB_NOT_CONVERGED. */
+size_t qb_svd_workspace_bytes(int64_t m, int64_t n, int64_t k);
+int qb_svd(const double* Q, int64_t m, int64_t k, int64_t ldq,
+           const double* B, int64_t n, int64_t ldb,
+           double* U, int64_t ldu, double* S, double* V, int64_t ldv,
+           int32_t* sweeps, void* workspace, size_t ws_bytes, void* stream);
+
+/* Partial column-pivoted QR (Section 3.3.2): A P ~ Q B P = Qhat R with
+ * Qhat = Q Q_tilde (m x k, ldqh >= m), R (k x n upper trapezoidal,
+ * ldr >= k) and perm (n, device int64): column j of Qhat R is column
+ * perm[j] of Q B.  Householder QR of B with column pivoting: column norms
+ * recomputed every step, ties to the smallest index, R_jj = -sign(pivot
+ * entry) * norm. */
+size_t qb_pivoted_qr_workspace_bytes(int64_t m, int64_t n, int64_t k);
+int qb_pivoted_qr(const double* Q, int64_t m, int64_t k, int64_t ldq,
+                  const double* B, int64_t n, int64_t ldb,
+                  double* Qhat, int64_t ldqh, double* R, int64_t ldr, int64_t* perm,
+                  void* workspace, size_t ws_bytes, void* stream);
 
 /* ---- measurement ---------------------------------------------------------
  * Optional per-kernel timing: when enabled, every kernel launch of the

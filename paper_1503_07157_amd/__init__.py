@@ -10,9 +10,11 @@ from .qb import (  # noqa: F401
     downdate,
     frob2,
     orth,
+    pivoted_qr,
     project,
     qb_factor,
     sample_product,
     sketch,
+    svd,
     workspace_bytes,
 )

@@ -24,6 +24,7 @@ c_size = ctypes.c_size_t
 QB_OK = 0
 QB_KMAX = 1
 QB_RANK_EXHAUSTED = 2
+QB_NOT_CONVERGED = 3
 QB_EINVAL = -1
 QB_ENONFINITE = -2
 QB_EWORKSPACE = -3
@@ -77,6 +78,12 @@ SIGNATURES = {
                                    ctypes.POINTER(c_dbl), c_vp, c_size, c_vp]),
     "qb_frob2": (ctypes.c_int, [c_vp, c_i64, c_i64, c_i64, ctypes.POINTER(c_dbl),
                                 ctypes.POINTER(c_i32), c_vp, c_size, c_vp]),
+    "qb_svd_workspace_bytes": (c_size, [c_i64, c_i64, c_i64]),
+    "qb_svd": (ctypes.c_int, [c_vp, c_i64, c_i64, c_i64, c_vp, c_i64, c_i64, c_vp, c_i64, c_vp,
+                              c_vp, c_i64, ctypes.POINTER(c_i32), c_vp, c_size, c_vp]),
+    "qb_pivoted_qr_workspace_bytes": (c_size, [c_i64, c_i64, c_i64]),
+    "qb_pivoted_qr": (ctypes.c_int, [c_vp, c_i64, c_i64, c_i64, c_vp, c_i64, c_i64, c_vp, c_i64,
+                                     c_vp, c_i64, c_vp, c_vp, c_size, c_vp]),
     "qb_profile_enable": (ctypes.c_int, [ctypes.c_int]),
     "qb_profile_count": (c_i32, []),
     "qb_profile_name": (ctypes.c_char_p, [c_i32]),

@@ -183,6 +183,7 @@ const char* qb_status_string(int status) {
     case QB_OK: return "QB_OK";
     case QB_KMAX: return "QB_KMAX: k reached kmax before the tolerance";
     case QB_RANK_EXHAUSTED: return "QB_RANK_EXHAUSTED: residual at rounding level or full rank";
+    case QB_NOT_CONVERGED: return "QB_NOT_CONVERGED: Jacobi sweeps reached their cap";
     case QB_EINVAL: return "QB_EINVAL: invalid argument";
     case QB_ENONFINITE: return "QB_ENONFINITE: input holds NaN or Inf";
     case QB_EWORKSPACE: return "QB_EWORKSPACE: workspace missing or too small";

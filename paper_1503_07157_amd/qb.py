@@ -217,3 +217,50 @@ def frob2(X: torch.Tensor):
     _check(lib.qb_frob2(X.data_ptr(), m, n, ldx, ctypes.byref(out), ctypes.byref(bad),
                         _aligned_ptr(ws), need, _stream(X.device)), "qb_frob2")
     return float(out.value), bool(bad.value)
+
+
+def svd(Q: torch.Tensor, B: torch.Tensor):
+    """Low-rank SVD of Q B (Section 3.3.1): returns (U, S, V, sweeps) with
+    Q B = U diag(S) V^T, S non-increasing."""
+    lib = _lib.load()
+    ldq, ldb = _ld(Q, "Q"), _ld(B, "B")
+    m, k = Q.shape
+    k2, n = B.shape
+    if k2 != k:
+        raise ValueError("Q and B do not conform")
+    dev = Q.device
+    U = torch.empty((k, m), dtype=torch.float64, device=dev).t()
+    V = torch.empty((k, n), dtype=torch.float64, device=dev).t()
+    S = torch.empty(k, dtype=torch.float64, device=dev)
+    need = int(lib.qb_svd_workspace_bytes(m, n, k))
+    if need == 0:
+        raise QBError(_lib.QB_EINVAL, "qb_svd_workspace_bytes")
+    ws = _workspace(need, dev)
+    sweeps = ctypes.c_int32(0)
+    _check(lib.qb_svd(Q.data_ptr(), m, k, ldq, B.data_ptr(), n, ldb, U.data_ptr(), m,
+                      S.data_ptr(), V.data_ptr(), n, ctypes.byref(sweeps), _aligned_ptr(ws),
+                      need, _stream(dev)), "qb_svd")
+    return U, S, V, int(sweeps.value)
+
+
+def pivoted_qr(Q: torch.Tensor, B: torch.Tensor):
+    """Partial column-pivoted QR from Q B (Section 3.3.2): returns
+    (Qhat, R, perm) with (Q B)[:, perm] = Qhat R."""
+    lib = _lib.load()
+    ldq, ldb = _ld(Q, "Q"), _ld(B, "B")
+    m, k = Q.shape
+    k2, n = B.shape
+    if k2 != k:
+        raise ValueError("Q and B do not conform")
+    dev = Q.device
+    Qh = torch.empty((k, m), dtype=torch.float64, device=dev).t()
+    R = torch.empty((n, k), dtype=torch.float64, device=dev).t()
+    perm = torch.empty(n, dtype=torch.int64, device=dev)
+    need = int(lib.qb_pivoted_qr_workspace_bytes(m, n, k))
+    if need == 0:
+        raise QBError(_lib.QB_EINVAL, "qb_pivoted_qr_workspace_bytes")
+    ws = _workspace(need, dev)
+    _check(lib.qb_pivoted_qr(Q.data_ptr(), m, k, ldq, B.data_ptr(), n, ldb, Qh.data_ptr(), m,
+                             R.data_ptr(), k, perm.data_ptr(), _aligned_ptr(ws), need,
+                             _stream(dev)), "qb_pivoted_qr")
+    return Qh, R, perm
