@@ -223,6 +223,43 @@ int qb_pivoted_qr(const double* Q, int64_t m, int64_t k, int64_t ldq,
                   double* Qhat, int64_t ldqh, double* R, int64_t ldr, int64_t* perm,
                   void* workspace, size_t ws_bytes, void* stream);
 
+/* ---- batched QB ------------------------------------------------------------
+ * Many independent factorisations (Figure 4, P = 0) advanced together: each
+ * step of the block loop is one launch over every problem still active, and
+ * each problem stops by the rule of qb_factor on its own.  Inputs are float
+ * (the storage of the batched workload); every stored value and product is
+ * float64, so each problem follows the float64 qb_factor.  Callers that
+ * cannot afford one float64 copy of every input in the workspace should
+ * split the batch. */
+typedef struct qb_problem {
+  /* inputs */
+  const float* A;         /* device, column-major, m x n, lda >= m          */
+  int64_t m, n, lda;
+  double eps;             /* absolute Frobenius tolerance                    */
+  uint64_t seed;          /* sketch seed (the Philox key of qb_sketch)       */
+  int64_t kmax;           /* cap on k, < 0 for min(m, n)                     */
+  double* Q;              /* device, m x kmax, ldq >= m (float64)            */
+  int64_t ldq;
+  double* B;              /* device, kmax x n, ldb >= kmax (float64)         */
+  int64_t ldb;
+  int32_t b;              /* block size, 1 <= b <= 64                        */
+  /* outputs */
+  int32_t status;         /* as qb_factor; QB_ENONFINITE for a NaN or Inf    */
+  int32_t stop_reason;    /* QB_STOP_*                                       */
+  int32_t blocks;
+  int64_t k;
+  double normA2, resid2;  /* ||A||_F^2 and the final ||A - QB||_F^2         */
+} qb_problem;
+
+/* Workspace for a batch (0 when any problem is invalid): one float64 copy
+ * of each A plus O((m + n) b) per problem. */
+size_t qb_factor_batched_workspace_bytes(const qb_problem* probs, int32_t count);
+/* probs: HOST array; every problem's outputs are written there.  Returns
+ * QB_OK when the batch ran (see each problem's status), QB_EINVAL when any
+ * problem is invalid (nothing runs), QB_EWORKSPACE or QB_EHIP. */
+int qb_factor_batched(qb_problem* probs, int32_t count, void* workspace, size_t ws_bytes,
+                      void* stream);
+
 /* ---- measurement ---------------------------------------------------------
  * Optional per-kernel timing: when enabled, every kernel launch of the
  * library is bracketed by two HIP events on the stream it runs on and

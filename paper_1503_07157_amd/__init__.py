@@ -13,6 +13,7 @@ from .qb import (  # noqa: F401
     pivoted_qr,
     project,
     qb_factor,
+    qb_factor_batched,
     sample_product,
     sketch,
     svd,

@@ -56,6 +56,29 @@ class QBInfo(ctypes.Structure):
     ]
 
 
+class QBProblem(ctypes.Structure):
+    _fields_ = [
+        ("A", c_vp),
+        ("m", c_i64),
+        ("n", c_i64),
+        ("lda", c_i64),
+        ("eps", c_dbl),
+        ("seed", ctypes.c_uint64),
+        ("kmax", c_i64),
+        ("Q", c_vp),
+        ("ldq", c_i64),
+        ("B", c_vp),
+        ("ldb", c_i64),
+        ("b", c_i32),
+        ("status", c_i32),
+        ("stop_reason", c_i32),
+        ("blocks", c_i32),
+        ("k", c_i64),
+        ("normA2", c_dbl),
+        ("resid2", c_dbl),
+    ]
+
+
 # name -> (restype, argtypes)
 SIGNATURES = {
     "qb_workspace_bytes": (c_size, [c_i64, c_i64, c_i32, c_i64, c_u32]),
@@ -84,6 +107,8 @@ SIGNATURES = {
     "qb_pivoted_qr_workspace_bytes": (c_size, [c_i64, c_i64, c_i64]),
     "qb_pivoted_qr": (ctypes.c_int, [c_vp, c_i64, c_i64, c_i64, c_vp, c_i64, c_i64, c_vp, c_i64,
                                      c_vp, c_i64, c_vp, c_vp, c_size, c_vp]),
+    "qb_factor_batched_workspace_bytes": (c_size, [ctypes.POINTER(QBProblem), c_i32]),
+    "qb_factor_batched": (ctypes.c_int, [ctypes.POINTER(QBProblem), c_i32, c_vp, c_size, c_vp]),
     "qb_profile_enable": (ctypes.c_int, [ctypes.c_int]),
     "qb_profile_count": (c_i32, []),
     "qb_profile_name": (ctypes.c_char_p, [c_i32]),

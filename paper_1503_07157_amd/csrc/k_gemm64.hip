@@ -304,6 +304,10 @@ __device__ __forceinline__ int acc_col(int j) {
   return (wave / S::WGM) * S::WN + 16 * j + (lane & 15);
 }
 
+__device__ __forceinline__ bool vec_ok_dev(const double* p, int64_t ld) {
+  return (reinterpret_cast<uintptr_t>(p) & 15) == 0 && (ld & 1) == 0;
+}
+
 // four consecutive rows [row0, row0 + 4) of column col of X (ld); vec: X and
 // ld allow 16-byte accesses at even rows
 __device__ __forceinline__ d4 load4(const double* __restrict__ X, int64_t ld, int64_t row0,
@@ -571,6 +575,61 @@ __global__ __launch_bounds__(S::NT, S::OCC) void downdate_kernel(double* __restr
   if (threadIdx.x == 0) sq_part[blockIdx.x + static_cast<int64_t>(blockIdx.y) * gridDim.x] = tot;
 }
 
+// ---- batched products ------------------------------------------------------
+// Workgroup -> (problem, tile) by binary search over the problems' first
+// workgroup indices; then the same tile loop and epilogues as above.
+template <class S, int OP>
+__global__ __launch_bounds__(S::NT, S::OCC) void gemm_batched_kernel(
+    const BatchGemm* __restrict__ desc, int count) {
+  __shared__ __attribute__((aligned(16))) double As[2 * S::A_LDS];
+  __shared__ __attribute__((aligned(16))) double Bs[2 * S::B_LDS];
+  __shared__ double red[S::NT / 64];
+  const int64_t blk = blockIdx.x;
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {  // last problem with tile0 <= blk
+    const int mid = (lo + hi + 1) >> 1;
+    if (desc[mid].tile0 <= blk) lo = mid;
+    else hi = mid - 1;
+  }
+  const BatchGemm g = desc[lo];
+  const int64_t t = blk - g.tile0;
+  const int64_t m0 = (t % g.tiles_m) * S::BM;
+  const int64_t n0 = (t / g.tiles_m) * S::BN;
+  const int64_t M = g.M, N = g.N, K = g.K;
+  d4 acc[S::IB][S::JB];
+  mma_loop<S, OP == kBatchTN>(g.A, g.lda, g.B, g.ldb, m0, n0, M, N, 0, K, g.vec != 0, As, Bs,
+                              acc);
+  const bool vc = vec_ok_dev(g.C, g.ldc);
+  double sq = 0.0;
+#pragma unroll
+  for (int i = 0; i < S::IB; ++i) {
+    const int64_t row0 = m0 + acc_row0<S>(i);
+    d4 old[S::JB];
+#pragma unroll
+    for (int j = 0; j < S::JB; ++j) {
+      const bool need = (OP == kBatchDD) || (OP == kBatchNN && g.beta != 0.0);
+      old[j] = need ? load4(g.C, g.ldc, row0, n0 + acc_col<S>(j), M, N, vc)
+                    : (d4){0.0, 0.0, 0.0, 0.0};
+    }
+#pragma unroll
+    for (int j = 0; j < S::JB; ++j) {
+      const int64_t col = n0 + acc_col<S>(j);
+      d4 v;
+      if (OP == kBatchNN) v = g.alpha * acc[i][j] + g.beta * old[j];
+      else if (OP == kBatchTN) v = acc[i][j];
+      else v = old[j] - acc[i][j];
+      store4(g.C, g.ldc, row0, col, M, N, vc, v);
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (row0 + r < M && col < N) sq += v[r] * v[r];
+    }
+  }
+  if (OP != kBatchNN && g.sq != nullptr) {
+    const double tot = block_sum(sq, red);
+    if (threadIdx.x == 0) g.sq[t] = tot;
+  }
+}
+
 int64_t part_ld(int64_t M) { return (M + 1) & ~int64_t(1); }
 
 int64_t kchunk_for(int64_t K, int split) {
@@ -737,6 +796,22 @@ int downdate(double* R, int64_t ldr, const double* Qm, int64_t ldq, const double
   }
   QB_HIP_TRY(hipGetLastError());
   if (sq_count) *sq_count = static_cast<int>(grid.x * grid.y);
+  return kOk;
+}
+
+int gemm_batched(int op, const BatchGemm* desc, int count, int64_t total_tiles, hipStream_t s) {
+  if (count <= 0 || total_tiles <= 0) return kOk;
+  using S = Small;
+  static_assert(S::BM == kBatchTile && S::BN == kBatchTile, "batched tile");
+  const dim3 grid(static_cast<unsigned>(total_tiles));
+  ProfScope ps(kKGemmBatched, 0.0, 0.0, s);
+  if (op == kBatchNN)
+    hipLaunchKernelGGL((gemm_batched_kernel<S, kBatchNN>), grid, dim3(S::NT), 0, s, desc, count);
+  else if (op == kBatchTN)
+    hipLaunchKernelGGL((gemm_batched_kernel<S, kBatchTN>), grid, dim3(S::NT), 0, s, desc, count);
+  else
+    hipLaunchKernelGGL((gemm_batched_kernel<S, kBatchDD>), grid, dim3(S::NT), 0, s, desc, count);
+  QB_HIP_TRY(hipGetLastError());
   return kOk;
 }
 

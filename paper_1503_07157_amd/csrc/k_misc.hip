@@ -56,11 +56,10 @@ __global__ __launch_bounds__(kSumThreads) void sumsq_kernel(const double* __rest
 
 // one workgroup: out[0] = hi, out[1] = lo of the sum of part[0..count);
 // iflag[0] = OR of flags[0..count) when flags is non-null
-__global__ __launch_bounds__(kSumThreads) void sum_partials_kernel(const double* __restrict__ part,
-                                                                   int count,
-                                                                   const int* __restrict__ flags,
-                                                                   double* __restrict__ out,
-                                                                   int* __restrict__ iflag) {
+__device__ __forceinline__ void sum_partials_body(const double* __restrict__ part, int count,
+                                                  const int* __restrict__ flags,
+                                                  double* __restrict__ out,
+                                                  int* __restrict__ iflag) {
   __shared__ double hs[kSumThreads], ls[kSumThreads];
   __shared__ int fs[kSumThreads];
   double hi = 0.0, lo = 0.0;
@@ -92,6 +91,68 @@ __global__ __launch_bounds__(kSumThreads) void sum_partials_kernel(const double*
     out[0] = s;
     out[1] = e;
     if (iflag) iflag[0] = fs[0];
+  }
+}
+
+__global__ __launch_bounds__(kSumThreads) void sum_partials_kernel(const double* __restrict__ part,
+                                                                   int count,
+                                                                   const int* __restrict__ flags,
+                                                                   double* __restrict__ out,
+                                                                   int* __restrict__ iflag) {
+  sum_partials_body(part, count, flags, out, iflag);
+}
+
+// one workgroup per problem of a batch
+__global__ __launch_bounds__(kSumThreads) void sum_batched_kernel(const BatchSum* __restrict__ d) {
+  const BatchSum b = d[blockIdx.x];
+  sum_partials_body(b.part, b.count, b.flags, b.out, b.iflag);
+}
+
+constexpr int kConvPer = 8;  // elements per thread in convert_batched_kernel
+
+// R = double(A) for a batch of float matrices; per-workgroup sums of
+// squares (of the converted values) and non-finite flags
+__global__ __launch_bounds__(kSumThreads) void convert_batched_kernel(
+    const BatchConvert* __restrict__ desc, int count) {
+  __shared__ double red[kSumThreads / 64];
+  __shared__ int fred[kSumThreads / 64];
+  const int64_t blk = blockIdx.x;
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (desc[mid].block0 <= blk) lo = mid;
+    else hi = mid - 1;
+  }
+  const BatchConvert c = desc[lo];
+  const int64_t lb = blk - c.block0;
+  const int64_t total = c.m * c.n;
+  double s = 0.0;
+  int bad = 0;
+#pragma unroll
+  for (int q = 0; q < kConvPer; ++q) {
+    const int64_t e = (lb * kConvPer + q) * kSumThreads + threadIdx.x;
+    if (e < total) {
+      const int64_t i = e % c.m, j = e / c.m;
+      const double v = static_cast<double>(c.A[i + j * c.lda]);
+      c.R[i + j * c.ldr] = v;
+      bad |= !isfinite(v);
+      s += v * v;
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    s += __shfl_xor(s, off);
+    bad |= __shfl_xor(bad, off);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) { red[wave] = s; fred[wave] = bad; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    int f = 0;
+    for (int w = 0; w < kSumThreads / 64; ++w) { t += red[w]; f |= fred[w]; }
+    c.part[lb] = t;
+    c.flags[lb] = f;
   }
 }
 
@@ -147,6 +208,28 @@ int sum_partials_ex(const double* part, int count, const int* flags, double* out
     hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(kSumThreads), 0, s, part, count, flags,
                        out, out_flag);
   }
+  QB_HIP_TRY(hipGetLastError());
+  return kOk;
+}
+
+int64_t convert_blocks(int64_t m, int64_t n) {
+  return cdiv(m * n, static_cast<int64_t>(kSumThreads) * kConvPer);
+}
+
+int convert_batched(const BatchConvert* desc, int count, int64_t total_blocks, hipStream_t s) {
+  if (count <= 0 || total_blocks <= 0) return kOk;
+  ProfScope ps(kKBatchMisc, 0.0, 0.0, s);
+  hipLaunchKernelGGL(convert_batched_kernel, dim3(static_cast<unsigned>(total_blocks)),
+                     dim3(kSumThreads), 0, s, desc, count);
+  QB_HIP_TRY(hipGetLastError());
+  return kOk;
+}
+
+int sum_batched(const BatchSum* desc, int count, hipStream_t s) {
+  if (count <= 0) return kOk;
+  ProfScope ps(kKBatchMisc, 0.0, 0.0, s);
+  hipLaunchKernelGGL(sum_batched_kernel, dim3(static_cast<unsigned>(count)), dim3(kSumThreads), 0,
+                     s, desc);
   QB_HIP_TRY(hipGetLastError());
   return kOk;
 }

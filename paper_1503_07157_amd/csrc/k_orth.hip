@@ -378,9 +378,9 @@ __device__ __forceinline__ void lds_block16(double* M, int ra, int ka, int kb, i
 }
 
 template <int WMAX>
-__global__ __launch_bounds__(512) void chol_inv_lds_kernel(const double* __restrict__ G, int w,
-                                                           int* __restrict__ kept,
-                                                           double* __restrict__ Tinv) {
+__device__ __forceinline__ void chol_inv_lds_body(const double* __restrict__ G, int w,
+                                                  int* __restrict__ kept,
+                                                  double* __restrict__ Tinv) {
   using L = LdsInvShape<WMAX>;
   constexpr int TS = L::TS, NW = L::NW;
   __shared__ double Ts[WMAX * TS];
@@ -465,6 +465,20 @@ __global__ __launch_bounds__(512) void chol_inv_lds_kernel(const double* __restr
   }
   for (int i = threadIdx.x; i < wk; i += blockDim.x) kept[1 + i] = klist[i];
   if (threadIdx.x == 0) kept[0] = wk;
+}
+
+template <int WMAX>
+__global__ __launch_bounds__(512) void chol_inv_lds_kernel(const double* __restrict__ G, int w,
+                                                           int* __restrict__ kept,
+                                                           double* __restrict__ Tinv) {
+  chol_inv_lds_body<WMAX>(G, w, kept, Tinv);
+}
+
+// one workgroup per problem of a batch
+template <int WMAX>
+__global__ __launch_bounds__(512) void chol_inv_batched_kernel(const BatchChol* __restrict__ desc) {
+  const BatchChol c = desc[blockIdx.x];
+  chol_inv_lds_body<WMAX>(c.G, c.w, c.kept, c.Tinv);
 }
 
 // Column `a` of the inverse of the kept part Tc = T[kept][:, kept]; written
@@ -571,6 +585,15 @@ int cholqr_pass(const double* X, int64_t ldx, double* Qout, int64_t ldqo, int64_
 }
 
 }  // namespace
+
+int chol_inv_batched(const BatchChol* desc, int count, hipStream_t s) {
+  if (count <= 0) return kOk;
+  ProfScope ps(kKCholBatched, 0.0, 0.0, s);
+  hipLaunchKernelGGL(chol_inv_batched_kernel<64>, dim3(static_cast<unsigned>(count)),
+                     dim3(LdsInvShape<64>::THREADS), 0, s, desc);
+  QB_HIP_TRY(hipGetLastError());
+  return kOk;
+}
 
 size_t orth_work_bytes(int64_t m, int w) {
   Arena a{nullptr, 0, 0};

@@ -116,14 +116,10 @@ __device__ __forceinline__ void sincos_2pi_fixed(double u, double* cs, double* s
   }
 }
 
-// one thread per (row pair t, column jj)
-__global__ __launch_bounds__(256) void sketch_kernel(uint32_t k0, uint32_t k1, int64_t n,
-                                                     int64_t col0, double* __restrict__ out,
-                                                     int64_t ld) {
-  const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  const int64_t jj = blockIdx.y;
-  const int64_t npairs = (n + 1) / 2;
-  if (t >= npairs) return;
+// entries (2t, jj) and (2t + 1, jj) of columns [col0, col0 + w) of the sketch
+__device__ __forceinline__ void sketch_pair(uint32_t k0, uint32_t k1, int64_t n, int64_t col0,
+                                            double* __restrict__ out, int64_t ld, int64_t t,
+                                            int64_t jj) {
   const uint32_t j = static_cast<uint32_t>(col0 + jj);
   const Words x = philox4x32_10(static_cast<uint32_t>(t), j, 0u, 0u, k0, k1);
   const double u1 = unit53(x.x0, x.x1);
@@ -136,7 +132,48 @@ __global__ __launch_bounds__(256) void sketch_kernel(uint32_t k0, uint32_t k1, i
   if (2 * t + 1 < n) col[2 * t + 1] = rho * s;
 }
 
+// one thread per (row pair t, column jj)
+__global__ __launch_bounds__(256) void sketch_kernel(uint32_t k0, uint32_t k1, int64_t n,
+                                                     int64_t col0, double* __restrict__ out,
+                                                     int64_t ld) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t npairs = (n + 1) / 2;
+  if (t >= npairs) return;
+  sketch_pair(k0, k1, n, col0, out, ld, t, blockIdx.y);
+}
+
+// batch: workgroup -> (problem, pair block, column)
+__global__ __launch_bounds__(256) void sketch_batched_kernel(const BatchSketch* __restrict__ desc,
+                                                             int count) {
+  const int64_t blk = blockIdx.x;
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (desc[mid].block0 <= blk) lo = mid;
+    else hi = mid - 1;
+  }
+  const BatchSketch d = desc[lo];
+  const int64_t npairs = (d.n + 1) / 2;
+  const int64_t nb = (npairs + 255) / 256;
+  const int64_t lb = blk - d.block0;
+  const int64_t t = (lb % nb) * 256 + threadIdx.x;
+  if (t >= npairs) return;
+  sketch_pair(static_cast<uint32_t>(d.seed), static_cast<uint32_t>(d.seed >> 32), d.n, d.col0,
+              d.out, d.ld, t, lb / nb);
+}
+
 }  // namespace
+
+int64_t sketch_blocks(int64_t n, int w) { return ((n + 1) / 2 + 255) / 256 * w; }
+
+int sketch_batched(const BatchSketch* desc, int count, int64_t total_blocks, hipStream_t s) {
+  if (count <= 0 || total_blocks <= 0) return kOk;
+  ProfScope ps(kKSketch, 0.0, 0.0, s);
+  hipLaunchKernelGGL(sketch_batched_kernel, dim3(static_cast<unsigned>(total_blocks)), dim3(256),
+                     0, s, desc, count);
+  QB_HIP_TRY(hipGetLastError());
+  return kOk;
+}
 
 int launch_sketch(uint64_t seed, int64_t n, int64_t col0, int w, double* out, int64_t ld,
                   hipStream_t s) {

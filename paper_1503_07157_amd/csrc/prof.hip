@@ -60,7 +60,8 @@ int collect_locked() {
 
 const char* kNames[kKCount] = {"sketch", "gemm_nn", "gemm_tn", "reduce", "downdate",
                                "chol_drop", "trinv", "norm", "copy", "gemm_nn_lowp",
-                               "gemm_tn_lowp", "gemm_nn_64", "gemm_tn_64", "gemm_nn_256"};
+                               "gemm_tn_lowp", "gemm_nn_64", "gemm_tn_64", "gemm_nn_256",
+                               "gemm_batched", "chol_batched", "batch_misc"};
 
 }  // namespace
 

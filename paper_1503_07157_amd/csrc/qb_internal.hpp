@@ -64,7 +64,7 @@ struct Arena {
 // performs.  Elapsed times are folded in when the counters are read.
 enum KernelId {
   kKSketch = 0, kKGemmNN, kKGemmTN, kKReduce, kKDowndate, kKChol, kKTrinv, kKNorm, kKCopy,
-  kKGemmNNLowp, kKGemmTNLowp, kKGemmNNSmall, kKGemmTNSmall, kKGemmNNTall, kKCount
+  kKGemmNNLowp, kKGemmTNLowp, kKGemmNNSmall, kKGemmTNSmall, kKGemmNNTall, kKGemmBatched, kKCholBatched, kKBatchMisc, kKCount
 };
 const char* kernel_name(int id);
 bool prof_enabled();
@@ -134,6 +134,66 @@ int zero_matrix(double* Y, int64_t ldy, int64_t M, int64_t N, hipStream_t s);
 
 // orth: CholQR2 with dropping.  X (m x w, ldx) -> Q (m x w, ldq), kept
 // columns first, zero columns after; *kept_dev receives the count.
+// ---- batched forms (many independent problems in one launch) -------------
+// One problem of a batched product.  op NN: C(M x N) = alpha A(M x K) B(K x N)
+// + beta C; op TN: C(M x N) = A(K x M)^T B(K x N) (sq: per-tile sums of
+// squares of C, or null); op DD: C(M x N) -= A(M x K) B(K x N) with per-tile
+// sums of squares of the updated C into sq.  Workgroups [tile0, tile0 +
+// tiles_m * tiles_n) of the launch belong to this problem.
+struct BatchGemm {
+  const double* A;
+  const double* B;
+  double* C;
+  double* sq;
+  int64_t lda, ldb, ldc;
+  int64_t tile0;
+  int32_t M, N, K;
+  int32_t tiles_m, tiles_n;
+  int32_t vec;  // A and B 16-byte aligned with even leading dimensions
+  double alpha, beta;
+};
+enum { kBatchNN = 0, kBatchTN = 1, kBatchDD = 2 };
+constexpr int kBatchTile = 64;  // batched products use 64 x 64 output tiles
+int gemm_batched(int op, const BatchGemm* desc, int count, int64_t total_tiles, hipStream_t s);
+
+struct BatchChol {  // Cholesky with dropping + inverse of one w x w Gram matrix
+  const double* G;
+  int* kept;
+  double* Tinv;
+  int32_t w;
+};
+int chol_inv_batched(const BatchChol* desc, int count, hipStream_t s);  // w <= 64
+
+struct BatchSketch {  // columns [col0, col0 + w) of the n x inf sketch of seed
+  uint64_t seed;
+  int64_t n, col0, ld;
+  double* out;
+  int64_t block0;
+  int32_t w;
+};
+int sketch_batched(const BatchSketch* desc, int count, int64_t total_blocks, hipStream_t s);
+int64_t sketch_blocks(int64_t n, int w);
+
+struct BatchConvert {  // R = double(A) (A float, m x n) with sums of squares and
+  const float* A;      // non-finite flags per workgroup
+  double* R;
+  double* part;
+  int* flags;
+  int64_t lda, ldr, m, n;
+  int64_t block0;
+};
+int convert_batched(const BatchConvert* desc, int count, int64_t total_blocks, hipStream_t s);
+int64_t convert_blocks(int64_t m, int64_t n);
+
+struct BatchSum {  // out[0..1] = compensated sum of part[0..count) (hi, lo);
+  const double* part;  // iflag = OR of flags[0..count) when flags is set
+  const int* flags;
+  double* out;
+  int* iflag;
+  int32_t count;
+};
+int sum_batched(const BatchSum* desc, int count, hipStream_t s);
+
 struct OrthWork {
   double* gram;      // w x w
   double* tfull;     // w x w

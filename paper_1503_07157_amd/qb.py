@@ -14,7 +14,7 @@ from dataclasses import dataclass, field
 import torch
 
 from . import _lib
-from ._lib import (QBError, QBInfo, QB_BGEMM, QB_SAMPLE, QB_OVERWRITE_A, QB_POWER_NO_ORTH,
+from ._lib import (QBError, QBInfo, QBProblem, QB_BGEMM, QB_SAMPLE, QB_OVERWRITE_A, QB_POWER_NO_ORTH,
                    QB_SINGLE_BLOCK, QB_STOP)
 
 
@@ -32,9 +32,9 @@ def colmajor(x: torch.Tensor) -> torch.Tensor:
     return out
 
 
-def _ld(x: torch.Tensor, name: str) -> int:
-    if x.dtype != torch.float64:
-        raise TypeError(f"{name} must be float64")
+def _ld(x: torch.Tensor, name: str, dtype=torch.float64) -> int:
+    if x.dtype != dtype:
+        raise TypeError(f"{name} must be {str(dtype).replace('torch.', '')}")
     if not x.is_cuda:
         raise TypeError(f"{name} must be a device tensor")
     if x.dim() != 2:
@@ -264,3 +264,44 @@ def pivoted_qr(Q: torch.Tensor, B: torch.Tensor):
                              R.data_ptr(), k, perm.data_ptr(), _aligned_ptr(ws), need,
                              _stream(dev)), "qb_pivoted_qr")
     return Qh, R, perm
+
+
+def qb_factor_batched(As, eps, bs, seeds, kmax=None):
+    """Batched QB of the float32 column-major device matrices As (list):
+    eps, bs, seeds per problem (lists).  Returns a list of QBResult (no
+    trace), each with its own status."""
+    lib = _lib.load()
+    count = len(As)
+    probs = (QBProblem * count)()
+    keep = []
+    for i, A in enumerate(As):
+        if A.dtype != torch.float32:
+            raise ValueError("qb_factor_batched takes float32 matrices")
+        lda = _ld(A, "A", torch.float32)
+        m, n = A.shape
+        r = min(m, n)
+        kc = r if kmax is None else int(kmax[i])
+        Q = torch.empty((max(kc, 1), m), dtype=torch.float64, device=A.device).t()
+        B = torch.empty((n, max(kc, 1)), dtype=torch.float64, device=A.device).t()
+        keep.append((Q, B))
+        p = probs[i]
+        p.A, p.m, p.n, p.lda = A.data_ptr(), m, n, lda
+        p.eps, p.seed, p.kmax = float(eps[i]), int(seeds[i]) & 0xFFFFFFFFFFFFFFFF, kc
+        p.Q, p.ldq, p.B, p.ldb = Q.data_ptr(), _ld(Q, "Q"), B.data_ptr(), _ld(B, "B")
+        p.b = int(bs[i])
+    need = int(lib.qb_factor_batched_workspace_bytes(probs, count))
+    if need == 0:
+        raise QBError(_lib.QB_EINVAL, "qb_factor_batched_workspace_bytes")
+    ws = _workspace(need, As[0].device)
+    _check(lib.qb_factor_batched(probs, count, _aligned_ptr(ws), need, _stream(As[0].device)),
+           "qb_factor_batched")
+    out = []
+    for i in range(count):
+        p = probs[i]
+        Q, B = keep[i]
+        kk = int(p.k) if p.status >= 0 else 0
+        out.append(QBResult(Q=Q[:, :kk], B=B[:kk, :], k=kk, status=int(p.status),
+                            stop_reason=QB_STOP.get(p.stop_reason, str(p.stop_reason)),
+                            normA2=p.normA2, indicator=float("nan"), resid2=p.resid2,
+                            blocks=int(p.blocks), widths=[], E=[], D=[], R=None))
+    return out

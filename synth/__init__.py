@@ -19,4 +19,8 @@ from .matrices import (  # noqa: F401
     workload,
     workload_matrix,
     workload_matrix_gpu,
+    BatchSpec,
+    batch_specs,
+    batch_singular_values,
+    batch_matrix,
 )

@@ -178,3 +178,42 @@ def workload_matrix_gpu(name: str, device="cuda"):
     at = v @ u.t()
     del u, v
     return at.t()
+
+
+# ---- batched workload: many matrices of uneven sizes ------------------------
+@dataclass(frozen=True)
+class BatchSpec:
+    m: int
+    n: int
+    r: float          # singular values s_j = r^j, j = 1 .. min(m, n)
+    b: int
+    seed_u: int
+    seed_v: int
+    seed_omega: int
+
+
+def batch_specs(count: int = 512, seed: int = 4242, m_range=(256, 4096), n_max: int = 2048,
+                r_range=(0.9, 0.995), blocks=(16, 32, 64)):
+    """Sizes and spectra of a batch: m uniform in m_range, n uniform in
+    [128, min(m, n_max)] (or [m/2, m] when m < 128), s_j = r^j with r
+    uniform in r_range, b drawn from `blocks`."""
+    g = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        m = int(g.integers(m_range[0], m_range[1] + 1))
+        lo = min(128, m)
+        n = int(g.integers(lo, min(m, n_max) + 1))
+        r = float(g.uniform(*r_range))
+        b = int(g.choice(blocks))
+        out.append(BatchSpec(m, n, r, b, seed + 3 * i + 1, seed + 3 * i + 2, seed + 3 * i + 3))
+    return out
+
+
+def batch_singular_values(sp: BatchSpec) -> np.ndarray:
+    return sp.r ** np.arange(1, min(sp.m, sp.n) + 1, dtype=np.float64)
+
+
+def batch_matrix(sp: BatchSpec) -> np.ndarray:
+    """float32 m x n (column-major) U diag(r^j) V^T, U and V from numpy QR."""
+    A = prescribed_svd(sp.m, sp.n, batch_singular_values(sp), sp.seed_u, sp.seed_v)
+    return np.asfortranarray(A.astype(np.float32))

@@ -1,0 +1,74 @@
+"""GPU parity of the batched QB (qb_factor_batched) with the float64 oracle,
+problem by problem, through the C ABI.
+
+The batch mixes sizes, spectra and block sizes (s_j = r^j, uneven m and n,
+b in {16, 32, 64}) at eps = 1e-5 ||A||_F, the tolerance of the batched
+workload.  The inputs are float32; the batched path computes in float64,
+so each problem must match the oracle run on the same float32 values
+widened to float64: the same rank, widths, stop reason and Q B within
+1e-10 ||A||.  Plus the per-problem edge cases: a zero matrix, a NaN, kmax.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import paper_1503_07157_amd as qbmi
+import synth
+from oracle import STOP, randqb_pb
+from paper_1503_07157_amd._lib import QB_ENONFINITE, QB_KMAX
+
+STOP_NAMES = {v: k for k, v in STOP.items()}
+
+pytestmark = pytest.mark.gpu
+
+
+def dev32(x):
+    """Column-major float32 device copy."""
+    x = np.asarray(x, dtype=np.float32)
+    out = torch.empty((x.shape[1], x.shape[0]), dtype=torch.float32, device="cuda").t()
+    out.copy_(torch.from_numpy(np.ascontiguousarray(x)))
+    return out
+
+
+def test_batch_matches_oracle(cuda):
+    specs = synth.batch_specs(count=24, seed=77, m_range=(64, 700), n_max=400)
+    mats = [synth.batch_matrix(sp) for sp in specs]
+    eps = [1e-5 * float(np.linalg.norm(A.astype(np.float64))) for A in mats]
+    res = qbmi.qb_factor_batched([dev32(A) for A in mats], eps, [sp.b for sp in specs],
+                                 [sp.seed_omega for sp in specs])
+    for sp, A, e, g in zip(specs, mats, eps, res):
+        A64 = A.astype(np.float64)
+        o = randqb_pb(A64, e, sp.b, 0, sp.seed_omega)
+        nA = math.sqrt(g.normA2)
+        print(f"[case] {sp.m}x{sp.n} r={sp.r:.4f} b={sp.b}: k={g.k}/{o.k} "
+              f"stop={g.stop_reason}/{STOP_NAMES[o.stop_reason]}", flush=True)
+        assert g.status >= 0
+        assert g.k == o.k and g.blocks == o.blocks
+        assert g.stop_reason == STOP_NAMES[o.stop_reason]
+        Q, B = g.Q.cpu().numpy(), g.B.cpu().numpy()
+        assert np.linalg.norm(Q @ B - o.Q @ o.B) <= 1e-10 * nA
+        assert np.linalg.norm(A64 - Q @ B) <= e * (1 + 1e-9)
+        assert abs(g.normA2 - o.normA2) <= 1e-14 * o.normA2
+
+
+def test_batch_edge_cases(cuda):
+    r = np.random.default_rng(3)
+    good = synth.batch_matrix(synth.BatchSpec(300, 200, 0.95, 32, 5, 6, 7))
+    zero = np.zeros((100, 50), dtype=np.float32)
+    bad = r.standard_normal((80, 60)).astype(np.float32)
+    bad[3, 7] = np.nan
+    nA = float(np.linalg.norm(good.astype(np.float64)))
+    res = qbmi.qb_factor_batched([dev32(good), dev32(zero), dev32(bad), dev32(good)],
+                                 [1e-5 * nA, 0.0, 1.0, 1e-5 * nA], [32, 16, 16, 16],
+                                 [7, 1, 1, 7], kmax=[200, 50, 60, 40])
+    g, z, b, c = res
+    o = randqb_pb(good.astype(np.float64), 1e-5 * nA, 32, 0, 7)
+    assert g.k == o.k and g.status == 0
+    assert z.k == 0 and z.stop_reason == "ZERO" and z.status == 0
+    assert b.status == QB_ENONFINITE and b.k == 0
+    oc = randqb_pb(good.astype(np.float64), 1e-5 * nA, 16, 0, 7, kmax=40)
+    assert c.k == 40 == oc.k and c.status == QB_KMAX and c.stop_reason == "KMAX"
+    Q, B = c.Q.cpu().numpy(), c.B.cpu().numpy()
+    assert np.linalg.norm(Q @ B - oc.Q @ oc.B) <= 1e-10 * nA
