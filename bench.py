@@ -229,6 +229,115 @@ def post_experiment():
     print(json.dumps({"experiment": "post", "rows": out}), flush=True)
 
 
+def batched_experiment(steps, warmup, no_cpu):
+    """Many matrices of uneven sizes: 512 float32 matrices, m uniform in
+    [256, 4096], n uniform in [128, min(m, 2048)], s_j = r^j with r uniform
+    in [0.9, 0.995], b in {16, 32, 64}, eps = 1e-5 ||A||_F, P = 0, all
+    factorised by one qb_factor_batched call.  Reports seconds per batch,
+    matrices/s and nominal GFLOP/s (sum of 6 m n k + 2 m k^2), the same 512
+    problems run one by one through qb_factor for comparison, sampled parity
+    against the oracle and the oracle's own rate on those samples.  Prints
+    one JSON line."""
+    import numpy as np
+    import torch
+    import paper_1503_07157_amd as qbmi
+    from paper_1503_07157_amd import _lib
+    import synth
+
+    lib = _lib.load()
+    specs = synth.batch_specs()
+    t0 = time.perf_counter()
+    As = []
+    for i, sp in enumerate(specs):
+        As.append(synth.batch_matrix_gpu(sp))
+        if i % 128 == 127:
+            torch.cuda.synchronize()
+            log(f"[bench] batched: generated {i + 1}/{len(specs)} matrices "
+                f"({time.perf_counter() - t0:.1f} s)")
+    nA = [float(torch.linalg.norm(A, dtype=torch.float64)) for A in As]
+    eps = [1e-5 * v for v in nA]
+    bs = [sp.b for sp in specs]
+    seeds = [sp.seed_omega for sp in specs]
+
+    def one():
+        return qbmi.qb_factor_batched(As, eps, bs, seeds)
+
+    for _ in range(warmup):
+        one()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res = one()
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / steps
+    ks = [r.k for r in res]
+    nblk = [r.blocks for r in res]
+    active = [sum(1 for v in nblk if v > it) for it in range(max(nblk))]
+    flops = sum(nominal_flops(sp.m, sp.n, r.k, 0) for sp, r in zip(specs, res))
+    bad = [i for i, r in enumerate(res) if r.status < 0]
+    log(f"[bench] batched: {sec * 1e3:.1f} ms per batch of {len(specs)}, "
+        f"{flops / sec / 1e9:.0f} GFLOP/s, k in [{min(ks)}, {max(ks)}], errors {len(bad)}")
+    lib.qb_profile_enable(1)
+    one()
+    torch.cuda.synchronize()
+    prof = profile_snapshot(lib)
+    lib.qb_profile_enable(0)
+    kern = {name: {"ms": round(v["ms"], 3), "launches": v["launches"],
+                   **({"tflops": round(v["flops"] / v["ms"] / 1e9, 2)} if v["flops"] else {})}
+            for name, v in prof.items()}
+    # the same problems one by one through the single-matrix path (float64 input)
+    seq = 0.0
+    same_k = 0
+    for i, (sp, A) in enumerate(zip(specs, As)):
+        A64 = qbmi.colmajor(A.to(torch.float64))
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        r1 = qbmi.qb_factor(A64, eps[i], sp.b, 0, sp.seed_omega)
+        torch.cuda.synchronize()
+        seq += time.perf_counter() - ts
+        same_k += int(r1.k == res[i].k)
+        del A64, r1
+    log(f"[bench] batched: one by one {seq * 1e3:.1f} ms, same k {same_k}/{len(specs)}")
+    # parity on sampled problems against the oracle, which is also timed
+    cpu = None
+    parity = []
+    if not no_cpu:
+        from oracle import randqb_pb
+        import threadpoolctl
+        order = sorted(range(len(specs)), key=lambda i: specs[i].m * specs[i].n * max(ks[i], 1))
+        picks = [order[len(order) // 8], order[len(order) // 4], order[len(order) // 2]]
+        cpu_s = 0.0
+        cpu_fl = 0.0
+        for i in picks:
+            sp = specs[i]
+            Ah = As[i].cpu().numpy().astype(np.float64)
+            tc = time.perf_counter()
+            o = randqb_pb(Ah, eps[i], sp.b, 0, sp.seed_omega)
+            cpu_s += time.perf_counter() - tc
+            cpu_fl += nominal_flops(sp.m, sp.n, o.k, 0)
+            Qg, Bg = res[i].Q.cpu().numpy(), res[i].B.cpu().numpy()
+            d = float(np.linalg.norm(Qg @ Bg - o.Q @ o.B)) / nA[i]
+            parity.append({"index": i, "m": sp.m, "n": sp.n, "b": sp.b, "r": round(sp.r, 5),
+                           "k_gpu": res[i].k, "k_oracle": o.k, "qb_rel_diff": d})
+            log(f"[bench] batched parity #{i} {sp.m}x{sp.n} b={sp.b}: k {res[i].k}/{o.k} "
+                f"rel diff {d:.2e}")
+        info = threadpoolctl.threadpool_info()
+        cores = max([d.get("num_threads", 1) for d in info if d.get("user_api") == "blas"] or [1])
+        cpu = {"value": cpu_fl / cpu_s / 1e9, "unit": "GFLOP/s", "cores": int(cores),
+               "kind": "oracle", "seconds": cpu_s,
+               "sample": f"{len(picks)} of the 512 problems (the 1/8, 1/4 and 1/2 quantiles by "
+                         f"m n k), float64 numpy/OpenBLAS on the host"}
+    print(json.dumps({"experiment": "batched", "problems": len(specs),
+                      "seconds_per_batch": sec, "matrices_per_s": len(specs) / sec,
+                      "gflops": flops / sec / 1e9, "nominal_flops": flops,
+                      "k_min": min(ks), "k_max": max(ks), "k_total": sum(ks),
+                      "errors": len(bad), "iterations": len(active), "active_per_iteration": active,
+                      "one_by_one_seconds": seq,
+                      "one_by_one_same_k": same_k, "kernels": kern, "parity": parity,
+                      "cpu_baseline": cpu, "dtype": "f32 input, f64 arithmetic",
+                      "data": "synthetic"}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -240,7 +349,7 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-blocks", type=int, default=16)
-    ap.add_argument("--experiment", default=None, choices=["skip-reorth", "post"],
+    ap.add_argument("--experiment", default=None, choices=["skip-reorth", "post", "batched"],
                     help="run the Section 6.4 comparison instead of the benchmark")
     ap.add_argument("--matrix", default="workload", choices=["workload", "gaussian"],
                     help="gaussian: i.i.d. N(0, 1/m) entries of the workload's shape instead of "
@@ -256,6 +365,9 @@ def main():
         return
     if args.experiment == "post":
         post_experiment()
+        return
+    if args.experiment == "batched":
+        batched_experiment(args.steps, args.warmup, args.no_cpu)
         return
 
     import torch

@@ -592,13 +592,30 @@ __global__ __launch_bounds__(S::NT, S::OCC) void gemm_batched_kernel(
     else hi = mid - 1;
   }
   const BatchGemm g = desc[lo];
-  const int64_t t = blk - g.tile0;
+  const int64_t tiles = static_cast<int64_t>(g.tiles_m) * g.tiles_n;
+  const int64_t u = blk - g.tile0;
+  const int64_t kz = u / tiles, t = u - kz * tiles;
   const int64_t m0 = (t % g.tiles_m) * S::BM;
   const int64_t n0 = (t / g.tiles_m) * S::BN;
   const int64_t M = g.M, N = g.N, K = g.K;
+  const int64_t kbeg = kz * g.kchunk;
+  const int64_t kend = kbeg + g.kchunk < K ? kbeg + g.kchunk : K;
   d4 acc[S::IB][S::JB];
-  mma_loop<S, OP == kBatchTN>(g.A, g.lda, g.B, g.ldb, m0, n0, M, N, 0, K, g.vec != 0, As, Bs,
-                              acc);
+  mma_loop<S, OP == kBatchTN>(g.A, g.lda, g.B, g.ldb, m0, n0, M, N, kbeg, kend, g.vec != 0, As,
+                              Bs, acc);
+  if (g.ksplit > 1) {
+    // whole padded tile into this chunk's slot; rows and columns past M, N
+    // hold zeros (out-of-range operands load as zero)
+    const int64_t ldp = static_cast<int64_t>(g.tiles_m) * S::BM;
+    const int64_t np = static_cast<int64_t>(g.tiles_n) * S::BN;
+    double* P = g.part + kz * ldp * np;
+#pragma unroll
+    for (int i = 0; i < S::IB; ++i)
+#pragma unroll
+      for (int j = 0; j < S::JB; ++j)
+        store4(P, ldp, m0 + acc_row0<S>(i), n0 + acc_col<S>(j), ldp, np, true, acc[i][j]);
+    return;
+  }
   const bool vc = vec_ok_dev(g.C, g.ldc);
   double sq = 0.0;
 #pragma unroll
@@ -627,6 +644,45 @@ __global__ __launch_bounds__(S::NT, S::OCC) void gemm_batched_kernel(
   if (OP != kBatchNN && g.sq != nullptr) {
     const double tot = block_sum(sq, red);
     if (threadIdx.x == 0) g.sq[t] = tot;
+  }
+}
+
+// C from the depth chunks of the problems with ksplit > 1, in chunk order;
+// kBatchRed elements of C per workgroup
+template <int OP>
+__global__ __launch_bounds__(256) void gemm_batched_reduce_kernel(
+    const BatchGemm* __restrict__ desc, int count) {
+  __shared__ double red[4];
+  const int64_t blk = blockIdx.x;
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {  // last problem with rblock0 <= blk
+    const int mid = (lo + hi + 1) >> 1;
+    if (desc[mid].rblock0 <= blk) lo = mid;
+    else hi = mid - 1;
+  }
+  const BatchGemm g = desc[lo];
+  const int64_t rb = blk - g.rblock0;
+  const int64_t M = g.M, total = M * g.N;
+  const int64_t ldp = static_cast<int64_t>(g.tiles_m) * kBatchTile;
+  const int64_t slot = ldp * (static_cast<int64_t>(g.tiles_n) * kBatchTile);
+  double sq = 0.0;
+#pragma unroll
+  for (int q = 0; q < kBatchRed / 256; ++q) {
+    const int64_t e = rb * kBatchRed + q * 256 + threadIdx.x;
+    if (e < total) {
+      const int64_t i = e % M, j = e / M;
+      const double* p = g.part + i + j * ldp;
+      double v = 0.0;
+      for (int z = 0; z < g.ksplit; ++z) v += p[z * slot];
+      double* c = g.C + i + j * g.ldc;
+      if (OP == kBatchNN) v = g.alpha * v + (g.beta != 0.0 ? g.beta * *c : 0.0);
+      *c = v;
+      sq += v * v;
+    }
+  }
+  if (g.sq != nullptr) {
+    const double tot = block_sum(sq, red);
+    if (threadIdx.x == 0) g.sq[rb] = tot;
   }
 }
 
@@ -799,18 +855,33 @@ int downdate(double* R, int64_t ldr, const double* Qm, int64_t ldq, const double
   return kOk;
 }
 
-int gemm_batched(int op, const BatchGemm* desc, int count, int64_t total_tiles, hipStream_t s) {
+int gemm_batched(int op, const BatchGemm* desc, int count, int64_t total_tiles, int prof_id,
+                 double flops, hipStream_t s) {
   if (count <= 0 || total_tiles <= 0) return kOk;
   using S = Small;
   static_assert(S::BM == kBatchTile && S::BN == kBatchTile, "batched tile");
   const dim3 grid(static_cast<unsigned>(total_tiles));
-  ProfScope ps(kKGemmBatched, 0.0, 0.0, s);
+  ProfScope ps(prof_id, flops, 0.0, s);
   if (op == kBatchNN)
     hipLaunchKernelGGL((gemm_batched_kernel<S, kBatchNN>), grid, dim3(S::NT), 0, s, desc, count);
   else if (op == kBatchTN)
     hipLaunchKernelGGL((gemm_batched_kernel<S, kBatchTN>), grid, dim3(S::NT), 0, s, desc, count);
   else
     hipLaunchKernelGGL((gemm_batched_kernel<S, kBatchDD>), grid, dim3(S::NT), 0, s, desc, count);
+  QB_HIP_TRY(hipGetLastError());
+  return kOk;
+}
+
+int gemm_batched_reduce(int op, const BatchGemm* desc, int count, int64_t total_rblocks,
+                        int prof_id, hipStream_t s) {
+  if (count <= 0 || total_rblocks <= 0) return kOk;
+  if (op == kBatchDD) return kEInval;
+  const dim3 grid(static_cast<unsigned>(total_rblocks));
+  ProfScope ps(prof_id, 0.0, 0.0, s);
+  if (op == kBatchNN)
+    hipLaunchKernelGGL(gemm_batched_reduce_kernel<kBatchNN>, grid, dim3(256), 0, s, desc, count);
+  else
+    hipLaunchKernelGGL(gemm_batched_reduce_kernel<kBatchTN>, grid, dim3(256), 0, s, desc, count);
   QB_HIP_TRY(hipGetLastError());
   return kOk;
 }

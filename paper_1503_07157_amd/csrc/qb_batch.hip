@@ -28,6 +28,16 @@ constexpr double kFloorRelB = 0x1p-46;  // rounding floor of the residual, rel. 
 constexpr int kBMax = 64;               // widest panel of the batched form
 constexpr int kKeptStride = kBMax + 2;  // ints per problem in the kept table
 constexpr int kScal = 8;                // doubles per problem in the scalar table
+// Depth split of the products whose output has few tiles (the w x w Gram,
+// C = Qbar^T Q_i, B_i of a narrow matrix, and the m x w panels of a short
+// matrix): a problem's product is cut into at most ceil(kSplitTiles /
+// tiles) depth chunks of at least kSplitChunk, so that it spreads over
+// about kSplitTiles workgroups; the chunks are then summed in order.  The
+// choice depends only on the problem's own sizes, so its result does not
+// depend on the rest of the batch.
+constexpr int64_t kSplitTiles = 16;
+constexpr int64_t kSplitChunk = 256;
+constexpr int64_t kPartDoubles = (kSplitTiles + kSplitTiles - 2) * kBatchTile * kBatchTile;
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline int64_t even_up(int64_t v) { return (v + 1) & ~int64_t(1); }
@@ -50,7 +60,7 @@ struct Prob {
   int64_t m, n, kcap, ldr, ldm, ldc;
   int b;
   // device buffers
-  double *R, *omega, *Y, *Qt, *Qi, *C, *G, *Tinv, *sqA, *sqB, *sqR;
+  double *R, *omega, *Y, *Qt, *Qi, *C, *G, *Tinv, *sqA, *sqB, *sqR, *part;
   int *flA, *kept;
   double* scal;  // [0..1] ||R||^2, [2..3] ||B_i||^2, [4..5] ||A||^2
   int* iflag;
@@ -119,7 +129,9 @@ int carve_batch(Arena& a, const qb_problem* probs, int count, Layout* L) {
     p.nconv = convert_blocks(q.m, q.n);
     p.sqA = a.take<double>(static_cast<size_t>(p.nconv));
     p.flA = a.take<int>(static_cast<size_t>(p.nconv));
-    p.sqB = a.take<double>(static_cast<size_t>(cdiv(p.b, kBatchTile) * cdiv(q.n, kBatchTile)));
+    p.sqB = a.take<double>(static_cast<size_t>(std::max(cdiv(p.b, kBatchTile) * cdiv(q.n, kBatchTile),
+                                                        cdiv(int64_t(p.b) * q.n, kBatchRed))));
+    p.part = a.take<double>(static_cast<size_t>(kPartDoubles));
     p.sqR = a.take<double>(static_cast<size_t>(cdiv(q.m, kBatchTile) * cdiv(q.n, kBatchTile)));
     if (a.base != nullptr) {
       p.scal = L->scal_all + static_cast<size_t>(i) * kScal;
@@ -151,9 +163,10 @@ struct Stage {
   }
 };
 
+// part: the problem's split-K buffer (kPartDoubles), or null for no split
 BatchGemm gemm_desc(const double* A, int64_t lda, const double* B, int64_t ldb, double* C,
                     int64_t ldc, int64_t M, int64_t N, int64_t K, double alpha, double beta,
-                    double* sq) {
+                    double* sq, double* part) {
   BatchGemm g{};
   g.A = A;
   g.B = B;
@@ -172,17 +185,53 @@ BatchGemm gemm_desc(const double* A, int64_t lda, const double* B, int64_t ldb, 
   g.vec = (va && vb) ? 1 : 0;
   g.alpha = alpha;
   g.beta = beta;
+  g.ksplit = 1;
+  g.kchunk = static_cast<int32_t>(K);
+  g.part = nullptr;
+  const int64_t tiles = static_cast<int64_t>(g.tiles_m) * g.tiles_n;
+  if (part != nullptr && tiles < kSplitTiles && K >= 2 * kSplitChunk) {
+    int64_t ks = std::min(cdiv(kSplitTiles, tiles), K / kSplitChunk);
+    const int64_t chunk = cdiv(cdiv(K, ks), kTileK) * kTileK;
+    ks = cdiv(K, chunk);
+    if (ks > 1 && ks * tiles * kBatchTile * kBatchTile <= kPartDoubles) {
+      g.ksplit = static_cast<int32_t>(ks);
+      g.kchunk = static_cast<int32_t>(chunk);
+      g.part = part;
+    }
+  }
   return g;
 }
 
-// tile offsets; returns the total workgroup count
-int64_t place_tiles(std::vector<BatchGemm>& v) {
-  int64_t t = 0;
+struct Grid {
+  int64_t tiles = 0, rblocks = 0;  // workgroups of the product and of its reduction
+};
+
+int64_t reduce_blocks(const BatchGemm& g) {
+  return g.ksplit > 1 ? cdiv(static_cast<int64_t>(g.M) * g.N, kBatchRed) : 0;
+}
+
+// workgroup offsets of every problem in the product and reduce launches
+Grid place_tiles(std::vector<BatchGemm>& v) {
+  Grid t;
   for (auto& g : v) {
-    g.tile0 = t;
-    t += static_cast<int64_t>(g.tiles_m) * g.tiles_n;
+    g.tile0 = t.tiles;
+    g.rblock0 = t.rblocks;
+    t.tiles += static_cast<int64_t>(g.tiles_m) * g.tiles_n * g.ksplit;
+    t.rblocks += reduce_blocks(g);
   }
   return t;
+}
+
+// partial sums of squares that a TN product with sq leaves per problem
+int32_t sq_count(const BatchGemm& g) {
+  return static_cast<int32_t>(g.ksplit > 1 ? reduce_blocks(g)
+                                           : static_cast<int64_t>(g.tiles_m) * g.tiles_n);
+}
+
+double flops_of(const std::vector<BatchGemm>& v) {
+  double f = 0.0;
+  for (const auto& g : v) f += 2.0 * g.M * g.N * g.K;
+  return f;
 }
 
 }  // namespace
@@ -321,15 +370,17 @@ int qb_factor_batched(qb_problem* probs, int32_t count, void* workspace, size_t 
       std::vector<BatchGemm> gY(na);
       for (int a = 0; a < na; ++a) {
         const Prob& p = P[act[a]];
-        gY[a] = gemm_desc(p.R, p.ldr, p.omega, p.n, p.Y, p.ldm, p.m, p.w, p.n, 1.0, 0.0, nullptr);
+        gY[a] = gemm_desc(p.R, p.ldr, p.omega, p.n, p.Y, p.ldm, p.m, p.w, p.n, 1.0, 0.0, nullptr,
+                          p.part);
       }
-      const int64_t tY = place_tiles(gY);
+      const Grid tY = place_tiles(gY);
       // CholQR pass helpers: Gram, Cholesky, apply into dst
       auto gram = [&](const std::vector<int>& ids, double* const* X) {
         std::vector<BatchGemm> g(ids.size());
         for (size_t a = 0; a < ids.size(); ++a) {
           const Prob& p = P[ids[a]];
-          g[a] = gemm_desc(X[a], p.ldm, X[a], p.ldm, p.G, p.w, p.w, p.w, p.m, 1.0, 0.0, nullptr);
+          g[a] = gemm_desc(X[a], p.ldm, X[a], p.ldm, p.G, p.w, p.w, p.w, p.m, 1.0, 0.0, nullptr,
+                           p.part);
         }
         return g;
       };
@@ -347,7 +398,7 @@ int qb_factor_batched(qb_problem* probs, int32_t count, void* workspace, size_t 
         for (size_t a = 0; a < ids.size(); ++a) {
           const Prob& p = P[ids[a]];
           g[a] = gemm_desc(X[a], p.ldm, p.Tinv, p.w, D[a], ldd[a], p.m, p.w, p.w, 1.0, 0.0,
-                           nullptr);
+                           nullptr, p.part);
         }
         return g;
       };
@@ -371,8 +422,8 @@ int qb_factor_batched(qb_problem* probs, int32_t count, void* workspace, size_t 
       std::vector<BatchGemm> g1 = gram(act, xY.data()), a1 = apply(act, xY.data(), dQt.data(), lQt.data());
       std::vector<BatchGemm> g2 = gram(act, xQt.data()), a2 = apply(act, xQt.data(), d2.data(), l2.data());
       std::vector<BatchChol> c1 = chol(act);
-      const int64_t tg1 = place_tiles(g1), ta1 = place_tiles(a1), tg2 = place_tiles(g2),
-                    ta2 = place_tiles(a2);
+      const Grid tg1 = place_tiles(g1), ta1 = place_tiles(a1), tg2 = place_tiles(g2),
+                 ta2 = place_tiles(a2);
       // re-projection of the problems with k > 0, then CholQR2 into Q + k ldq
       std::vector<BatchGemm> rC(nr), rQ(nr);
       std::vector<double*> xQi(nr), dQt2(nr), xQt2(nr), dOut(nr);
@@ -380,8 +431,10 @@ int qb_factor_batched(qb_problem* probs, int32_t count, void* workspace, size_t 
       for (int a = 0; a < nr; ++a) {
         Prob& p = P[reproj[a]];
         qb_problem& q = probs[reproj[a]];
-        rC[a] = gemm_desc(q.Q, q.ldq, p.Qi, p.ldm, p.C, p.ldc, p.k, p.w, p.m, 1.0, 0.0, nullptr);
-        rQ[a] = gemm_desc(q.Q, q.ldq, p.C, p.ldc, p.Qi, p.ldm, p.m, p.w, p.k, -1.0, 1.0, nullptr);
+        rC[a] = gemm_desc(q.Q, q.ldq, p.Qi, p.ldm, p.C, p.ldc, p.k, p.w, p.m, 1.0, 0.0, nullptr,
+                          p.part);
+        rQ[a] = gemm_desc(q.Q, q.ldq, p.C, p.ldc, p.Qi, p.ldm, p.m, p.w, p.k, -1.0, 1.0, nullptr,
+                          p.part);
         xQi[a] = p.Qi;
         dQt2[a] = p.Qt;
         xQt2[a] = p.Qt;
@@ -392,8 +445,8 @@ int qb_factor_batched(qb_problem* probs, int32_t count, void* workspace, size_t 
       std::vector<BatchGemm> g3 = gram(reproj, xQi.data()), a3 = apply(reproj, xQi.data(), dQt2.data(), lQt2.data());
       std::vector<BatchGemm> g4 = gram(reproj, xQt2.data()), a4 = apply(reproj, xQt2.data(), dOut.data(), lOut.data());
       std::vector<BatchChol> c3 = chol(reproj);
-      const int64_t trC = place_tiles(rC), trQ = place_tiles(rQ), tg3 = place_tiles(g3),
-                    ta3 = place_tiles(a3), tg4 = place_tiles(g4), ta4 = place_tiles(a4);
+      const Grid trC = place_tiles(rC), trQ = place_tiles(rQ), tg3 = place_tiles(g3),
+                 ta3 = place_tiles(a3), tg4 = place_tiles(g4), ta4 = place_tiles(a4);
       // B_i = Q_i^T R with ||B_i||^2, R -= Q_i B_i with ||R||^2, sums
       std::vector<BatchGemm> gB(na), gD(na);
       std::vector<BatchSum> sB(na), sR(na);
@@ -402,14 +455,15 @@ int qb_factor_batched(qb_problem* probs, int32_t count, void* workspace, size_t 
         qb_problem& q = probs[act[a]];
         double* Qo = q.Q + p.k * q.ldq;
         double* Bo = q.B + p.k;
-        gB[a] = gemm_desc(Qo, q.ldq, p.R, p.ldr, Bo, q.ldb, p.w, p.n, p.m, 1.0, 0.0, p.sqB);
-        gD[a] = gemm_desc(Qo, q.ldq, Bo, q.ldb, p.R, p.ldr, p.m, p.n, p.w, 1.0, 0.0, p.sqR);
-        sB[a] = BatchSum{p.sqB, nullptr, p.scal + 2, nullptr,
-                         static_cast<int32_t>(cdiv(p.w, kBatchTile) * cdiv(p.n, kBatchTile))};
+        gB[a] = gemm_desc(Qo, q.ldq, p.R, p.ldr, Bo, q.ldb, p.w, p.n, p.m, 1.0, 0.0, p.sqB,
+                          p.part);
+        gD[a] = gemm_desc(Qo, q.ldq, Bo, q.ldb, p.R, p.ldr, p.m, p.n, p.w, 1.0, 0.0, p.sqR,
+                          nullptr);
+        sB[a] = BatchSum{p.sqB, nullptr, p.scal + 2, nullptr, sq_count(gB[a])};
         sR[a] = BatchSum{p.sqR, nullptr, p.scal + 0, nullptr,
                          static_cast<int32_t>(cdiv(p.m, kBatchTile) * cdiv(p.n, kBatchTile))};
       }
-      const int64_t tB = place_tiles(gB), tD = place_tiles(gD);
+      const Grid tB = place_tiles(gB), tD = place_tiles(gD);
 
       const size_t osk = sg.put(sk), oY = sg.put(gY), og1 = sg.put(g1), oc1 = sg.put(c1),
                    oa1 = sg.put(a1), og2 = sg.put(g2), oa2 = sg.put(a2);
@@ -423,25 +477,31 @@ int qb_factor_batched(qb_problem* probs, int32_t count, void* workspace, size_t 
       auto Ch = [&](size_t off) { return reinterpret_cast<const BatchChol*>(dev(off)); };
       int e = upload();
       e = e || sketch_batched(reinterpret_cast<const BatchSketch*>(dev(osk)), na, skb, st);
-      e = e || gemm_batched(kBatchNN, G(oY), na, tY, st);
-      e = e || gemm_batched(kBatchTN, G(og1), na, tg1, st);
+      auto mm = [&](int op, size_t off, const std::vector<BatchGemm>& v, const Grid& t,
+                    int pid) -> int {
+        const int c = static_cast<int>(v.size());
+        if (gemm_batched(op, G(off), c, t.tiles, pid, flops_of(v), st)) return 1;
+        return gemm_batched_reduce(op, G(off), c, t.rblocks, pid, st) ? 1 : 0;
+      };
+      e = e || mm(kBatchNN, oY, gY, tY, kKBatchSample);
+      e = e || mm(kBatchTN, og1, g1, tg1, kKBatchGram);
       e = e || chol_inv_batched(Ch(oc1), na, st);
-      e = e || gemm_batched(kBatchNN, G(oa1), na, ta1, st);
-      e = e || gemm_batched(kBatchTN, G(og2), na, tg2, st);
+      e = e || mm(kBatchNN, oa1, a1, ta1, kKBatchApply);
+      e = e || mm(kBatchTN, og2, g2, tg2, kKBatchGram);
       e = e || chol_inv_batched(Ch(oc1), na, st);
-      e = e || gemm_batched(kBatchNN, G(oa2), na, ta2, st);
+      e = e || mm(kBatchNN, oa2, a2, ta2, kKBatchApply);
       if (nr) {
-        e = e || gemm_batched(kBatchTN, G(orC), nr, trC, st);
-        e = e || gemm_batched(kBatchNN, G(orQ), nr, trQ, st);
-        e = e || gemm_batched(kBatchTN, G(og3), nr, tg3, st);
+        e = e || mm(kBatchTN, orC, rC, trC, kKBatchReproj);
+        e = e || mm(kBatchNN, orQ, rQ, trQ, kKBatchReproj);
+        e = e || mm(kBatchTN, og3, g3, tg3, kKBatchGram);
         e = e || chol_inv_batched(Ch(oc3), nr, st);
-        e = e || gemm_batched(kBatchNN, G(oa3), nr, ta3, st);
-        e = e || gemm_batched(kBatchTN, G(og4), nr, tg4, st);
+        e = e || mm(kBatchNN, oa3, a3, ta3, kKBatchApply);
+        e = e || mm(kBatchTN, og4, g4, tg4, kKBatchGram);
         e = e || chol_inv_batched(Ch(oc3), nr, st);
-        e = e || gemm_batched(kBatchNN, G(oa4), nr, ta4, st);
+        e = e || mm(kBatchNN, oa4, a4, ta4, kKBatchApply);
       }
-      e = e || gemm_batched(kBatchTN, G(oB), na, tB, st);
-      e = e || gemm_batched(kBatchDD, G(oD), na, tD, st);
+      e = e || mm(kBatchTN, oB, gB, tB, kKBatchB);
+      e = e || mm(kBatchDD, oD, gD, tD, kKBatchDowndate);
       e = e || sum_batched(reinterpret_cast<const BatchSum*>(dev(osB)), na, st);
       e = e || sum_batched(reinterpret_cast<const BatchSum*>(dev(osR)), na, st);
       e = e || fetch();

@@ -64,7 +64,9 @@ struct Arena {
 // performs.  Elapsed times are folded in when the counters are read.
 enum KernelId {
   kKSketch = 0, kKGemmNN, kKGemmTN, kKReduce, kKDowndate, kKChol, kKTrinv, kKNorm, kKCopy,
-  kKGemmNNLowp, kKGemmTNLowp, kKGemmNNSmall, kKGemmTNSmall, kKGemmNNTall, kKGemmBatched, kKCholBatched, kKBatchMisc, kKCount
+  kKGemmNNLowp, kKGemmTNLowp, kKGemmNNSmall, kKGemmTNSmall, kKGemmNNTall,
+  kKBatchSample, kKBatchGram, kKBatchApply, kKBatchReproj, kKBatchB, kKBatchDowndate,
+  kKCholBatched, kKBatchMisc, kKCount
 };
 const char* kernel_name(int id);
 bool prof_enabled();
@@ -132,8 +134,6 @@ int copy_matrix(const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t M,
                 hipStream_t s);
 int zero_matrix(double* Y, int64_t ldy, int64_t M, int64_t N, hipStream_t s);
 
-// orth: CholQR2 with dropping.  X (m x w, ldx) -> Q (m x w, ldq), kept
-// columns first, zero columns after; *kept_dev receives the count.
 // ---- batched forms (many independent problems in one launch) -------------
 // One problem of a batched product.  op NN: C(M x N) = alpha A(M x K) B(K x N)
 // + beta C; op TN: C(M x N) = A(K x M)^T B(K x N) (sq: per-tile sums of
@@ -145,16 +145,28 @@ struct BatchGemm {
   const double* B;
   double* C;
   double* sq;
+  double* part;    // split-K partial tiles, ksplit slots of ldp x (tiles_n * 64)
   int64_t lda, ldb, ldc;
-  int64_t tile0;
+  int64_t tile0;   // first workgroup of this problem in the product launch
+  int64_t rblock0; // first workgroup of this problem in the reduce launch
   int32_t M, N, K;
   int32_t tiles_m, tiles_n;
+  int32_t ksplit, kchunk;  // depth split: ksplit chunks of kchunk (a multiple of kTileK)
   int32_t vec;  // A and B 16-byte aligned with even leading dimensions
   double alpha, beta;
 };
 enum { kBatchNN = 0, kBatchTN = 1, kBatchDD = 2 };
-constexpr int kBatchTile = 64;  // batched products use 64 x 64 output tiles
-int gemm_batched(int op, const BatchGemm* desc, int count, int64_t total_tiles, hipStream_t s);
+constexpr int kBatchTile = 64;      // batched products use 64 x 64 output tiles
+constexpr int kBatchRed = 1024;     // elements per workgroup of the split-K reduction
+// prof_id, flops: the profiler entry and the launch's algorithmic count (sum of 2 M N K).
+// total_tiles counts every (tile, depth chunk) workgroup.  Problems with
+// ksplit > 1 leave C to gemm_batched_reduce, which sums their chunks in
+// order (alpha sum + beta C for NN, the sum for TN) with per-workgroup sums
+// of squares into sq when sq is set; total_rblocks counts its workgroups.
+int gemm_batched(int op, const BatchGemm* desc, int count, int64_t total_tiles, int prof_id,
+                 double flops, hipStream_t s);
+int gemm_batched_reduce(int op, const BatchGemm* desc, int count, int64_t total_rblocks,
+                        int prof_id, hipStream_t s);
 
 struct BatchChol {  // Cholesky with dropping + inverse of one w x w Gram matrix
   const double* G;
@@ -194,6 +206,8 @@ struct BatchSum {  // out[0..1] = compensated sum of part[0..count) (hi, lo);
 };
 int sum_batched(const BatchSum* desc, int count, hipStream_t s);
 
+// orth: CholQR2 with dropping.  X (m x w, ldx) -> Q (m x w, ldq), kept
+// columns first, zero columns after; *kept_dev receives the count.
 struct OrthWork {
   double* gram;      // w x w
   double* tfull;     // w x w

@@ -23,4 +23,5 @@ from .matrices import (  # noqa: F401
     batch_specs,
     batch_singular_values,
     batch_matrix,
+    batch_matrix_gpu,
 )

@@ -217,3 +217,26 @@ def batch_matrix(sp: BatchSpec) -> np.ndarray:
     """float32 m x n (column-major) U diag(r^j) V^T, U and V from numpy QR."""
     A = prescribed_svd(sp.m, sp.n, batch_singular_values(sp), sp.seed_u, sp.seed_v)
     return np.asfortranarray(A.astype(np.float32))
+
+
+def batch_matrix_gpu(sp: BatchSpec, device="cuda"):
+    """GPU construction of the batch matrix (torch, device memory plumbing
+    only): U diag(r^j) V^T with U and V the Q factors of seeded N(0,1)
+    matrices from torch's device generator, built in float64 and rounded to
+    float32.  Column-major (strides (1, m)).  The values differ from
+    `batch_matrix` (another RNG); the same bytes go to both the GPU path and
+    the oracle."""
+    import torch
+
+    m, n = sp.m, sp.n
+    r = min(m, n)
+    s = torch.as_tensor(batch_singular_values(sp), dtype=torch.float64, device=device)
+    gen = torch.Generator(device=device)
+    gen.manual_seed(sp.seed_u)
+    u = torch.linalg.qr(torch.randn((m, r), generator=gen, dtype=torch.float64, device=device))[0]
+    gen.manual_seed(sp.seed_v)
+    v = torch.linalg.qr(torch.randn((n, r), generator=gen, dtype=torch.float64, device=device))[0]
+    u.mul_(s[None, :])
+    at = (v @ u.t()).to(torch.float32)
+    del u, v
+    return at.t()

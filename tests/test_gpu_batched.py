@@ -72,3 +72,34 @@ def test_batch_edge_cases(cuda):
     assert c.k == 40 == oc.k and c.status == QB_KMAX and c.stop_reason == "KMAX"
     Q, B = c.Q.cpu().numpy(), c.B.cpu().numpy()
     assert np.linalg.norm(Q @ B - oc.Q @ oc.B) <= 1e-10 * nA
+
+
+def test_batch_full_distribution(cuda):
+    """48 problems drawn from the full size range (m up to 4096, n up to
+    2048), built on the GPU, in one call: every problem meets its tolerance
+    with orthonormal Q and the exact residual identity; the two cheapest
+    match the oracle problem by problem."""
+    specs = synth.batch_specs(count=48, seed=9090)
+    As = [synth.batch_matrix_gpu(sp) for sp in specs]
+    nA = [float(torch.linalg.norm(A, dtype=torch.float64)) for A in As]
+    eps = [1e-5 * v for v in nA]
+    res = qbmi.qb_factor_batched(As, eps, [sp.b for sp in specs], [sp.seed_omega for sp in specs])
+    for sp, A, e, g in zip(specs, As, eps, res):
+        print(f"[case] {sp.m}x{sp.n} r={sp.r:.4f} b={sp.b}: k={g.k} stop={g.stop_reason}", flush=True)
+        assert g.status == 0 and g.stop_reason in ("TOL_TRACKED", "TOL_DIRECT", "RANK_CAP")
+        A64 = A.to(torch.float64)
+        R = A64 - g.Q @ g.B
+        assert float(torch.linalg.norm(R)) <= e * (1 + 1e-9)
+        I = g.Q.t() @ g.Q
+        assert float(torch.linalg.norm(I - torch.eye(g.k, dtype=torch.float64, device=cuda))) <= 1e-12 * g.k
+        # ||A - Q B||^2 = ||A||^2 - ||B||^2 for orthonormal Q and B = Q^T A
+        lhs = float(torch.linalg.norm(R)) ** 2
+        rhs = float(torch.linalg.norm(A64)) ** 2 - float(torch.linalg.norm(g.B)) ** 2
+        assert abs(lhs - rhs) <= 1e-12 * float(torch.linalg.norm(A64)) ** 2
+    order = sorted(range(len(specs)), key=lambda i: specs[i].m * specs[i].n * max(res[i].k, 1))
+    for i in order[:2]:
+        sp = specs[i]
+        o = randqb_pb(As[i].cpu().numpy().astype(np.float64), eps[i], sp.b, 0, sp.seed_omega)
+        assert res[i].k == o.k
+        Qg, Bg = res[i].Q.cpu().numpy(), res[i].B.cpu().numpy()
+        assert np.linalg.norm(Qg @ Bg - o.Q @ o.B) <= 1e-10 * nA[i]
