@@ -209,3 +209,40 @@ def test_real_oracle_passes_the_cpqr_pins():
 ])
 def test_cpqr_mutations_are_caught(old, new):
     assert not _cpqr_pins_hold(mutant("postprocess", old, new))
+
+
+def _adjoint_fd_holds(mod) -> bool:
+    """The central-difference pin of test_oracle_adjoint on one case."""
+    from tests.test_oracle_adjoint import case, loss_np
+    m, n, b, s, P = 60, 40, 8, 3, 1
+    A, g = case(m, n)
+    dQ = g.standard_normal((m, b * s))
+    dB = g.standard_normal((b * s, n))
+    _, _, dA = mod.qb_fixed_vjp(A, dQ, dB, b, s, P, 5)
+    h = 1e-5 * np.linalg.norm(A)
+    for _ in range(3):
+        E = g.standard_normal((m, n))
+        E /= np.linalg.norm(E)
+        fd = (loss_np(A + h * E, dQ, dB, b, s, P, 5) - loss_np(A - h * E, dQ, dB, b, s, P, 5)) / (2 * h)
+        if abs(fd - float(np.sum(dA * E))) > 1e-7 * np.linalg.norm(dA):
+            return False
+    return True
+
+
+def test_real_oracle_passes_the_adjoint_pin():
+    import oracle.adjoint
+    assert _adjoint_fd_holds(oracle.adjoint)
+
+
+@pytest.mark.parametrize("old,new", [
+    # re-projection treated as a constant projector in the backward
+    ("Qi = orth_t(Qi - Qbar @ (Qbar.T @ Qi))", "Qi = orth_t(Qi - Qbar.detach() @ (Qbar.detach().T @ Qi))"),
+    # B_i = Q_i^T R with Q_i held fixed
+    ("Bi = Qi.T @ R", "Bi = Qi.detach().T @ R"),
+    # one operand of the Gram matrix held fixed
+    ("L = torch.linalg.cholesky(X.T @ X)", "L = torch.linalg.cholesky(X.detach().T @ X)"),
+    # power iteration: the transposed product held fixed
+    ("Z = orth_t(R.T @ Qi)", "Z = orth_t(R.detach().T @ Qi)"),
+])
+def test_adjoint_mutations_are_caught(old, new):
+    assert not _adjoint_fd_holds(mutant("adjoint", old, new))
