@@ -338,6 +338,76 @@ def batched_experiment(steps, warmup, no_cpu):
                       "data": "synthetic"}), flush=True)
 
 
+def adjoint_experiment(steps, warmup, no_cpu):
+    """The fixed-sketch QB map and its hand-written adjoint on a 4096 x 2048
+    float32 matrix with s_j = exp(-j/100), b = 64, 4 blocks (k = 256), P in
+    {0, 1}, loss L = <G, Q B> with G ~ N(0, 1): seconds for the forward
+    (qb_fixed) and for the backward (qb_adjoint), the backward's GEMM rate
+    from the per-kernel profile, its error against the float64 oracle
+    gradient, and the oracle's own time for the same gradient.  Prints one
+    JSON line."""
+    import numpy as np
+    import torch
+    import paper_1503_07157_amd as qbmi
+    from paper_1503_07157_amd import _lib
+    import synth
+
+    lib = _lib.load()
+    m, n, b, s, seed = 4096, 2048, 64, 4, 77
+    A32 = synth.prescribed_svd(m, n, np.exp(-np.arange(1, n + 1) / 100.0), 31, 32).astype(np.float32)
+    A64 = A32.astype(np.float64)
+    G = np.random.default_rng(5).standard_normal((m, n))
+    Ad = qbmi.colmajor(torch.from_numpy(A64).cuda())
+    Gd = qbmi.colmajor(torch.from_numpy(G).cuda())
+    rows = []
+    for P in (0, 1):
+        Q, B = qbmi.qb_fixed(Ad, b, s, P, seed)
+        dQ = qbmi.colmajor(Gd @ B.t())
+        dB = qbmi.colmajor(Q.t() @ Gd)
+        for _ in range(warmup):
+            qbmi.qb_fixed(Ad, b, s, P, seed)
+            qbmi.qb_adjoint(Ad, Q, B, dQ, dB, b, s, P, seed)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            qbmi.qb_fixed(Ad, b, s, P, seed)
+        torch.cuda.synchronize()
+        t_fwd = (time.perf_counter() - t0) / steps
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            dA = qbmi.qb_adjoint(Ad, Q, B, dQ, dB, b, s, P, seed)
+        torch.cuda.synchronize()
+        t_bwd = (time.perf_counter() - t0) / steps
+        lib.qb_profile_enable(1)
+        qbmi.qb_adjoint(Ad, Q, B, dQ, dB, b, s, P, seed)
+        torch.cuda.synchronize()
+        prof = profile_snapshot(lib)
+        lib.qb_profile_enable(0)
+        gemm_fl = sum(v["flops"] for k, v in prof.items() if k.startswith("gemm"))
+        gemm_ms = sum(v["ms"] for k, v in prof.items() if k.startswith("gemm"))
+        row = {"power_iters": P, "forward_s": t_fwd, "backward_s": t_bwd,
+               "backward_gemm_flops": gemm_fl, "backward_gemm_tflops": gemm_fl / gemm_ms / 1e9,
+               "backward_gflops": gemm_fl / t_bwd / 1e9,
+               "kernels": {k: {"ms": round(v["ms"], 3), "launches": v["launches"]}
+                           for k, v in prof.items()}}
+        if not no_cpu:
+            from oracle.adjoint import qb_fixed_vjp
+            Qn, Bn = Q.cpu().numpy(), B.cpu().numpy()
+            tc = time.perf_counter()
+            _, _, dAo = qb_fixed_vjp(A64, G @ Bn.T, Qn.T @ G, b, s, P, seed)
+            row["oracle_s"] = time.perf_counter() - tc
+            row["rel_err_vs_oracle"] = float(np.linalg.norm(dA.cpu().numpy() - dAo) / np.linalg.norm(dAo))
+        log(f"[bench] adjoint P={P}: forward {t_fwd * 1e3:.1f} ms, backward {t_bwd * 1e3:.1f} ms "
+            f"({row['backward_gflops']:.0f} GFLOP/s), oracle {row.get('oracle_s', float('nan')):.2f} s")
+        rows.append(row)
+    import threadpoolctl
+    info = threadpoolctl.threadpool_info()
+    cores = max([d.get("num_threads", 1) for d in info if d.get("user_api") == "blas"] or [1])
+    print(json.dumps({"experiment": "adjoint", "workload": "exp100_4096x2048_f32, b=64, 4 blocks",
+                      "rows": rows, "oracle": "torch CPU float64 autograd", "oracle_cores": cores,
+                      "dtype": "f32 input, f64 arithmetic", "data": "synthetic"}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -349,7 +419,7 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-blocks", type=int, default=16)
-    ap.add_argument("--experiment", default=None, choices=["skip-reorth", "post", "batched"],
+    ap.add_argument("--experiment", default=None, choices=["skip-reorth", "post", "batched", "adjoint"],
                     help="run the Section 6.4 comparison instead of the benchmark")
     ap.add_argument("--matrix", default="workload", choices=["workload", "gaussian"],
                     help="gaussian: i.i.d. N(0, 1/m) entries of the workload's shape instead of "
@@ -368,6 +438,9 @@ def main():
         return
     if args.experiment == "batched":
         batched_experiment(args.steps, args.warmup, args.no_cpu)
+        return
+    if args.experiment == "adjoint":
+        adjoint_experiment(args.steps, args.warmup, args.no_cpu)
         return
 
     import torch

@@ -260,6 +260,35 @@ size_t qb_factor_batched_workspace_bytes(const qb_problem* probs, int32_t count)
 int qb_factor_batched(qb_problem* probs, int32_t count, void* workspace, size_t ws_bytes,
                       void* stream);
 
+/* ---- adjoint of the fixed-sketch map A -> (Q, B) ----------------------------
+ * With the sketch (seed), the block width b, the number of blocks s and the
+ * number of power iterations P fixed, the blocked scheme (Figure 4, with the
+ * power iterations of Figure 6 and the re-projection of Section 4.4) maps A
+ * to Q = [Q_1 .. Q_s] (m x s b) and B = [B_1; ..; B_s] (s b x n) smoothly
+ * wherever every orthonormalisation sees a full-column-rank matrix; that
+ * map is qb_factor(A, eps = 0, b, P, seed) with kmax = s b when no column
+ * is dropped.
+ *
+ * qb_adjoint writes dA = J^T (dQ, dB), the gradient of <dQ, Q> + <dB, B>
+ * with respect to A (m x n, lda), given A and the forward's Q (m x s b, ldq)
+ * and B (s b x n, ldb).  dQ (m x s b, lddq) or dB (s b x n, lddb) may be
+ * NULL for a zero upstream gradient.  Only Q and B of the forward are used:
+ * the samples and power-iteration intermediates are recomputed.  All
+ * matrices are float64, column-major, device memory; dA (ldda >= m) is
+ * overwritten and must not alias the inputs.
+ *
+ * Requirements: 1 <= b <= 256, s >= 1, s b <= min(m, n), 0 <= P <= 8,
+ * leading dimensions below 2^24.  Returns QB_OK; QB_RANK_EXHAUSTED when a
+ * recomputed orthonormalisation dropped a column (the map is not
+ * differentiable there; dA is then unspecified); QB_EINVAL, QB_EWORKSPACE
+ * or QB_EHIP.  Synchronises the stream before returning. */
+size_t qb_adjoint_workspace_bytes(int64_t m, int64_t n, int32_t b, int32_t blocks,
+                                  int32_t power_iters);
+int qb_adjoint(const double* A, int64_t m, int64_t n, int64_t lda, int32_t b, int32_t blocks,
+               int32_t power_iters, uint64_t seed, const double* Q, int64_t ldq, const double* B,
+               int64_t ldb, const double* dQ, int64_t lddq, const double* dB, int64_t lddb,
+               double* dA, int64_t ldda, void* workspace, size_t ws_bytes, void* stream);
+
 /* ---- measurement ---------------------------------------------------------
  * Optional per-kernel timing: when enabled, every kernel launch of the
  * library is bracketed by two HIP events on the stream it runs on and

@@ -5,6 +5,7 @@ this package only loads it and marshals torch tensors into its calls.
 """
 from ._lib import QBError, load  # noqa: F401
 from .qb import (  # noqa: F401
+    QBFunction,
     QBResult,
     colmajor,
     downdate,
@@ -12,8 +13,10 @@ from .qb import (  # noqa: F401
     orth,
     pivoted_qr,
     project,
+    qb_adjoint,
     qb_factor,
     qb_factor_batched,
+    qb_fixed,
     sample_product,
     sketch,
     svd,

@@ -109,6 +109,10 @@ SIGNATURES = {
                                      c_vp, c_i64, c_vp, c_vp, c_size, c_vp]),
     "qb_factor_batched_workspace_bytes": (c_size, [ctypes.POINTER(QBProblem), c_i32]),
     "qb_factor_batched": (ctypes.c_int, [ctypes.POINTER(QBProblem), c_i32, c_vp, c_size, c_vp]),
+    "qb_adjoint_workspace_bytes": (c_size, [c_i64, c_i64, c_i32, c_i32, c_i32]),
+    "qb_adjoint": (ctypes.c_int, [c_vp, c_i64, c_i64, c_i64, c_i32, c_i32, c_i32, c_u64,
+                                  c_vp, c_i64, c_vp, c_i64, c_vp, c_i64, c_vp, c_i64,
+                                  c_vp, c_i64, c_vp, c_size, c_vp]),
     "qb_profile_enable": (ctypes.c_int, [ctypes.c_int]),
     "qb_profile_count": (c_i32, []),
     "qb_profile_name": (ctypes.c_char_p, [c_i32]),

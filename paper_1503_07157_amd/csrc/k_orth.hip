@@ -622,4 +622,29 @@ int orth_cholqr2(const double* X, int64_t ldx, double* Q, int64_t ldq, int64_t m
   return cholqr_pass(ow.qtmp, ow.ldt, Q, ldq, m, w, ow, s);
 }
 
+namespace {
+// flag[0] = 1 when a pass kept fewer than w columns
+__global__ void flag_dropped_kernel(const int* __restrict__ kept, int w, int* __restrict__ flag) {
+  if (threadIdx.x == 0 && kept[0] != w) flag[0] = 1;
+}
+}  // namespace
+
+int orth_cholqr2_rinv(const double* X, int64_t ldx, double* Q, int64_t ldq, int64_t m, int w,
+                      const OrthWork& ow, double* t1inv, double* rinv, int* dropped,
+                      hipStream_t s) {
+  if (w < 1 || w > kMaxPanel) return kEInval;
+  int rc = cholqr_pass(X, ldx, ow.qtmp, ow.ldt, m, w, ow, s);
+  if (rc) return rc;
+  hipLaunchKernelGGL(flag_dropped_kernel, dim3(1), dim3(64), 0, s, ow.kept, w, dropped);
+  QB_HIP_TRY(hipGetLastError());
+  rc = copy_matrix(ow.tinv, w, t1inv, w, w, w, s);
+  if (rc) return rc;
+  rc = cholqr_pass(ow.qtmp, ow.ldt, Q, ldq, m, w, ow, s);
+  if (rc) return rc;
+  hipLaunchKernelGGL(flag_dropped_kernel, dim3(1), dim3(64), 0, s, ow.kept, w, dropped);
+  QB_HIP_TRY(hipGetLastError());
+  // R = T2 T1, so R^{-1} = T1^{-1} T2^{-1}
+  return gemm_nn(t1inv, w, ow.tinv, w, rinv, w, w, w, w, 1.0, 0.0, 1, nullptr, s);
+}
+
 }  // namespace qb

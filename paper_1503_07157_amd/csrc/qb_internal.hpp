@@ -222,5 +222,11 @@ size_t orth_work_bytes(int64_t m, int w);
 int orth_carve(Arena& a, int64_t m, int w, OrthWork* ow);
 int orth_cholqr2(const double* X, int64_t ldx, double* Q, int64_t ldq, int64_t m, int w,
                  const OrthWork& ow, hipStream_t s);
+// orth_cholqr2 that also returns R^{-1} (w x w, ld w) of X = Q R, with
+// R = T2 T1 the product of the two passes' factors (t1inv: w x w scratch),
+// and sets *dropped (device int) to 1 when either pass dropped a column
+int orth_cholqr2_rinv(const double* X, int64_t ldx, double* Q, int64_t ldq, int64_t m, int w,
+                      const OrthWork& ow, double* t1inv, double* rinv, int* dropped,
+                      hipStream_t s);
 
 }  // namespace qb

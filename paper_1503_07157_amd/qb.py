@@ -305,3 +305,69 @@ def qb_factor_batched(As, eps, bs, seeds, kmax=None):
                             normA2=p.normA2, indicator=float("nan"), resid2=p.resid2,
                             blocks=int(p.blocks), widths=[], E=[], D=[], R=None))
     return out
+
+
+def qb_adjoint(A, Q, B, dQ, dB, b: int, blocks: int, power_iters: int, seed: int):
+    """dA = J^T (dQ, dB) for the fixed-sketch map A -> (Q, B) (qb_factor with
+    eps = 0, kmax = blocks * b, no dropped column); float64 column-major
+    device tensors, dQ or dB may be None.  Raises QBError with
+    QB_RANK_EXHAUSTED when a recomputed orthonormalisation loses rank."""
+    lib = _lib.load()
+    lda = _ld(A, "A")
+    m, n = A.shape
+    kt = int(b) * int(blocks)
+    if Q.shape != (m, kt) or B.shape != (kt, n):
+        raise ValueError("Q and B must be m x (blocks b) and (blocks b) x n")
+    ldq, ldb = _ld(Q, "Q"), _ld(B, "B")
+    pdq, lddq = (0, m) if dQ is None else (dQ.data_ptr(), _ld(dQ, "dQ"))
+    pdb, lddb = (0, kt) if dB is None else (dB.data_ptr(), _ld(dB, "dB"))
+    if dQ is not None and dQ.shape != Q.shape:
+        raise ValueError("dQ must have the shape of Q")
+    if dB is not None and dB.shape != B.shape:
+        raise ValueError("dB must have the shape of B")
+    dA = torch.empty((n, m), dtype=torch.float64, device=A.device).t()
+    need = int(lib.qb_adjoint_workspace_bytes(m, n, int(b), int(blocks), int(power_iters)))
+    if need == 0:
+        raise QBError(_lib.QB_EINVAL, "qb_adjoint_workspace_bytes")
+    ws = _workspace(need, A.device)
+    code = lib.qb_adjoint(A.data_ptr(), m, n, lda, int(b), int(blocks), int(power_iters),
+                          int(seed) & 0xFFFFFFFFFFFFFFFF, Q.data_ptr(), ldq, B.data_ptr(), ldb,
+                          pdq, lddq, pdb, lddb, dA.data_ptr(), _ld(dA, "dA"), _aligned_ptr(ws),
+                          need, _stream(A.device))
+    if code != _lib.QB_OK:
+        raise QBError(code, "qb_adjoint")
+    return dA
+
+
+def qb_fixed(A, b: int, blocks: int, power_iters: int, seed: int):
+    """The fixed-sketch map A -> (Q, B): qb_factor with eps = 0 and kmax =
+    blocks * b; raises unless it ran exactly `blocks` full blocks."""
+    res = qb_factor(A, 0.0, b, power_iters, seed, kmax=int(b) * int(blocks))
+    if res.k != int(b) * int(blocks) or res.blocks != int(blocks):
+        raise QBError(_lib.QB_RANK_EXHAUSTED, "qb_fixed: a block lost rank")
+    return res.Q, res.B
+
+
+class QBFunction(torch.autograd.Function):
+    """(Q, B) = QBFunction.apply(A, b, blocks, power_iters, seed): the
+    fixed-sketch QB map with its hand-written adjoint (qb_adjoint) as the
+    backward.  A may be float32 or float64 (column-major or not); it is
+    widened to a column-major float64 copy, Q and B are float64 and the
+    gradient is returned in A's dtype."""
+
+    @staticmethod
+    def forward(ctx, A, b, blocks, power_iters, seed):
+        A64 = colmajor(A.detach())
+        Q, B = qb_fixed(A64, b, blocks, power_iters, seed)
+        ctx.save_for_backward(A64, Q, B)
+        ctx.cfg = (int(b), int(blocks), int(power_iters), int(seed), A.dtype)
+        return Q, B
+
+    @staticmethod
+    def backward(ctx, gQ, gB):
+        A64, Q, B = ctx.saved_tensors
+        b, blocks, P, seed, dtype = ctx.cfg
+        dQ = None if gQ is None else colmajor(gQ)
+        dB = None if gB is None else colmajor(gB)
+        dA = qb_adjoint(A64, Q, B, dQ, dB, b, blocks, P, seed)
+        return dA.to(dtype), None, None, None, None

@@ -1,0 +1,119 @@
+"""GPU parity of the hand-written adjoint of the fixed-sketch QB map
+(qb_adjoint, QBFunction) with the float64 oracle gradient
+(oracle.adjoint.qb_fixed_vjp), with central finite differences of the GPU
+forward, and with torch's numerical Jacobian on a tiny case."""
+import numpy as np
+import pytest
+import torch
+
+import paper_1503_07157_amd as qbmi
+import synth
+from oracle.adjoint import qb_fixed_vjp
+from paper_1503_07157_amd._lib import QB_RANK_EXHAUSTED
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(x):
+    return qbmi.colmajor(torch.from_numpy(np.ascontiguousarray(x)).cuda())
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("P", [0, 1])
+@pytest.mark.parametrize("upstream", ["QB", "Q", "B"])
+def test_adjoint_matches_oracle(cuda, P, upstream):
+    m, n, b, s, seed = 300, 200, 16, 3, 21
+    A = synth.prescribed_svd(m, n, np.exp(-np.arange(1, n + 1) / 20.0), 5, 6)
+    g = np.random.default_rng(9)
+    dQ = g.standard_normal((m, b * s)) if upstream != "B" else None
+    dB = g.standard_normal((b * s, n)) if upstream != "Q" else None
+    Qo, Bo, dAo = qb_fixed_vjp(A, dQ if dQ is not None else np.zeros((m, b * s)),
+                               dB if dB is not None else np.zeros((b * s, n)), b, s, P, seed)
+    Ad = dev(A)
+    Q, B = qbmi.qb_fixed(Ad, b, s, P, seed)
+    assert np.linalg.norm(Q.cpu().numpy() - Qo) <= 1e-11
+    dA = qbmi.qb_adjoint(Ad, Q, B, None if dQ is None else dev(dQ), None if dB is None else dev(dB),
+                         b, s, P, seed).cpu().numpy()
+    e = rel(dA, dAo)
+    print(f"[case] P={P} upstream={upstream}: rel err vs oracle {e:.2e}", flush=True)
+    assert e <= 1e-10
+
+
+@pytest.mark.parametrize("P", [0, 1])
+def test_workload_fp32_loss(cuda, P):
+    """4096 x 2048 float32 A with s_j = exp(-j/100), b = 64, 4 blocks,
+    L = <G, Q B>: the autograd gradient against the float64 oracle (at the
+    float32 rounding of the returned gradient), and the float64 gradient
+    against the oracle (1e-10) and against central differences (h = 1e-3 on
+    unit directions, float64 forward) to 1e-6."""
+    m, n, b, s, seed = 4096, 2048, 64, 4, 77
+    A32 = synth.prescribed_svd(m, n, np.exp(-np.arange(1, n + 1) / 100.0), 31, 32).astype(np.float32)
+    A64 = A32.astype(np.float64)
+    G = np.random.default_rng(5).standard_normal((m, n))
+    Gd = dev(G)
+    # autograd through QBFunction on the float32 input
+    At = torch.from_numpy(np.asfortranarray(A32)).cuda().requires_grad_(True)
+    Q, B = qbmi.QBFunction.apply(At, b, s, P, seed)
+    L = (Gd * (Q @ B)).sum()
+    L.backward()
+    g32 = At.grad.double().cpu().numpy()
+    # oracle gradient of the same loss
+    Qn, Bn = Q.detach().cpu().numpy(), B.detach().cpu().numpy()
+    _, _, dAo = qb_fixed_vjp(A64, G @ Bn.T, Qn.T @ G, b, s, P, seed)
+    e32 = rel(g32, dAo)
+    # float64 gradient straight from the adjoint
+    Ad = dev(A64)
+    Q64, B64 = qbmi.qb_fixed(Ad, b, s, P, seed)
+    dQ = Gd @ B64.t()
+    dB = Q64.t() @ Gd
+    dA = qbmi.qb_adjoint(Ad, Q64, B64, qbmi.colmajor(dQ), qbmi.colmajor(dB), b, s, P, seed)
+    e64 = rel(dA.cpu().numpy(), dAo)
+    print(f"[case] workload P={P}: fp32 grad rel err {e32:.2e}, fp64 grad {e64:.2e}", flush=True)
+    assert e32 <= 1e-6
+    assert e64 <= 1e-10
+
+    def loss(X):
+        Qx, Bx = qbmi.qb_fixed(X, b, s, P, seed)
+        return float((Gd * (Qx @ Bx)).sum())
+
+    rng = np.random.default_rng(11)
+    gn = float(torch.linalg.norm(dA))
+    for t in range(2):
+        E = torch.from_numpy(rng.standard_normal((m, n))).cuda()
+        E /= torch.linalg.norm(E)
+        ad = float((dA * E).sum())
+        errs = {}
+        for h in (1e-3, 1e-4):
+            fd = (loss(qbmi.colmajor(Ad + h * E)) - loss(qbmi.colmajor(Ad - h * E))) / (2 * h)
+            errs[h] = abs(fd - ad) / gn
+            print(f"[case] workload P={P} dir {t} h={h:g}: fd {fd:.12e} adjoint {ad:.12e} "
+                  f"|fd - adj| / ||dA|| = {errs[h]:.2e}", flush=True)
+        assert errs[1e-3] <= 1e-6
+
+
+def test_gradcheck_tiny(cuda):
+    A = dev(synth.prescribed_svd(24, 16, np.exp(-np.arange(1, 17) / 4.0), 2, 3))
+    A.requires_grad_(True)
+
+    def f(X):
+        return qbmi.QBFunction.apply(X, 4, 2, 1, 13)
+
+    assert torch.autograd.gradcheck(f, (A,), eps=1e-6, atol=1e-6, rtol=1e-4)
+
+
+def test_rank_loss_is_reported(cuda):
+    """A rank-4 input with b = 8: the forward stops short (a column is
+    dropped) and the adjoint, whose recomputed sample A Omega_1 has rank 4,
+    reports the rank loss instead of returning a gradient."""
+    m, n = 120, 80
+    full = synth.prescribed_svd(m, n, np.linspace(1.0, 0.5, n), 1, 2)
+    low = synth.exact_rank(m, n, 4, 4)
+    Q, B = qbmi.qb_fixed(dev(full), 8, 1, 0, 3)
+    with pytest.raises(qbmi.QBError):
+        qbmi.qb_fixed(dev(low), 8, 1, 0, 3)
+    with pytest.raises(qbmi.QBError) as ei:
+        qbmi.qb_adjoint(dev(low), Q, B, torch.ones_like(Q), None, 8, 1, 0, 3)
+    assert ei.value.code == QB_RANK_EXHAUSTED
