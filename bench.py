@@ -285,6 +285,16 @@ def batched_experiment(steps, warmup, no_cpu):
     kern = {name: {"ms": round(v["ms"], 3), "launches": v["launches"],
                    **({"tflops": round(v["flops"] / v["ms"] / 1e9, 2)} if v["flops"] else {})}
             for name, v in prof.items()}
+    # critical path: the problem that needs the most block iterations, alone
+    slow = max(range(len(specs)), key=lambda i: nblk[i])
+    qbmi.qb_factor_batched([As[slow]], [eps[slow]], [bs[slow]], [seeds[slow]])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    qbmi.qb_factor_batched([As[slow]], [eps[slow]], [bs[slow]], [seeds[slow]])
+    torch.cuda.synchronize()
+    tail = time.perf_counter() - t0
+    log(f"[bench] batched: the {nblk[slow]}-iteration problem alone ({specs[slow].m}x{specs[slow].n}, "
+        f"b={bs[slow]}) takes {tail * 1e3:.1f} ms")
     # the same problems one by one through the single-matrix path (float64 input)
     seq = 0.0
     same_k = 0
@@ -332,6 +342,7 @@ def batched_experiment(steps, warmup, no_cpu):
                       "gflops": flops / sec / 1e9, "nominal_flops": flops,
                       "k_min": min(ks), "k_max": max(ks), "k_total": sum(ks),
                       "errors": len(bad), "iterations": len(active), "active_per_iteration": active,
+                      "longest_problem_alone_seconds": tail,
                       "one_by_one_seconds": seq,
                       "one_by_one_same_k": same_k, "kernels": kern, "parity": parity,
                       "cpu_baseline": cpu, "dtype": "f32 input, f64 arithmetic",

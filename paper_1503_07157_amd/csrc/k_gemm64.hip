@@ -62,6 +62,13 @@ struct Shape {
 using Big = Shape<128, 128>;
 using Small = Shape<64, 64>;
 using Tall = Shape<256, 128, 4, 2>;
+// Batched Gram matrices of panels w <= 16 or 32 wide: the tile matches the
+// w x w output, so neither side of the MFMA work is padded to 64.  (Tiles
+// narrow on one side only, 128 x 16 for R Omega or 16 x 128 for Q_i^T R,
+// measured no faster than 64 x 64 there: those products stream R and are
+// not bound by the padded MFMA work.)
+using BatchG16 = Shape<16, 16, 1, 1>;
+using BatchG32 = Shape<32, 32, 2, 2>;
 static_assert(Big::BM == kTileM && Big::BN == kTileN, "tile constants");
 
 // A is "m-contiguous" when element (m, k) lies at X[m + k*ld] (column-major
@@ -600,6 +607,17 @@ __global__ __launch_bounds__(S::NT, S::OCC) void gemm_batched_kernel(
   const int64_t M = g.M, N = g.N, K = g.K;
   const int64_t kbeg = kz * g.kchunk;
   const int64_t kend = kbeg + g.kchunk < K ? kbeg + g.kchunk : K;
+  // the old C of a downdate (or of an NN product with beta) is read before
+  // the MMA loop, so its latency overlaps the operand loads
+  const bool vc = vec_ok_dev(g.C, g.ldc);
+  const bool need = g.ksplit == 1 && ((OP == kBatchDD) || (OP == kBatchNN && g.beta != 0.0));
+  d4 old[S::IB][S::JB];
+#pragma unroll
+  for (int i = 0; i < S::IB; ++i)
+#pragma unroll
+    for (int j = 0; j < S::JB; ++j)
+      old[i][j] = need ? load4(g.C, g.ldc, m0 + acc_row0<S>(i), n0 + acc_col<S>(j), M, N, vc)
+                       : (d4){0.0, 0.0, 0.0, 0.0};
   d4 acc[S::IB][S::JB];
   mma_loop<S, OP == kBatchTN>(g.A, g.lda, g.B, g.ldb, m0, n0, M, N, kbeg, kend, g.vec != 0, As,
                               Bs, acc);
@@ -616,25 +634,17 @@ __global__ __launch_bounds__(S::NT, S::OCC) void gemm_batched_kernel(
         store4(P, ldp, m0 + acc_row0<S>(i), n0 + acc_col<S>(j), ldp, np, true, acc[i][j]);
     return;
   }
-  const bool vc = vec_ok_dev(g.C, g.ldc);
   double sq = 0.0;
 #pragma unroll
   for (int i = 0; i < S::IB; ++i) {
     const int64_t row0 = m0 + acc_row0<S>(i);
-    d4 old[S::JB];
-#pragma unroll
-    for (int j = 0; j < S::JB; ++j) {
-      const bool need = (OP == kBatchDD) || (OP == kBatchNN && g.beta != 0.0);
-      old[j] = need ? load4(g.C, g.ldc, row0, n0 + acc_col<S>(j), M, N, vc)
-                    : (d4){0.0, 0.0, 0.0, 0.0};
-    }
 #pragma unroll
     for (int j = 0; j < S::JB; ++j) {
       const int64_t col = n0 + acc_col<S>(j);
       d4 v;
-      if (OP == kBatchNN) v = g.alpha * acc[i][j] + g.beta * old[j];
+      if (OP == kBatchNN) v = g.alpha * acc[i][j] + g.beta * old[i][j];
       else if (OP == kBatchTN) v = acc[i][j];
-      else v = old[j] - acc[i][j];
+      else v = old[i][j] - acc[i][j];
       store4(g.C, g.ldc, row0, col, M, N, vc, v);
 #pragma unroll
       for (int r = 0; r < 4; ++r)
@@ -663,8 +673,8 @@ __global__ __launch_bounds__(256) void gemm_batched_reduce_kernel(
   const BatchGemm g = desc[lo];
   const int64_t rb = blk - g.rblock0;
   const int64_t M = g.M, total = M * g.N;
-  const int64_t ldp = static_cast<int64_t>(g.tiles_m) * kBatchTile;
-  const int64_t slot = ldp * (static_cast<int64_t>(g.tiles_n) * kBatchTile);
+  const int64_t ldp = static_cast<int64_t>(g.tiles_m) * g.bm;
+  const int64_t slot = ldp * (static_cast<int64_t>(g.tiles_n) * g.bn);
   double sq = 0.0;
 #pragma unroll
   for (int q = 0; q < kBatchRed / 256; ++q) {
@@ -855,19 +865,37 @@ int downdate(double* R, int64_t ldr, const double* Qm, int64_t ldq, const double
   return kOk;
 }
 
-int gemm_batched(int op, const BatchGemm* desc, int count, int64_t total_tiles, int prof_id,
-                 double flops, hipStream_t s) {
-  if (count <= 0 || total_tiles <= 0) return kOk;
-  using S = Small;
-  static_assert(S::BM == kBatchTile && S::BN == kBatchTile, "batched tile");
+namespace {
+template <class S>
+void launch_batched(int op, const BatchGemm* desc, int count, int64_t total_tiles, hipStream_t s) {
   const dim3 grid(static_cast<unsigned>(total_tiles));
-  ProfScope ps(prof_id, flops, 0.0, s);
   if (op == kBatchNN)
     hipLaunchKernelGGL((gemm_batched_kernel<S, kBatchNN>), grid, dim3(S::NT), 0, s, desc, count);
   else if (op == kBatchTN)
     hipLaunchKernelGGL((gemm_batched_kernel<S, kBatchTN>), grid, dim3(S::NT), 0, s, desc, count);
   else
     hipLaunchKernelGGL((gemm_batched_kernel<S, kBatchDD>), grid, dim3(S::NT), 0, s, desc, count);
+}
+}  // namespace
+
+void batch_tile_dims(int cls, int* bm, int* bn) {
+  switch (cls) {
+    case kTileG16: *bm = BatchG16::BM; *bn = BatchG16::BN; return;
+    case kTileG32: *bm = BatchG32::BM; *bn = BatchG32::BN; return;
+    default: *bm = Small::BM; *bn = Small::BN; return;
+  }
+}
+
+int gemm_batched(int op, int cls, const BatchGemm* desc, int count, int64_t total_tiles,
+                 int prof_id, double flops, hipStream_t s) {
+  if (count <= 0 || total_tiles <= 0) return kOk;
+  if (op == kBatchDD && cls != kTile64) return kEInval;
+  ProfScope ps(prof_id, flops, 0.0, s);
+  switch (cls) {
+    case kTileG16: launch_batched<BatchG16>(op, desc, count, total_tiles, s); break;
+    case kTileG32: launch_batched<BatchG32>(op, desc, count, total_tiles, s); break;
+    default: launch_batched<Small>(op, desc, count, total_tiles, s); break;
+  }
   QB_HIP_TRY(hipGetLastError());
   return kOk;
 }

@@ -163,10 +163,13 @@ struct Stage {
   }
 };
 
+// tile class of the w x w Gram of a panel; every other product takes 64 x 64
+int cls_g(int w) { return w <= 16 ? kTileG16 : w <= 32 ? kTileG32 : kTile64; }
+
 // part: the problem's split-K buffer (kPartDoubles), or null for no split
-BatchGemm gemm_desc(const double* A, int64_t lda, const double* B, int64_t ldb, double* C,
-                    int64_t ldc, int64_t M, int64_t N, int64_t K, double alpha, double beta,
-                    double* sq, double* part) {
+BatchGemm gemm_desc(int cls, const double* A, int64_t lda, const double* B, int64_t ldb,
+                    double* C, int64_t ldc, int64_t M, int64_t N, int64_t K, double alpha,
+                    double beta, double* sq, double* part) {
   BatchGemm g{};
   g.A = A;
   g.B = B;
@@ -178,8 +181,13 @@ BatchGemm gemm_desc(const double* A, int64_t lda, const double* B, int64_t ldb, 
   g.M = static_cast<int32_t>(M);
   g.N = static_cast<int32_t>(N);
   g.K = static_cast<int32_t>(K);
-  g.tiles_m = static_cast<int32_t>(cdiv(M, kBatchTile));
-  g.tiles_n = static_cast<int32_t>(cdiv(N, kBatchTile));
+  int bm = kBatchTile, bn = kBatchTile;
+  batch_tile_dims(cls, &bm, &bn);
+  g.cls = cls;
+  g.bm = bm;
+  g.bn = bn;
+  g.tiles_m = static_cast<int32_t>(cdiv(M, bm));
+  g.tiles_n = static_cast<int32_t>(cdiv(N, bn));
   const bool va = (reinterpret_cast<uintptr_t>(A) & 15) == 0 && (lda & 1) == 0;
   const bool vb = (reinterpret_cast<uintptr_t>(B) & 15) == 0 && (ldb & 1) == 0;
   g.vec = (va && vb) ? 1 : 0;
@@ -193,7 +201,7 @@ BatchGemm gemm_desc(const double* A, int64_t lda, const double* B, int64_t ldb, 
     int64_t ks = std::min(cdiv(kSplitTiles, tiles), K / kSplitChunk);
     const int64_t chunk = cdiv(cdiv(K, ks), kTileK) * kTileK;
     ks = cdiv(K, chunk);
-    if (ks > 1 && ks * tiles * kBatchTile * kBatchTile <= kPartDoubles) {
+    if (ks > 1 && ks * tiles * bm * bn <= kPartDoubles) {
       g.ksplit = static_cast<int32_t>(ks);
       g.kchunk = static_cast<int32_t>(chunk);
       g.part = part;
@@ -202,24 +210,43 @@ BatchGemm gemm_desc(const double* A, int64_t lda, const double* B, int64_t ldb, 
   return g;
 }
 
-struct Grid {
-  int64_t tiles = 0, rblocks = 0;  // workgroups of the product and of its reduction
-};
-
 int64_t reduce_blocks(const BatchGemm& g) {
   return g.ksplit > 1 ? cdiv(static_cast<int64_t>(g.M) * g.N, kBatchRed) : 0;
 }
 
-// workgroup offsets of every problem in the product and reduce launches
-Grid place_tiles(std::vector<BatchGemm>& v) {
-  Grid t;
-  for (auto& g : v) {
-    g.tile0 = t.tiles;
-    g.rblock0 = t.rblocks;
-    t.tiles += static_cast<int64_t>(g.tiles_m) * g.tiles_n * g.ksplit;
-    t.rblocks += reduce_blocks(g);
+// One step's product over the active problems, grouped by tile class: one
+// launch per non-empty class (workgroup offsets tile0 within it), one
+// reduction launch over all (offsets rblock0).
+struct Step {
+  std::vector<BatchGemm> d;
+  int begin[kTileClasses + 1] = {};
+  int64_t tiles[kTileClasses] = {};
+  double flops[kTileClasses] = {};
+  int64_t rblocks = 0;
+  size_t off = 0;
+  int count() const { return static_cast<int>(d.size()); }
+};
+
+Step group(const std::vector<BatchGemm>& v) {
+  Step st;
+  st.d.reserve(v.size());
+  for (int c = 0; c < kTileClasses; ++c) {
+    st.begin[c] = st.count();
+    int64_t t = 0;
+    for (const BatchGemm& g : v) {
+      if (g.cls != c) continue;
+      BatchGemm h = g;
+      h.tile0 = t;
+      t += static_cast<int64_t>(h.tiles_m) * h.tiles_n * h.ksplit;
+      h.rblock0 = st.rblocks;
+      st.rblocks += reduce_blocks(h);
+      st.flops[c] += 2.0 * h.M * h.N * h.K;
+      st.d.push_back(h);
+    }
+    st.tiles[c] = t;
   }
-  return t;
+  st.begin[kTileClasses] = st.count();
+  return st;
 }
 
 // partial sums of squares that a TN product with sq leaves per problem
@@ -228,11 +255,6 @@ int32_t sq_count(const BatchGemm& g) {
                                            : static_cast<int64_t>(g.tiles_m) * g.tiles_n);
 }
 
-double flops_of(const std::vector<BatchGemm>& v) {
-  double f = 0.0;
-  for (const auto& g : v) f += 2.0 * g.M * g.N * g.K;
-  return f;
-}
 
 }  // namespace
 }  // namespace qb
@@ -370,17 +392,16 @@ int qb_factor_batched(qb_problem* probs, int32_t count, void* workspace, size_t 
       std::vector<BatchGemm> gY(na);
       for (int a = 0; a < na; ++a) {
         const Prob& p = P[act[a]];
-        gY[a] = gemm_desc(p.R, p.ldr, p.omega, p.n, p.Y, p.ldm, p.m, p.w, p.n, 1.0, 0.0, nullptr,
-                          p.part);
+        gY[a] = gemm_desc(kTile64, p.R, p.ldr, p.omega, p.n, p.Y, p.ldm, p.m, p.w, p.n, 1.0,
+                          0.0, nullptr, p.part);
       }
-      const Grid tY = place_tiles(gY);
       // CholQR pass helpers: Gram, Cholesky, apply into dst
       auto gram = [&](const std::vector<int>& ids, double* const* X) {
         std::vector<BatchGemm> g(ids.size());
         for (size_t a = 0; a < ids.size(); ++a) {
           const Prob& p = P[ids[a]];
-          g[a] = gemm_desc(X[a], p.ldm, X[a], p.ldm, p.G, p.w, p.w, p.w, p.m, 1.0, 0.0, nullptr,
-                           p.part);
+          g[a] = gemm_desc(cls_g(p.w), X[a], p.ldm, X[a], p.ldm, p.G, p.w, p.w, p.w, p.m, 1.0,
+                           0.0, nullptr, p.part);
         }
         return g;
       };
@@ -397,8 +418,8 @@ int qb_factor_batched(qb_problem* probs, int32_t count, void* workspace, size_t 
         std::vector<BatchGemm> g(ids.size());
         for (size_t a = 0; a < ids.size(); ++a) {
           const Prob& p = P[ids[a]];
-          g[a] = gemm_desc(X[a], p.ldm, p.Tinv, p.w, D[a], ldd[a], p.m, p.w, p.w, 1.0, 0.0,
-                           nullptr, p.part);
+          g[a] = gemm_desc(kTile64, X[a], p.ldm, p.Tinv, p.w, D[a], ldd[a], p.m, p.w, p.w,
+                           1.0, 0.0, nullptr, p.part);
         }
         return g;
       };
@@ -422,8 +443,7 @@ int qb_factor_batched(qb_problem* probs, int32_t count, void* workspace, size_t 
       std::vector<BatchGemm> g1 = gram(act, xY.data()), a1 = apply(act, xY.data(), dQt.data(), lQt.data());
       std::vector<BatchGemm> g2 = gram(act, xQt.data()), a2 = apply(act, xQt.data(), d2.data(), l2.data());
       std::vector<BatchChol> c1 = chol(act);
-      const Grid tg1 = place_tiles(g1), ta1 = place_tiles(a1), tg2 = place_tiles(g2),
-                 ta2 = place_tiles(a2);
+
       // re-projection of the problems with k > 0, then CholQR2 into Q + k ldq
       std::vector<BatchGemm> rC(nr), rQ(nr);
       std::vector<double*> xQi(nr), dQt2(nr), xQt2(nr), dOut(nr);
@@ -431,10 +451,10 @@ int qb_factor_batched(qb_problem* probs, int32_t count, void* workspace, size_t 
       for (int a = 0; a < nr; ++a) {
         Prob& p = P[reproj[a]];
         qb_problem& q = probs[reproj[a]];
-        rC[a] = gemm_desc(q.Q, q.ldq, p.Qi, p.ldm, p.C, p.ldc, p.k, p.w, p.m, 1.0, 0.0, nullptr,
-                          p.part);
-        rQ[a] = gemm_desc(q.Q, q.ldq, p.C, p.ldc, p.Qi, p.ldm, p.m, p.w, p.k, -1.0, 1.0, nullptr,
-                          p.part);
+        rC[a] = gemm_desc(kTile64, q.Q, q.ldq, p.Qi, p.ldm, p.C, p.ldc, p.k, p.w, p.m, 1.0,
+                          0.0, nullptr, p.part);
+        rQ[a] = gemm_desc(kTile64, q.Q, q.ldq, p.C, p.ldc, p.Qi, p.ldm, p.m, p.w, p.k, -1.0,
+                          1.0, nullptr, p.part);
         xQi[a] = p.Qi;
         dQt2[a] = p.Qt;
         xQt2[a] = p.Qt;
@@ -445,8 +465,7 @@ int qb_factor_batched(qb_problem* probs, int32_t count, void* workspace, size_t 
       std::vector<BatchGemm> g3 = gram(reproj, xQi.data()), a3 = apply(reproj, xQi.data(), dQt2.data(), lQt2.data());
       std::vector<BatchGemm> g4 = gram(reproj, xQt2.data()), a4 = apply(reproj, xQt2.data(), dOut.data(), lOut.data());
       std::vector<BatchChol> c3 = chol(reproj);
-      const Grid trC = place_tiles(rC), trQ = place_tiles(rQ), tg3 = place_tiles(g3),
-                 ta3 = place_tiles(a3), tg4 = place_tiles(g4), ta4 = place_tiles(a4);
+
       // B_i = Q_i^T R with ||B_i||^2, R -= Q_i B_i with ||R||^2, sums
       std::vector<BatchGemm> gB(na), gD(na);
       std::vector<BatchSum> sB(na), sR(na);
@@ -455,53 +474,64 @@ int qb_factor_batched(qb_problem* probs, int32_t count, void* workspace, size_t 
         qb_problem& q = probs[act[a]];
         double* Qo = q.Q + p.k * q.ldq;
         double* Bo = q.B + p.k;
-        gB[a] = gemm_desc(Qo, q.ldq, p.R, p.ldr, Bo, q.ldb, p.w, p.n, p.m, 1.0, 0.0, p.sqB,
-                          p.part);
-        gD[a] = gemm_desc(Qo, q.ldq, Bo, q.ldb, p.R, p.ldr, p.m, p.n, p.w, 1.0, 0.0, p.sqR,
-                          nullptr);
+        gB[a] = gemm_desc(kTile64, Qo, q.ldq, p.R, p.ldr, Bo, q.ldb, p.w, p.n, p.m, 1.0, 0.0,
+                          p.sqB, p.part);
+        gD[a] = gemm_desc(kTile64, Qo, q.ldq, Bo, q.ldb, p.R, p.ldr, p.m, p.n, p.w, 1.0, 0.0,
+                          p.sqR, nullptr);
         sB[a] = BatchSum{p.sqB, nullptr, p.scal + 2, nullptr, sq_count(gB[a])};
         sR[a] = BatchSum{p.sqR, nullptr, p.scal + 0, nullptr,
                          static_cast<int32_t>(cdiv(p.m, kBatchTile) * cdiv(p.n, kBatchTile))};
       }
-      const Grid tB = place_tiles(gB), tD = place_tiles(gD);
 
-      const size_t osk = sg.put(sk), oY = sg.put(gY), og1 = sg.put(g1), oc1 = sg.put(c1),
-                   oa1 = sg.put(a1), og2 = sg.put(g2), oa2 = sg.put(a2);
-      const size_t orC = nr ? sg.put(rC) : 0, orQ = nr ? sg.put(rQ) : 0,
-                   og3 = nr ? sg.put(g3) : 0, oc3 = nr ? sg.put(c3) : 0,
-                   oa3 = nr ? sg.put(a3) : 0, og4 = nr ? sg.put(g4) : 0,
-                   oa4 = nr ? sg.put(a4) : 0;
-      const size_t oB = sg.put(gB), oD = sg.put(gD), osB = sg.put(sB), osR = sg.put(sR);
+
+      Step sY = group(gY), s1 = group(g1), sa1 = group(a1), s2 = group(g2), sa2 = group(a2);
+      Step srC = group(rC), srQ = group(rQ), s3 = group(g3), sa3 = group(a3), s4 = group(g4),
+           sa4 = group(a4);
+      Step sBB = group(gB), sDD = group(gD);
+      const size_t osk = sg.put(sk);
+      for (Step* x : {&sY, &s1, &sa1, &s2, &sa2}) x->off = sg.put(x->d);
+      const size_t oc1 = sg.put(c1);
+      size_t oc3 = 0;
+      if (nr) {
+        for (Step* x : {&srC, &srQ, &s3, &sa3, &s4, &sa4}) x->off = sg.put(x->d);
+        oc3 = sg.put(c3);
+      }
+      sBB.off = sg.put(sBB.d);
+      sDD.off = sg.put(sDD.d);
+      const size_t osB = sg.put(sB), osR = sg.put(sR);
       if (sg.overflow) return QB_EWORKSPACE;
       auto G = [&](size_t off) { return reinterpret_cast<const BatchGemm*>(dev(off)); };
       auto Ch = [&](size_t off) { return reinterpret_cast<const BatchChol*>(dev(off)); };
       int e = upload();
       e = e || sketch_batched(reinterpret_cast<const BatchSketch*>(dev(osk)), na, skb, st);
-      auto mm = [&](int op, size_t off, const std::vector<BatchGemm>& v, const Grid& t,
-                    int pid) -> int {
-        const int c = static_cast<int>(v.size());
-        if (gemm_batched(op, G(off), c, t.tiles, pid, flops_of(v), st)) return 1;
-        return gemm_batched_reduce(op, G(off), c, t.rblocks, pid, st) ? 1 : 0;
+      auto mm = [&](int op, const Step& x, int pid) -> int {
+        for (int c = 0; c < kTileClasses; ++c) {
+          const int cnt = x.begin[c + 1] - x.begin[c];
+          if (cnt == 0) continue;
+          if (gemm_batched(op, c, G(x.off) + x.begin[c], cnt, x.tiles[c], pid, x.flops[c], st))
+            return 1;
+        }
+        return gemm_batched_reduce(op, G(x.off), x.count(), x.rblocks, pid, st) ? 1 : 0;
       };
-      e = e || mm(kBatchNN, oY, gY, tY, kKBatchSample);
-      e = e || mm(kBatchTN, og1, g1, tg1, kKBatchGram);
+      e = e || mm(kBatchNN, sY, kKBatchSample);
+      e = e || mm(kBatchTN, s1, kKBatchGram);
       e = e || chol_inv_batched(Ch(oc1), na, st);
-      e = e || mm(kBatchNN, oa1, a1, ta1, kKBatchApply);
-      e = e || mm(kBatchTN, og2, g2, tg2, kKBatchGram);
+      e = e || mm(kBatchNN, sa1, kKBatchApply);
+      e = e || mm(kBatchTN, s2, kKBatchGram);
       e = e || chol_inv_batched(Ch(oc1), na, st);
-      e = e || mm(kBatchNN, oa2, a2, ta2, kKBatchApply);
+      e = e || mm(kBatchNN, sa2, kKBatchApply);
       if (nr) {
-        e = e || mm(kBatchTN, orC, rC, trC, kKBatchReproj);
-        e = e || mm(kBatchNN, orQ, rQ, trQ, kKBatchReproj);
-        e = e || mm(kBatchTN, og3, g3, tg3, kKBatchGram);
+        e = e || mm(kBatchTN, srC, kKBatchReproj);
+        e = e || mm(kBatchNN, srQ, kKBatchReproj);
+        e = e || mm(kBatchTN, s3, kKBatchGram);
         e = e || chol_inv_batched(Ch(oc3), nr, st);
-        e = e || mm(kBatchNN, oa3, a3, ta3, kKBatchApply);
-        e = e || mm(kBatchTN, og4, g4, tg4, kKBatchGram);
+        e = e || mm(kBatchNN, sa3, kKBatchApply);
+        e = e || mm(kBatchTN, s4, kKBatchGram);
         e = e || chol_inv_batched(Ch(oc3), nr, st);
-        e = e || mm(kBatchNN, oa4, a4, ta4, kKBatchApply);
+        e = e || mm(kBatchNN, sa4, kKBatchApply);
       }
-      e = e || mm(kBatchTN, oB, gB, tB, kKBatchB);
-      e = e || mm(kBatchDD, oD, gD, tD, kKBatchDowndate);
+      e = e || mm(kBatchTN, sBB, kKBatchB);
+      e = e || mm(kBatchDD, sDD, kKBatchDowndate);
       e = e || sum_batched(reinterpret_cast<const BatchSum*>(dev(osB)), na, st);
       e = e || sum_batched(reinterpret_cast<const BatchSum*>(dev(osR)), na, st);
       e = e || fetch();

@@ -139,32 +139,39 @@ int zero_matrix(double* Y, int64_t ldy, int64_t M, int64_t N, hipStream_t s);
 // + beta C; op TN: C(M x N) = A(K x M)^T B(K x N) (sq: per-tile sums of
 // squares of C, or null); op DD: C(M x N) -= A(M x K) B(K x N) with per-tile
 // sums of squares of the updated C into sq.  Workgroups [tile0, tile0 +
-// tiles_m * tiles_n) of the launch belong to this problem.
+// tiles_m * tiles_n * ksplit) of the launch belong to this problem; every
+// problem of one launch has the launch's tile class.
 struct BatchGemm {
   const double* A;
   const double* B;
   double* C;
   double* sq;
-  double* part;    // split-K partial tiles, ksplit slots of ldp x (tiles_n * 64)
+  double* part;    // split-K partial tiles, ksplit slots of (tiles_m bm) x (tiles_n bn)
   int64_t lda, ldb, ldc;
   int64_t tile0;   // first workgroup of this problem in the product launch
   int64_t rblock0; // first workgroup of this problem in the reduce launch
   int32_t M, N, K;
   int32_t tiles_m, tiles_n;
   int32_t ksplit, kchunk;  // depth split: ksplit chunks of kchunk (a multiple of kTileK)
+  int32_t bm, bn;          // output tile of the launch this problem belongs to
+  int32_t cls;             // its tile class (host bookkeeping)
   int32_t vec;  // A and B 16-byte aligned with even leading dimensions
   double alpha, beta;
 };
 enum { kBatchNN = 0, kBatchTN = 1, kBatchDD = 2 };
-constexpr int kBatchTile = 64;      // batched products use 64 x 64 output tiles
+constexpr int kBatchTile = 64;      // the default (and downdate) tile of batched products
+// tile classes of batched products: 64 x 64, and 16 x 16 / 32 x 32 for the
+// Gram matrices of narrow panels
+enum { kTile64 = 0, kTileG16, kTileG32, kTileClasses };
+void batch_tile_dims(int cls, int* bm, int* bn);
 constexpr int kBatchRed = 1024;     // elements per workgroup of the split-K reduction
 // prof_id, flops: the profiler entry and the launch's algorithmic count (sum of 2 M N K).
 // total_tiles counts every (tile, depth chunk) workgroup.  Problems with
 // ksplit > 1 leave C to gemm_batched_reduce, which sums their chunks in
 // order (alpha sum + beta C for NN, the sum for TN) with per-workgroup sums
 // of squares into sq when sq is set; total_rblocks counts its workgroups.
-int gemm_batched(int op, const BatchGemm* desc, int count, int64_t total_tiles, int prof_id,
-                 double flops, hipStream_t s);
+int gemm_batched(int op, int cls, const BatchGemm* desc, int count, int64_t total_tiles,
+                 int prof_id, double flops, hipStream_t s);
 int gemm_batched_reduce(int op, const BatchGemm* desc, int count, int64_t total_rblocks,
                         int prof_id, hipStream_t s);
 
