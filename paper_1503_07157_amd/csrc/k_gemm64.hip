@@ -65,8 +65,9 @@ using Tall = Shape<256, 128, 4, 2>;
 // Batched Gram matrices of panels w <= 16 or 32 wide: the tile matches the
 // w x w output, so neither side of the MFMA work is padded to 64.  (Tiles
 // narrow on one side only, 128 x 16 for R Omega or 16 x 128 for Q_i^T R,
-// measured no faster than 64 x 64 there: those products stream R and are
-// not bound by the padded MFMA work.)
+// measured no faster than 64 x 64 there, and 256 x 64 for R Omega 60 %
+// slower: those products are bound by the latency of their depth loops,
+// and 64 x 64 tiles give the most workgroups.)
 using BatchG16 = Shape<16, 16, 1, 1>;
 using BatchG32 = Shape<32, 32, 2, 2>;
 static_assert(Big::BM == kTileM && Big::BN == kTileN, "tile constants");
