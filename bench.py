@@ -94,8 +94,9 @@ def run_variant(qbmi, lib, torch, A, eps, wl, P, sample, steps, warmup, bufs, pr
 def committed_traffic(kernel):
     """HBM bytes per launch of `kernel` from a committed rocprofv3 counter
     summary under profiles/ (FETCH_SIZE + WRITE_SIZE, copy-kernel scaled).
-    None unless the summary's kernel source hash matches the current file:
-    counters taken on an older kernel say nothing about this one."""
+    None unless the SHA-256 of every source file the summary names matches
+    the current file: counters taken on an older kernel say nothing about
+    this one."""
     import glob
     import hashlib
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
@@ -107,13 +108,22 @@ def committed_traffic(kernel):
                 kv = dict(p.split("=", 1) for p in parts[1:] if "=" in p)
                 if kv.get("kernel") != kernel:
                     continue
-                src = os.path.join(ROOT, kv.get("source", ""))
-                if not os.path.isfile(src):
+                srcs = kv.get("source", "").split(",")
+                shas = kv.get("sha256", "").split(",")
+                if len(srcs) != len(shas) or not srcs[0]:
                     continue
-                with open(src, "rb") as g:
-                    if hashlib.sha256(g.read()).hexdigest() != kv.get("sha256"):
-                        continue
-                return float(kv["bytes_per_launch"]), os.path.relpath(path, ROOT)
+                ok = True
+                for src, sha in zip(srcs, shas):
+                    fp = os.path.join(ROOT, src)
+                    if not os.path.isfile(fp):
+                        ok = False
+                        break
+                    with open(fp, "rb") as g:
+                        if hashlib.sha256(g.read()).hexdigest() != sha:
+                            ok = False
+                            break
+                if ok:
+                    return float(kv["bytes_per_launch"]), os.path.relpath(path, ROOT)
     return None, None
 
 

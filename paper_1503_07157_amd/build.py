@@ -31,7 +31,8 @@ COMMON = [
 PER_FILE = {
     "k_sketch.hip": ["-ffp-contract=off"],
 }
-SOURCES = ["k_sketch.hip", "k_gemm64.hip", "k_gemm_lowp.hip", "k_orth.hip", "k_misc.hip", "qb_api.hip",
+SOURCES = ["k_sketch.hip", "k_gemm64.hip", "k_gemm_batched.hip", "k_gemm_lowp.hip", "k_orth.hip",
+           "k_misc.hip", "qb_api.hip",
            "k_post.hip", "qb_batch.hip", "qb_adjoint.hip", "prof.hip"]
 
 

@@ -1,0 +1,184 @@
+// Batched FP64 MFMA products: every active problem's product of one step of
+// the batched block loop in one launch.  Workgroup -> (problem, tile, depth
+// chunk) by binary search over the problems' first workgroup indices; the
+// tile loop and epilogues are those of the single-matrix kernels
+// (gemm_tiles.hpp).  Problems whose product is split over depth chunks
+// leave their partial tiles to gemm_batched_reduce, which sums them in chunk
+// order, so results are bitwise reproducible.
+#include "gemm_tiles.hpp"
+
+namespace qb {
+namespace {
+
+// Batched Gram matrices of panels w <= 16 or 32 wide: the tile matches the
+// w x w output, so neither side of the MFMA work is padded to 64.  (Tiles
+// narrow on one side only, 128 x 16 for R Omega or 16 x 128 for Q_i^T R,
+// measured no faster than 64 x 64 there, and 256 x 64 for R Omega 60 %
+// slower: those products are bound by the latency of their depth loops,
+// and 64 x 64 tiles give the most workgroups.)
+using BatchG16 = Shape<16, 16, 1, 1>;
+using BatchG32 = Shape<32, 32, 2, 2>;
+
+template <class S, int OP>
+__global__ __launch_bounds__(S::NT, S::OCC) void gemm_batched_kernel(
+    const BatchGemm* __restrict__ desc, int count) {
+  __shared__ __attribute__((aligned(16))) double As[2 * S::A_LDS];
+  __shared__ __attribute__((aligned(16))) double Bs[2 * S::B_LDS];
+  __shared__ double red[S::NT / 64];
+  const int64_t blk = blockIdx.x;
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {  // last problem with tile0 <= blk
+    const int mid = (lo + hi + 1) >> 1;
+    if (desc[mid].tile0 <= blk) lo = mid;
+    else hi = mid - 1;
+  }
+  const BatchGemm g = desc[lo];
+  const int64_t tiles = static_cast<int64_t>(g.tiles_m) * g.tiles_n;
+  const int64_t u = blk - g.tile0;
+  const int64_t kz = u / tiles, t = u - kz * tiles;
+  const int64_t m0 = (t % g.tiles_m) * S::BM;
+  const int64_t n0 = (t / g.tiles_m) * S::BN;
+  const int64_t M = g.M, N = g.N, K = g.K;
+  const int64_t kbeg = kz * g.kchunk;
+  const int64_t kend = kbeg + g.kchunk < K ? kbeg + g.kchunk : K;
+  // the old C of a downdate (or of an NN product with beta) is read before
+  // the MMA loop, so its latency overlaps the operand loads
+  const bool vc = vec_ok_dev(g.C, g.ldc);
+  const bool need = g.ksplit == 1 && ((OP == kBatchDD) || (OP == kBatchNN && g.beta != 0.0));
+  d4 old[S::IB][S::JB];
+#pragma unroll
+  for (int i = 0; i < S::IB; ++i)
+#pragma unroll
+    for (int j = 0; j < S::JB; ++j)
+      old[i][j] = need ? load4(g.C, g.ldc, m0 + acc_row0<S>(i), n0 + acc_col<S>(j), M, N, vc)
+                       : (d4){0.0, 0.0, 0.0, 0.0};
+  d4 acc[S::IB][S::JB];
+  mma_loop<S, OP == kBatchTN>(g.A, g.lda, g.B, g.ldb, m0, n0, M, N, kbeg, kend, g.vec != 0, As,
+                              Bs, acc);
+  if (g.ksplit > 1) {
+    // whole padded tile into this chunk's slot; rows and columns past M, N
+    // hold zeros (out-of-range operands load as zero)
+    const int64_t ldp = static_cast<int64_t>(g.tiles_m) * S::BM;
+    const int64_t np = static_cast<int64_t>(g.tiles_n) * S::BN;
+    double* P = g.part + kz * ldp * np;
+#pragma unroll
+    for (int i = 0; i < S::IB; ++i)
+#pragma unroll
+      for (int j = 0; j < S::JB; ++j)
+        store4(P, ldp, m0 + acc_row0<S>(i), n0 + acc_col<S>(j), ldp, np, true, acc[i][j]);
+    return;
+  }
+  double sq = 0.0;
+#pragma unroll
+  for (int i = 0; i < S::IB; ++i) {
+    const int64_t row0 = m0 + acc_row0<S>(i);
+#pragma unroll
+    for (int j = 0; j < S::JB; ++j) {
+      const int64_t col = n0 + acc_col<S>(j);
+      d4 v;
+      if (OP == kBatchNN) v = g.alpha * acc[i][j] + g.beta * old[i][j];
+      else if (OP == kBatchTN) v = acc[i][j];
+      else v = old[i][j] - acc[i][j];
+      store4(g.C, g.ldc, row0, col, M, N, vc, v);
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (row0 + r < M && col < N) sq += v[r] * v[r];
+    }
+  }
+  if (OP != kBatchNN && g.sq != nullptr) {
+    const double tot = block_sum(sq, red);
+    if (threadIdx.x == 0) g.sq[t] = tot;
+  }
+}
+
+// C from the depth chunks of the problems with ksplit > 1, in chunk order;
+// kBatchRed elements of C per workgroup
+template <int OP>
+__global__ __launch_bounds__(256) void gemm_batched_reduce_kernel(
+    const BatchGemm* __restrict__ desc, int count) {
+  __shared__ double red[4];
+  const int64_t blk = blockIdx.x;
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {  // last problem with rblock0 <= blk
+    const int mid = (lo + hi + 1) >> 1;
+    if (desc[mid].rblock0 <= blk) lo = mid;
+    else hi = mid - 1;
+  }
+  const BatchGemm g = desc[lo];
+  const int64_t rb = blk - g.rblock0;
+  const int64_t M = g.M, total = M * g.N;
+  const int64_t ldp = static_cast<int64_t>(g.tiles_m) * g.bm;
+  const int64_t slot = ldp * (static_cast<int64_t>(g.tiles_n) * g.bn);
+  double sq = 0.0;
+#pragma unroll
+  for (int q = 0; q < kBatchRed / 256; ++q) {
+    const int64_t e = rb * kBatchRed + q * 256 + threadIdx.x;
+    if (e < total) {
+      const int64_t i = e % M, j = e / M;
+      const double* p = g.part + i + j * ldp;
+      double v = 0.0;
+      for (int z = 0; z < g.ksplit; ++z) v += p[z * slot];
+      double* c = g.C + i + j * g.ldc;
+      if (OP == kBatchNN) v = g.alpha * v + (g.beta != 0.0 ? g.beta * *c : 0.0);
+      *c = v;
+      sq += v * v;
+    }
+  }
+  if (g.sq != nullptr) {
+    const double tot = block_sum(sq, red);
+    if (threadIdx.x == 0) g.sq[rb] = tot;
+  }
+}
+
+}  // namespace
+
+namespace {
+template <class S>
+void launch_batched(int op, const BatchGemm* desc, int count, int64_t total_tiles, hipStream_t s) {
+  const dim3 grid(static_cast<unsigned>(total_tiles));
+  if (op == kBatchNN)
+    hipLaunchKernelGGL((gemm_batched_kernel<S, kBatchNN>), grid, dim3(S::NT), 0, s, desc, count);
+  else if (op == kBatchTN)
+    hipLaunchKernelGGL((gemm_batched_kernel<S, kBatchTN>), grid, dim3(S::NT), 0, s, desc, count);
+  else
+    hipLaunchKernelGGL((gemm_batched_kernel<S, kBatchDD>), grid, dim3(S::NT), 0, s, desc, count);
+}
+}  // namespace
+
+void batch_tile_dims(int cls, int* bm, int* bn) {
+  switch (cls) {
+    case kTileG16: *bm = BatchG16::BM; *bn = BatchG16::BN; return;
+    case kTileG32: *bm = BatchG32::BM; *bn = BatchG32::BN; return;
+    default: *bm = Small::BM; *bn = Small::BN; return;
+  }
+}
+
+int gemm_batched(int op, int cls, const BatchGemm* desc, int count, int64_t total_tiles,
+                 int prof_id, double flops, hipStream_t s) {
+  if (count <= 0 || total_tiles <= 0) return kOk;
+  if (op == kBatchDD && cls != kTile64) return kEInval;
+  ProfScope ps(prof_id, flops, 0.0, s);
+  switch (cls) {
+    case kTileG16: launch_batched<BatchG16>(op, desc, count, total_tiles, s); break;
+    case kTileG32: launch_batched<BatchG32>(op, desc, count, total_tiles, s); break;
+    default: launch_batched<Small>(op, desc, count, total_tiles, s); break;
+  }
+  QB_HIP_TRY(hipGetLastError());
+  return kOk;
+}
+
+int gemm_batched_reduce(int op, const BatchGemm* desc, int count, int64_t total_rblocks,
+                        int prof_id, hipStream_t s) {
+  if (count <= 0 || total_rblocks <= 0) return kOk;
+  if (op == kBatchDD) return kEInval;
+  const dim3 grid(static_cast<unsigned>(total_rblocks));
+  ProfScope ps(prof_id, 0.0, 0.0, s);
+  if (op == kBatchNN)
+    hipLaunchKernelGGL(gemm_batched_reduce_kernel<kBatchNN>, grid, dim3(256), 0, s, desc, count);
+  else
+    hipLaunchKernelGGL(gemm_batched_reduce_kernel<kBatchTN>, grid, dim3(256), 0, s, desc, count);
+  QB_HIP_TRY(hipGetLastError());
+  return kOk;
+}
+
+}  // namespace qb
