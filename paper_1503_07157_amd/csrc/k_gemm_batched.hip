@@ -15,7 +15,9 @@ namespace {
 // narrow on one side only, 128 x 16 for R Omega or 16 x 128 for Q_i^T R,
 // measured no faster than 64 x 64 there, and 256 x 64 for R Omega 60 %
 // slower: those products are bound by the latency of their depth loops,
-// and 64 x 64 tiles give the most workgroups.)
+// and 64 x 64 tiles give the most workgroups.  The batched downdate, a
+// stream over R, measured 69 ms per 512-problem batch with 64 x 64 tiles,
+// 75 ms with 32 x 32 and 178 ms with 128 x 128.)
 using BatchG16 = Shape<16, 16, 1, 1>;
 using BatchG32 = Shape<32, 32, 2, 2>;
 

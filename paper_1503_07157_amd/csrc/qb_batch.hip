@@ -482,8 +482,7 @@ int qb_factor_batched(qb_problem* probs, int32_t count, void* workspace, size_t 
         gD[a] = gemm_desc(kTile64, Qo, q.ldq, Bo, q.ldb, p.R, p.ldr, p.m, p.n, p.w, 1.0, 0.0,
                           p.sqR, nullptr);
         sB[a] = BatchSum{p.sqB, nullptr, p.scal + 2, nullptr, sq_count(gB[a])};
-        sR[a] = BatchSum{p.sqR, nullptr, p.scal + 0, nullptr,
-                         static_cast<int32_t>(cdiv(p.m, kBatchTile) * cdiv(p.n, kBatchTile))};
+        sR[a] = BatchSum{p.sqR, nullptr, p.scal + 0, nullptr, sq_count(gD[a])};
       }
 
 

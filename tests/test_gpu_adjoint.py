@@ -117,3 +117,14 @@ def test_rank_loss_is_reported(cuda):
     with pytest.raises(qbmi.QBError) as ei:
         qbmi.qb_adjoint(dev(low), Q, B, torch.ones_like(Q), None, 8, 1, 0, 3)
     assert ei.value.code == QB_RANK_EXHAUSTED
+
+
+def test_adjoint_bitwise_reproducible(cuda):
+    m, n, b, s = 500, 300, 32, 3
+    A = dev(synth.prescribed_svd(m, n, np.exp(-np.arange(1, n + 1) / 30.0), 8, 9))
+    Q, B = qbmi.qb_fixed(A, b, s, 1, 4)
+    g = np.random.default_rng(2)
+    dQ, dB = dev(g.standard_normal((m, b * s))), dev(g.standard_normal((b * s, n)))
+    d1 = qbmi.qb_adjoint(A, Q, B, dQ, dB, b, s, 1, 4)
+    d2 = qbmi.qb_adjoint(A, Q, B, dQ, dB, b, s, 1, 4)
+    assert torch.equal(d1, d2)

@@ -103,3 +103,24 @@ def test_batch_full_distribution(cuda):
         assert res[i].k == o.k
         Qg, Bg = res[i].Q.cpu().numpy(), res[i].B.cpu().numpy()
         assert np.linalg.norm(Qg @ Bg - o.Q @ o.B) <= 1e-10 * nA[i]
+
+
+def test_batch_result_independent_of_batch_mates(cuda):
+    """The depth split of a problem's products depends only on its own
+    sizes, so a problem factorised inside a batch gives bitwise the same Q
+    and B as the same problem alone, and a repeated batch is bitwise
+    reproducible."""
+    specs = synth.batch_specs(count=10, seed=515, m_range=(300, 1500), n_max=800)
+    mats = [dev32(synth.batch_matrix(sp)) for sp in specs]
+    eps = [1e-5 * float(torch.linalg.norm(A, dtype=torch.float64)) for A in mats]
+    bs = [sp.b for sp in specs]
+    seeds = [sp.seed_omega for sp in specs]
+    full = qbmi.qb_factor_batched(mats, eps, bs, seeds)
+    again = qbmi.qb_factor_batched(mats, eps, bs, seeds)
+    for i in (0, 3, 7):
+        alone = qbmi.qb_factor_batched([mats[i]], [eps[i]], [bs[i]], [seeds[i]])[0]
+        print(f"[case] problem {i}: k batch {full[i].k} alone {alone.k}", flush=True)
+        assert alone.k == full[i].k
+        assert torch.equal(alone.Q, full[i].Q) and torch.equal(alone.B, full[i].B)
+    for r1, r2 in zip(full, again):
+        assert r1.k == r2.k and torch.equal(r1.Q, r2.Q) and torch.equal(r1.B, r2.B)
