@@ -83,3 +83,55 @@ def test_invalid_arguments_rejected_on_host():
     assert k.value == 0
     assert lib.qb_sketch(1, 0, 0, 4, fake, 1, None) == _lib.QB_EINVAL
     assert lib.qb_sketch(1, 10, 0, 4, fake, 9, None) == _lib.QB_EINVAL
+
+
+def test_adjoint_arguments_checked_on_host():
+    lib = _lib.load()
+    assert lib.qb_adjoint_workspace_bytes(4096, 2048, 64, 4, 1) > 0
+    assert lib.qb_adjoint_workspace_bytes(100, 50, 16, 4, 0) == 0     # s b > min(m, n)
+    assert lib.qb_adjoint_workspace_bytes(1000, 500, 300, 1, 0) == 0  # b > 256
+    assert lib.qb_adjoint_workspace_bytes(1000, 500, 16, 2, 9) == 0   # P > 8
+    assert lib.qb_adjoint_workspace_bytes(1000, 500, 16, 0, 0) == 0
+    fake = ctypes.c_void_p(4096)
+    base = [fake, 100, 80, 100, 8, 2, 0, 1, fake, 100, fake, 16, None, 100, None, 16,
+            fake, 100, fake, 1 << 20, None]
+    bad = list(base)
+    bad[16] = None                                  # no dA
+    assert lib.qb_adjoint(*bad) == _lib.QB_EINVAL
+    bad = list(base)
+    bad[9] = 50                                     # ldq < m
+    assert lib.qb_adjoint(*bad) == _lib.QB_EINVAL
+    bad = list(base)
+    bad[11] = 8                                     # ldb < s b
+    assert lib.qb_adjoint(*bad) == _lib.QB_EINVAL
+    bad = list(base)
+    bad[18] = None                                  # no workspace
+    assert lib.qb_adjoint(*bad) == _lib.QB_EWORKSPACE
+
+
+def test_batched_arguments_checked_on_host():
+    lib = _lib.load()
+    fake = 4096
+
+    def prob(**kw):
+        p = _lib.QBProblem()
+        d = dict(A=fake, m=300, n=200, lda=300, eps=1.0, seed=1, kmax=-1, Q=fake, ldq=300,
+                 B=fake, ldb=200, b=32)
+        d.update(kw)
+        for k, v in d.items():
+            setattr(p, k, v)
+        return p
+
+    def ws(*ps):
+        arr = (_lib.QBProblem * len(ps))(*ps)
+        return lib.qb_factor_batched_workspace_bytes(arr, len(ps))
+
+    assert ws(prob(), prob(m=4096, n=2048, lda=4096, ldq=4096, ldb=2048, b=64)) > 0
+    assert ws(prob(b=65)) == 0          # panels up to 64 wide
+    assert ws(prob(kmax=201)) == 0      # kmax > min(m, n)
+    assert ws(prob(ldq=299)) == 0
+    assert ws(prob(ldb=100)) == 0       # ldb < kmax
+    assert ws(prob(eps=-1.0)) == 0
+    assert ws(prob(A=None)) == 0
+    arr = (_lib.QBProblem * 1)(prob(b=0))
+    assert lib.qb_factor_batched(arr, 1, ctypes.c_void_p(256), 1 << 20, None) == _lib.QB_EINVAL
