@@ -114,8 +114,9 @@ struct Tile {
 // resource per operand at its tile origin; each lane keeps loop-invariant
 // 32-bit byte offsets and the advance along k goes into the scalar offset,
 // so a load costs no address arithmetic and no bounds test.  Used only when
-// the whole tile, every depth slice, 16-byte alignment (base and even ld)
-// and a byte extent below 2^31 are guaranteed (checked per workgroup).
+// every depth slice, 16-byte alignment (base and even ld) and a byte extent
+// below 2^31 are guaranteed, and the tile is whole or its missing rows or
+// columns read as zero (checked per workgroup in mma_loop).
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 constexpr int kBufDword3 = 0x00020000;  // raw (untyped) buffer, gfx9 family
 
@@ -231,10 +232,22 @@ __device__ __forceinline__ void mma_loop(const double* __restrict__ A, int64_t l
   if (kbeg >= kend) return;
 
   const int64_t klen = kend - kbeg;
-  const int64_t ext_a = A_KCONTIG ? klen + (S::BM - 1) * lda : S::BM + (klen - 1) * lda;
-  const int64_t ext_b = klen + (S::BN - 1) * ldb;
-  const bool fast = vec && m0 + S::BM <= M && n0 + S::BN <= N && klen % BK == 0 &&
-                    8 * ext_a < (int64_t(1) << 31) && 8 * ext_b < (int64_t(1) << 31);
+  // A k-contiguous operand tile that runs past the last valid row or column
+  // (a partial edge tile, or a panel narrower than the tile) still takes the
+  // buffer-load path: with ld >= klen, every element of a row or column
+  // beyond the valid ones lies at or past the resource's extent, where
+  // buffer loads return zero.  An m-contiguous A tile must be whole.
+  // The lane offsets of the whole tile stay below 2^31 bytes (no 32-bit
+  // wrap back into the valid range); the resources cover the valid part.
+  const int64_t mv = M - m0 < S::BM ? M - m0 : S::BM;
+  const int64_t nv = N - n0 < S::BN ? N - n0 : S::BN;
+  const int64_t full_a = A_KCONTIG ? klen + (S::BM - 1) * lda : S::BM + (klen - 1) * lda;
+  const int64_t full_b = klen + (S::BN - 1) * ldb;
+  const int64_t ext_a = A_KCONTIG ? klen + (mv - 1) * lda : full_a;
+  const int64_t ext_b = klen + (nv - 1) * ldb;
+  const bool fast = vec && (A_KCONTIG ? lda >= klen : m0 + S::BM <= M) && ldb >= klen &&
+                    klen % BK == 0 && 8 * full_a < (int64_t(1) << 31) &&
+                    8 * full_b < (int64_t(1) << 31);
   if (fast) {
     const double* a0 = A_KCONTIG ? A + kbeg + m0 * lda : A + m0 + kbeg * lda;
     const double* b0 = Bm + kbeg + n0 * ldb;
