@@ -43,17 +43,22 @@ __global__ __launch_bounds__(S::NT, S::OCC) void gemm_batched_kernel(
   const int64_t M = g.M, N = g.N, K = g.K;
   const int64_t kbeg = kz * g.kchunk;
   const int64_t kend = kbeg + g.kchunk < K ? kbeg + g.kchunk : K;
-  // the old C of a downdate (or of an NN product with beta) is read before
-  // the MMA loop, so its latency overlaps the operand loads
   const bool vc = vec_ok_dev(g.C, g.ldc);
   const bool need = g.ksplit == 1 && ((OP == kBatchDD) || (OP == kBatchNN && g.beta != 0.0));
-  d4 old[S::IB][S::JB];
+  // a downdate reads its old C tile before the MMA loop, so the read latency
+  // overlaps the operand loads (69 against 74 ms per 512-problem batch, at
+  // three workgroups per CU for the extra registers instead of four); the
+  // other products read it in the epilogue and keep four
+  constexpr bool kAhead = OP == kBatchDD;
+  d4 ahead[kAhead ? S::IB : 1][S::JB];
+  if constexpr (kAhead) {
 #pragma unroll
-  for (int i = 0; i < S::IB; ++i)
+    for (int i = 0; i < S::IB; ++i)
 #pragma unroll
-    for (int j = 0; j < S::JB; ++j)
-      old[i][j] = need ? load4(g.C, g.ldc, m0 + acc_row0<S>(i), n0 + acc_col<S>(j), M, N, vc)
-                       : (d4){0.0, 0.0, 0.0, 0.0};
+      for (int j = 0; j < S::JB; ++j)
+        ahead[i][j] = need ? load4(g.C, g.ldc, m0 + acc_row0<S>(i), n0 + acc_col<S>(j), M, N, vc)
+                           : (d4){0.0, 0.0, 0.0, 0.0};
+  }
   d4 acc[S::IB][S::JB];
   mma_loop<S, OP == kBatchTN>(g.A, g.lda, g.B, g.ldb, m0, n0, M, N, kbeg, kend, g.vec != 0, As,
                               Bs, acc);
@@ -74,13 +79,20 @@ __global__ __launch_bounds__(S::NT, S::OCC) void gemm_batched_kernel(
 #pragma unroll
   for (int i = 0; i < S::IB; ++i) {
     const int64_t row0 = m0 + acc_row0<S>(i);
+    d4 old[S::JB];
+#pragma unroll
+    for (int j = 0; j < S::JB; ++j) {
+      if constexpr (kAhead) old[j] = ahead[i][j];
+      else old[j] = need ? load4(g.C, g.ldc, row0, n0 + acc_col<S>(j), M, N, vc)
+                         : (d4){0.0, 0.0, 0.0, 0.0};
+    }
 #pragma unroll
     for (int j = 0; j < S::JB; ++j) {
       const int64_t col = n0 + acc_col<S>(j);
       d4 v;
-      if (OP == kBatchNN) v = g.alpha * acc[i][j] + g.beta * old[i][j];
+      if (OP == kBatchNN) v = g.alpha * acc[i][j] + g.beta * old[j];
       else if (OP == kBatchTN) v = acc[i][j];
-      else v = old[i][j] - acc[i][j];
+      else v = old[j] - acc[i][j];
       store4(g.C, g.ldc, row0, col, M, N, vc, v);
 #pragma unroll
       for (int r = 0; r < 4; ++r)
