@@ -232,21 +232,24 @@ __device__ __forceinline__ void mma_loop(const double* __restrict__ A, int64_t l
   if (kbeg >= kend) return;
 
   const int64_t klen = kend - kbeg;
+  // The buffer-load path covers the whole slices of the depth range; a
+  // ragged last slice (fewer than BK) follows on the guarded path below.
   // A k-contiguous operand tile that runs past the last valid row or column
   // (a partial edge tile, or a panel narrower than the tile) still takes the
-  // buffer-load path: with ld >= klen, every element of a row or column
+  // buffer-load path: with ld >= the depth, every element of a row or column
   // beyond the valid ones lies at or past the resource's extent, where
-  // buffer loads return zero.  An m-contiguous A tile must be whole.
-  // The lane offsets of the whole tile stay below 2^31 bytes (no 32-bit
-  // wrap back into the valid range); the resources cover the valid part.
+  // buffer loads return zero.  An m-contiguous A tile must be whole.  The
+  // lane offsets of the whole tile stay below 2^31 bytes (no 32-bit wrap
+  // back into the valid range); the resources cover the valid part.
+  const int64_t kfast = klen - klen % BK;
   const int64_t mv = M - m0 < S::BM ? M - m0 : S::BM;
   const int64_t nv = N - n0 < S::BN ? N - n0 : S::BN;
-  const int64_t full_a = A_KCONTIG ? klen + (S::BM - 1) * lda : S::BM + (klen - 1) * lda;
-  const int64_t full_b = klen + (S::BN - 1) * ldb;
-  const int64_t ext_a = A_KCONTIG ? klen + (mv - 1) * lda : full_a;
-  const int64_t ext_b = klen + (nv - 1) * ldb;
-  const bool fast = vec && (A_KCONTIG ? lda >= klen : m0 + S::BM <= M) && ldb >= klen &&
-                    klen % BK == 0 && 8 * full_a < (int64_t(1) << 31) &&
+  const int64_t full_a = A_KCONTIG ? kfast + (S::BM - 1) * lda : S::BM + (kfast - 1) * lda;
+  const int64_t full_b = kfast + (S::BN - 1) * ldb;
+  const int64_t ext_a = A_KCONTIG ? kfast + (mv - 1) * lda : full_a;
+  const int64_t ext_b = kfast + (nv - 1) * ldb;
+  const bool fast = vec && kfast > 0 && (A_KCONTIG ? lda >= kfast : m0 + S::BM <= M) &&
+                    ldb >= kfast && 8 * full_a < (int64_t(1) << 31) &&
                     8 * full_b < (int64_t(1) << 31);
   if (fast) {
     const double* a0 = A_KCONTIG ? A + kbeg + m0 * lda : A + m0 + kbeg * lda;
@@ -256,7 +259,7 @@ __device__ __forceinline__ void mma_loop(const double* __restrict__ A, int64_t l
     // byte advance of one depth slice
     const uint32_t da = static_cast<uint32_t>(8 * (A_KCONTIG ? BK : BK * lda));
     const uint32_t db = static_cast<uint32_t>(8 * BK);
-    const int nslice = static_cast<int>(klen / BK);
+    const int nslice = static_cast<int>(kfast / BK);
     FastTile<S, A_KCONTIG> tl;
     tl.setup(lda, ldb);
     tl.load(rA, 0u, rB, 0u);
@@ -273,6 +276,15 @@ __device__ __forceinline__ void mma_loop(const double* __restrict__ A, int64_t l
       lds_barrier();
       stage ^= 1;
     }
+    if (kfast == klen) return;
+    // ragged last slice: one guarded load into a free stage (every wave
+    // has passed the barrier after the last multiply)
+    Tile<S, A_KCONTIG> tt;
+    tt.load(A, lda, Bm, ldb, m0, n0, M, N, kbeg + kfast, kend);
+    tt.store(As, Bs);
+    lds_barrier();
+    mma_slice<S, A_KCONTIG>(As, Bs, acc);
+    lds_barrier();
     return;
   }
 
