@@ -293,8 +293,18 @@ def batched_experiment(steps, warmup, no_cpu):
     prof = profile_snapshot(lib)
     lib.qb_profile_enable(0)
     kern = {name: {"ms": round(v["ms"], 3), "launches": v["launches"],
-                   **({"tflops": round(v["flops"] / v["ms"] / 1e9, 2)} if v["flops"] else {})}
+                   **({"tflops": round(v["flops"] / v["ms"] / 1e9, 2)} if v["flops"] else {}),
+                   **({"gbs": round(v["bytes"] / v["ms"] / 1e6, 1)} if v["bytes"] else {})}
             for name, v in prof.items()}
+    # the largest kernel class: the downdate, a stream over R (HBM-bound)
+    dom_name = max((k for k in prof if k.startswith("batch_")), key=lambda k: prof[k]["ms"])
+    dom = prof[dom_name]
+    gbs = dom["bytes"] / dom["ms"] / 1e6 if dom["bytes"] else None
+    roofline = {"bound": "hbm", "kernel": dom_name, "achieved": gbs, "peak": PEAK["hbm_gbs"],
+                "unit": "GB/s", "frac": gbs / PEAK["hbm_gbs"] if gbs else None,
+                "tflops": dom["flops"] / dom["ms"] / 1e9 if dom["flops"] else None,
+                "note": "algorithmic bytes (8 (MK + KN + 2MN) per product) over the summed "
+                        "launch durations, HIP events, one extra profiled batch"}
     # critical path: the problem that needs the most block iterations, alone
     slow = max(range(len(specs)), key=lambda i: nblk[i])
     qbmi.qb_factor_batched([As[slow]], [eps[slow]], [bs[slow]], [seeds[slow]])
@@ -354,7 +364,8 @@ def batched_experiment(steps, warmup, no_cpu):
                       "errors": len(bad), "iterations": len(active), "active_per_iteration": active,
                       "longest_problem_alone_seconds": tail,
                       "one_by_one_seconds": seq,
-                      "one_by_one_same_k": same_k, "kernels": kern, "parity": parity,
+                      "one_by_one_same_k": same_k, "roofline": roofline, "kernels": kern,
+                      "parity": parity,
                       "cpu_baseline": cpu, "dtype": "f32 input, f64 arithmetic",
                       "data": "synthetic"}), flush=True)
 
@@ -409,6 +420,10 @@ def adjoint_experiment(steps, warmup, no_cpu):
         row = {"power_iters": P, "forward_s": t_fwd, "backward_s": t_bwd,
                "backward_gemm_flops": gemm_fl, "backward_gemm_tflops": gemm_fl / gemm_ms / 1e9,
                "backward_gflops": gemm_fl / t_bwd / 1e9,
+               "roofline": {"bound": "mfma", "kernel": "backward GEMMs (all classes)",
+                            "achieved": gemm_fl / gemm_ms / 1e9, "peak": PEAK["f64_mfma"],
+                            "unit": "TFLOP/s",
+                            "frac": gemm_fl / gemm_ms / 1e9 / PEAK["f64_mfma"]},
                "kernels": {k: {"ms": round(v["ms"], 3), "launches": v["launches"]}
                            for k, v in prof.items()}}
         if not no_cpu:

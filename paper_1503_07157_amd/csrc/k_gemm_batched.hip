@@ -168,10 +168,10 @@ void batch_tile_dims(int cls, int* bm, int* bn) {
 }
 
 int gemm_batched(int op, int cls, const BatchGemm* desc, int count, int64_t total_tiles,
-                 int prof_id, double flops, hipStream_t s) {
+                 int prof_id, double flops, double bytes, hipStream_t s) {
   if (count <= 0 || total_tiles <= 0) return kOk;
   if (op == kBatchDD && cls != kTile64) return kEInval;
-  ProfScope ps(prof_id, flops, 0.0, s);
+  ProfScope ps(prof_id, flops, bytes, s);
   switch (cls) {
     case kTileG16: launch_batched<BatchG16>(op, desc, count, total_tiles, s); break;
     case kTileG32: launch_batched<BatchG32>(op, desc, count, total_tiles, s); break;

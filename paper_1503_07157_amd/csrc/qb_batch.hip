@@ -225,12 +225,14 @@ struct Step {
   int begin[kTileClasses + 1] = {};
   int64_t tiles[kTileClasses] = {};
   double flops[kTileClasses] = {};
+  double bytes[kTileClasses] = {};
   int64_t rblocks = 0;
   size_t off = 0;
   int count() const { return static_cast<int>(d.size()); }
 };
 
-Step group(const std::vector<BatchGemm>& v) {
+// reads_c: the product also reads C (the downdate, Qi -= Qbar C)
+Step group(const std::vector<BatchGemm>& v, bool reads_c = false) {
   Step st;
   st.d.reserve(v.size());
   for (int c = 0; c < kTileClasses; ++c) {
@@ -244,6 +246,8 @@ Step group(const std::vector<BatchGemm>& v) {
       h.rblock0 = st.rblocks;
       st.rblocks += reduce_blocks(h);
       st.flops[c] += 2.0 * h.M * h.N * h.K;
+      st.bytes[c] += 8.0 * (double(h.M) * h.K + double(h.K) * h.N +
+                            double(h.M) * h.N * (reads_c ? 2.0 : 1.0));
       st.d.push_back(h);
     }
     st.tiles[c] = t;
@@ -487,9 +491,9 @@ int qb_factor_batched(qb_problem* probs, int32_t count, void* workspace, size_t 
 
 
       Step sY = group(gY), s1 = group(g1), sa1 = group(a1), s2 = group(g2), sa2 = group(a2);
-      Step srC = group(rC), srQ = group(rQ), s3 = group(g3), sa3 = group(a3), s4 = group(g4),
-           sa4 = group(a4);
-      Step sBB = group(gB), sDD = group(gD);
+      Step srC = group(rC), srQ = group(rQ, true), s3 = group(g3), sa3 = group(a3),
+           s4 = group(g4), sa4 = group(a4);
+      Step sBB = group(gB), sDD = group(gD, true);
       const size_t osk = sg.put(sk);
       for (Step* x : {&sY, &s1, &sa1, &s2, &sa2}) x->off = sg.put(x->d);
       const size_t oc1 = sg.put(c1);
@@ -510,7 +514,8 @@ int qb_factor_batched(qb_problem* probs, int32_t count, void* workspace, size_t 
         for (int c = 0; c < kTileClasses; ++c) {
           const int cnt = x.begin[c + 1] - x.begin[c];
           if (cnt == 0) continue;
-          if (gemm_batched(op, c, G(x.off) + x.begin[c], cnt, x.tiles[c], pid, x.flops[c], st))
+          if (gemm_batched(op, c, G(x.off) + x.begin[c], cnt, x.tiles[c], pid, x.flops[c],
+                           x.bytes[c], st))
             return 1;
         }
         return gemm_batched_reduce(op, G(x.off), x.count(), x.rblocks, pid, st) ? 1 : 0;

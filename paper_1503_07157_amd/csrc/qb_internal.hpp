@@ -165,13 +165,15 @@ constexpr int kBatchTile = 64;      // the default (and downdate) tile of batche
 enum { kTile64 = 0, kTileG16, kTileG32, kTileClasses };
 void batch_tile_dims(int cls, int* bm, int* bn);
 constexpr int kBatchRed = 1024;     // elements per workgroup of the split-K reduction
-// prof_id, flops: the profiler entry and the launch's algorithmic count (sum of 2 M N K).
+// prof_id, flops, bytes: the profiler entry and the launch's algorithmic
+// flops (sum of 2 M N K) and bytes (sum of 8 (M K + K N + M N), M N twice
+// when C is also read).
 // total_tiles counts every (tile, depth chunk) workgroup.  Problems with
 // ksplit > 1 leave C to gemm_batched_reduce, which sums their chunks in
 // order (alpha sum + beta C for NN, the sum for TN) with per-workgroup sums
 // of squares into sq when sq is set; total_rblocks counts its workgroups.
 int gemm_batched(int op, int cls, const BatchGemm* desc, int count, int64_t total_tiles,
-                 int prof_id, double flops, hipStream_t s);
+                 int prof_id, double flops, double bytes, hipStream_t s);
 int gemm_batched_reduce(int op, const BatchGemm* desc, int count, int64_t total_rblocks,
                         int prof_id, hipStream_t s);
 
