@@ -10,16 +10,26 @@
 namespace qb {
 namespace {
 
-// Batched Gram matrices of panels w <= 16 or 32 wide: the tile matches the
-// w x w output, so neither side of the MFMA work is padded to 64.  (Tiles
-// narrow on one side only, 128 x 16 for R Omega or 16 x 128 for Q_i^T R,
-// measured no faster than 64 x 64 there, and 256 x 64 for R Omega 60 %
-// slower: those products are bound by the latency of their depth loops,
-// and 64 x 64 tiles give the most workgroups.  The batched downdate, a
-// stream over R, measured 69 ms per 512-problem batch with 64 x 64 tiles,
-// 75 ms with 32 x 32 and 178 ms with 128 x 128.)
+// Tile choices, measured on 512 uneven problems (ms per batch):
+//   * Gram matrices of panels w <= 16 or 32: 16 x 16 / 32 x 32 tiles, so
+//     neither side of the MFMA work is padded to 64 (Gram 25 -> 21 ms);
+//   * the other products of panels w <= 32 (R Omega, the T^{-1}
+//     application, Qbar C, Qbar^T Q_i; Q_i^T R): 64 x 32 / 32 x 64 tiles of
+//     four waves side by side along the long side, padding to 32 instead
+//     of 64 (batch 249 -> 229..234 ms over runs).  Two-wave 32 x 16 / 16 x 32 tiles for
+//     w <= 16 were slower (239 ms), as were 128 x 16 / 16 x 128 with two
+//     waves and 256 x 64 for R Omega: these products are bound by each
+//     workgroup's depth loop, and four-wave tiles with many workgroups win;
+//   * the downdate, a stream over R: 64 x 64 (69 ms) against 32 x 32
+//     (75 ms) and 128 x 128 (178 ms).
+// (A workgroup-parallel search for the owning problem in place of the
+// binary search below measured the same, 234 ms: not the bottleneck.)
 using BatchG16 = Shape<16, 16, 1, 1>;
 using BatchG32 = Shape<32, 32, 2, 2>;
+// Panels w <= 32 wide: four waves side by side along the long side, so the
+// narrow side is padded to 32 instead of 64 with the same number of waves.
+using BatchN32 = Shape<64, 32, 4, 1>;
+using BatchM32 = Shape<32, 64, 1, 4>;
 
 template <class S, int OP>
 __global__ __launch_bounds__(S::NT, S::OCC) void gemm_batched_kernel(
@@ -163,6 +173,8 @@ void batch_tile_dims(int cls, int* bm, int* bn) {
   switch (cls) {
     case kTileG16: *bm = BatchG16::BM; *bn = BatchG16::BN; return;
     case kTileG32: *bm = BatchG32::BM; *bn = BatchG32::BN; return;
+    case kTileN32: *bm = BatchN32::BM; *bn = BatchN32::BN; return;
+    case kTileM32: *bm = BatchM32::BM; *bn = BatchM32::BN; return;
     default: *bm = Small::BM; *bn = Small::BN; return;
   }
 }
@@ -175,6 +187,8 @@ int gemm_batched(int op, int cls, const BatchGemm* desc, int count, int64_t tota
   switch (cls) {
     case kTileG16: launch_batched<BatchG16>(op, desc, count, total_tiles, s); break;
     case kTileG32: launch_batched<BatchG32>(op, desc, count, total_tiles, s); break;
+    case kTileN32: launch_batched<BatchN32>(op, desc, count, total_tiles, s); break;
+    case kTileM32: launch_batched<BatchM32>(op, desc, count, total_tiles, s); break;
     default: launch_batched<Small>(op, desc, count, total_tiles, s); break;
   }
   QB_HIP_TRY(hipGetLastError());

@@ -166,8 +166,12 @@ struct Stage {
   }
 };
 
-// tile class of the w x w Gram of a panel; every other product takes 64 x 64
+// tile classes by panel width: the w x w Gram; products whose N is the
+// panel (R Omega, the T^{-1} application, Qbar C, Qbar^T Q_i); products
+// whose M is the panel (B_i = Q_i^T R); the downdate takes 64 x 64
 int cls_g(int w) { return w <= 16 ? kTileG16 : w <= 32 ? kTileG32 : kTile64; }
+int cls_n(int w) { return w <= 32 ? kTileN32 : kTile64; }
+int cls_m(int w) { return w <= 32 ? kTileM32 : kTile64; }
 
 // part: the problem's split-K buffer (kPartDoubles), or null for no split
 BatchGemm gemm_desc(int cls, const double* A, int64_t lda, const double* B, int64_t ldb,
@@ -399,7 +403,7 @@ int qb_factor_batched(qb_problem* probs, int32_t count, void* workspace, size_t 
       std::vector<BatchGemm> gY(na);
       for (int a = 0; a < na; ++a) {
         const Prob& p = P[act[a]];
-        gY[a] = gemm_desc(kTile64, p.R, p.ldr, p.omega, p.n, p.Y, p.ldm, p.m, p.w, p.n, 1.0,
+        gY[a] = gemm_desc(cls_n(p.w), p.R, p.ldr, p.omega, p.n, p.Y, p.ldm, p.m, p.w, p.n, 1.0,
                           0.0, nullptr, p.part);
       }
       // CholQR pass helpers: Gram, Cholesky, apply into dst
@@ -425,7 +429,7 @@ int qb_factor_batched(qb_problem* probs, int32_t count, void* workspace, size_t 
         std::vector<BatchGemm> g(ids.size());
         for (size_t a = 0; a < ids.size(); ++a) {
           const Prob& p = P[ids[a]];
-          g[a] = gemm_desc(kTile64, X[a], p.ldm, p.Tinv, p.w, D[a], ldd[a], p.m, p.w, p.w,
+          g[a] = gemm_desc(cls_n(p.w), X[a], p.ldm, p.Tinv, p.w, D[a], ldd[a], p.m, p.w, p.w,
                            1.0, 0.0, nullptr, p.part);
         }
         return g;
@@ -458,9 +462,9 @@ int qb_factor_batched(qb_problem* probs, int32_t count, void* workspace, size_t 
       for (int a = 0; a < nr; ++a) {
         Prob& p = P[reproj[a]];
         qb_problem& q = probs[reproj[a]];
-        rC[a] = gemm_desc(kTile64, q.Q, q.ldq, p.Qi, p.ldm, p.C, p.ldc, p.k, p.w, p.m, 1.0,
+        rC[a] = gemm_desc(cls_n(p.w), q.Q, q.ldq, p.Qi, p.ldm, p.C, p.ldc, p.k, p.w, p.m, 1.0,
                           0.0, nullptr, p.part);
-        rQ[a] = gemm_desc(kTile64, q.Q, q.ldq, p.C, p.ldc, p.Qi, p.ldm, p.m, p.w, p.k, -1.0,
+        rQ[a] = gemm_desc(cls_n(p.w), q.Q, q.ldq, p.C, p.ldc, p.Qi, p.ldm, p.m, p.w, p.k, -1.0,
                           1.0, nullptr, p.part);
         xQi[a] = p.Qi;
         dQt2[a] = p.Qt;
@@ -481,7 +485,7 @@ int qb_factor_batched(qb_problem* probs, int32_t count, void* workspace, size_t 
         qb_problem& q = probs[act[a]];
         double* Qo = q.Q + p.k * q.ldq;
         double* Bo = q.B + p.k;
-        gB[a] = gemm_desc(kTile64, Qo, q.ldq, p.R, p.ldr, Bo, q.ldb, p.w, p.n, p.m, 1.0, 0.0,
+        gB[a] = gemm_desc(cls_m(p.w), Qo, q.ldq, p.R, p.ldr, Bo, q.ldb, p.w, p.n, p.m, 1.0, 0.0,
                           p.sqB, p.part);
         gD[a] = gemm_desc(kTile64, Qo, q.ldq, Bo, q.ldb, p.R, p.ldr, p.m, p.n, p.w, 1.0, 0.0,
                           p.sqR, nullptr);

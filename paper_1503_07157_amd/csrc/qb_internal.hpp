@@ -160,9 +160,10 @@ struct BatchGemm {
 };
 enum { kBatchNN = 0, kBatchTN = 1, kBatchDD = 2 };
 constexpr int kBatchTile = 64;      // the default (and downdate) tile of batched products
-// tile classes of batched products: 64 x 64, and 16 x 16 / 32 x 32 for the
-// Gram matrices of narrow panels
-enum { kTile64 = 0, kTileG16, kTileG32, kTileClasses };
+// tile classes of batched products: 64 x 64; 16 x 16 / 32 x 32 for the
+// Gram matrices of narrow panels; 64 x 32 / 32 x 64 for the other products
+// of panels at most 32 wide (narrow N / narrow M)
+enum { kTile64 = 0, kTileG16, kTileG32, kTileN32, kTileM32, kTileClasses };
 void batch_tile_dims(int cls, int* bm, int* bn);
 constexpr int kBatchRed = 1024;     // elements per workgroup of the split-K reduction
 // prof_id, flops, bytes: the profiler entry and the launch's algorithmic
