@@ -147,6 +147,30 @@ int carve_batch(Arena& a, const qb_problem* probs, int count, Layout* L) {
   return (a.base != nullptr && a.used > a.cap) ? kEWorkspace : kOk;
 }
 
+// Per-thread pinned host memory for the descriptors and the per-iteration
+// scalars, grown on demand and kept for the life of the thread (so a call
+// allocates nothing once the thread has run a batch as large).  A call has
+// synchronised its stream before returning, so the next one may reuse it.
+void* pinned_stage(size_t bytes) {
+  struct Pinned {
+    void* p = nullptr;
+    size_t cap = 0;
+  };
+  thread_local Pinned ps;
+  if (bytes > ps.cap) {
+    if (ps.p != nullptr) (void)hipHostFree(ps.p);
+    ps.p = nullptr;
+    ps.cap = 0;
+    const size_t want = std::max(bytes + bytes / 4, size_t(1) << 20);
+    if (hipHostMalloc(&ps.p, want, hipHostMallocDefault) != hipSuccess) {
+      ps.p = nullptr;
+      return nullptr;
+    }
+    ps.cap = want;
+  }
+  return ps.p;
+}
+
 // host staging of one iteration's descriptors; offsets into the device block
 struct Stage {
   char* host = nullptr;
@@ -300,13 +324,11 @@ int qb_factor_batched(qb_problem* probs, int32_t count, void* workspace, size_t 
   // pinned host memory for the descriptors and the per-iteration scalars
   Stage sg;
   sg.cap = L.desc_bytes;
-  void* hbuf = nullptr;
   const size_t scal_bytes = static_cast<size_t>(count) * kScal * sizeof(double);
   const size_t kept_bytes = static_cast<size_t>(count) * kKeptStride * sizeof(int);
   const size_t flag_bytes = static_cast<size_t>(count) * sizeof(int);
-  if (hipHostMalloc(&hbuf, sg.cap + scal_bytes + kept_bytes + flag_bytes, hipHostMallocDefault) !=
-      hipSuccess)
-    return QB_EHIP;
+  void* hbuf = pinned_stage(sg.cap + scal_bytes + kept_bytes + flag_bytes);
+  if (hbuf == nullptr) return QB_EHIP;
   sg.host = static_cast<char*>(hbuf);
   double* hscal = reinterpret_cast<double*>(sg.host + sg.cap);
   int* hkept = reinterpret_cast<int*>(sg.host + sg.cap + scal_bytes);
@@ -593,8 +615,10 @@ int qb_factor_batched(qb_problem* probs, int32_t count, void* workspace, size_t 
     }
     return QB_OK;
   };
-  int rc = run();
-  if (hipHostFree(hbuf) != hipSuccess && rc == QB_OK) rc = QB_EHIP;
+  const int rc = run();
+  // the staging buffer is reused by the thread's next call: nothing queued
+  // may still read or write it (a failed run can leave copies in flight)
+  if (rc != QB_OK) (void)hipStreamSynchronize(st);
   return rc;
 }
 
