@@ -57,8 +57,9 @@ __global__ __launch_bounds__(S::NT, S::OCC) void gemm_batched_kernel(
   const bool need = g.ksplit == 1 && ((OP == kBatchDD) || (OP == kBatchNN && g.beta != 0.0));
   // a downdate reads its old C tile before the MMA loop, so the read latency
   // overlaps the operand loads (69 against 74 ms per 512-problem batch, at
-  // three workgroups per CU for the extra registers instead of four); the
-  // other products read it in the epilogue and keep four
+  // three workgroups per CU for the extra registers instead of four; half
+  // the tile read ahead at four workgroups per CU: 76 ms); the other
+  // products read it in the epilogue and keep four
   constexpr bool kAhead = OP == kBatchDD;
   d4 ahead[kAhead ? S::IB : 1][S::JB];
   if constexpr (kAhead) {
