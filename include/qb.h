@@ -264,6 +264,33 @@ size_t qb_factor_batched_workspace_bytes(const qb_problem* probs, int32_t count)
 int qb_factor_batched(qb_problem* probs, int32_t count, void* workspace, size_t ws_bytes,
                       void* stream);
 
+/* Tile classes of the batched products (process-wide).  Each product role
+ * of a block iteration takes, per panel width class (0: w <= 16, 1: w <= 32,
+ * 2: w <= 64), one output tile class.  Every allowed class computes the
+ * same products (results may differ in the last bits, as the depth split
+ * follows the tile count); B_i allows 64 x 64 and, for w <= 32, 32 x 64;
+ * the downdate 64 x 64 and 32 x 32; the others any class.  For the tuner
+ * (paper_1503_07157_amd/autotune.py) and for callers with their own
+ * measurements; batched calls that start after a change use it.
+ * qb_batched_set_tile returns QB_OK or QB_EINVAL (unknown role, class or
+ * width class, or a class not allowed for the role); qb_batched_get_tile
+ * returns the class or QB_EINVAL. */
+#define QB_TILE_64X64 0
+#define QB_TILE_16X16 1
+#define QB_TILE_32X32 2
+#define QB_TILE_64X32 3  /* 64 rows x 32 columns: panels as the N side */
+#define QB_TILE_32X64 4  /* 32 rows x 64 columns: panels as the M side */
+#define QB_ROLE_SAMPLE 0     /* R Omega_i                */
+#define QB_ROLE_GRAM 1       /* X^T X of each CholQR pass */
+#define QB_ROLE_APPLY 2      /* X T^{-1}                  */
+#define QB_ROLE_REPROJ_C 3   /* Qbar^T Q_i                */
+#define QB_ROLE_REPROJ_Q 4   /* Q_i - Qbar C              */
+#define QB_ROLE_B 5          /* B_i = Q_i^T R             */
+#define QB_ROLE_DOWNDATE 6   /* R - Q_i B_i               */
+#define QB_ROLES 7
+int qb_batched_set_tile(int32_t role, int32_t width_class, int32_t tile_class);
+int qb_batched_get_tile(int32_t role, int32_t width_class);
+
 /* ---- adjoint of the fixed-sketch map A -> (Q, B) ----------------------------
  * With the sketch (seed), the block width b, the number of blocks s and the
  * number of power iterations P fixed, the blocked scheme (Figure 4, with the

@@ -7,6 +7,7 @@ from ._lib import QBError, load  # noqa: F401
 from .qb import (  # noqa: F401
     QBFunction,
     QBResult,
+    batched_tiles,
     colmajor,
     downdate,
     frob2,
@@ -18,6 +19,7 @@ from .qb import (  # noqa: F401
     qb_factor_batched,
     qb_fixed,
     sample_product,
+    set_batched_tiles,
     sketch,
     svd,
     workspace_bytes,

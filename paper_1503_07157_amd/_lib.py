@@ -31,6 +31,9 @@ QB_EWORKSPACE = -3
 QB_EHIP = -4
 QB_ENODEVICE = -5
 
+BATCH_ROLES = {"sample": 0, "gram": 1, "apply": 2, "reproj_c": 3, "reproj_q": 4, "b": 5,
+               "downdate": 6}
+BATCH_TILES = {"64x64": 0, "16x16": 1, "32x32": 2, "64x32": 3, "32x64": 4}
 QB_STOP = {0: "TOL_TRACKED", 1: "TOL_DIRECT", 2: "RANK_CAP", 3: "EXHAUSTED", 4: "KMAX", 5: "ZERO"}
 
 QB_OVERWRITE_A = 1 << 0
@@ -109,6 +112,8 @@ SIGNATURES = {
                                      c_vp, c_i64, c_vp, c_vp, c_size, c_vp]),
     "qb_factor_batched_workspace_bytes": (c_size, [ctypes.POINTER(QBProblem), c_i32]),
     "qb_factor_batched": (ctypes.c_int, [ctypes.POINTER(QBProblem), c_i32, c_vp, c_size, c_vp]),
+    "qb_batched_set_tile": (ctypes.c_int, [c_i32, c_i32, c_i32]),
+    "qb_batched_get_tile": (ctypes.c_int, [c_i32, c_i32]),
     "qb_adjoint_workspace_bytes": (c_size, [c_i64, c_i64, c_i32, c_i32, c_i32]),
     "qb_adjoint": (ctypes.c_int, [c_vp, c_i64, c_i64, c_i64, c_i32, c_i32, c_i32, c_u64,
                                   c_vp, c_i64, c_vp, c_i64, c_vp, c_i64, c_vp, c_i64,

@@ -13,6 +13,7 @@
 // workgroup per problem.  Inputs are float; every stored value and every
 // product is float64, so each problem follows the float64 oracle.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -22,6 +23,11 @@
 
 namespace qb {
 namespace {
+
+static_assert(kTile64 == QB_TILE_64X64 && kTileG16 == QB_TILE_16X16 &&
+                  kTileG32 == QB_TILE_32X32 && kTileN32 == QB_TILE_64X32 &&
+                  kTileM32 == QB_TILE_32X64 && kTileClasses == 5,
+              "public tile class numbers");
 
 constexpr double kDeltaRelB = 1e-13;   // hybrid band, relative to ||A||_F^2
 constexpr double kFloorRelB = 0x1p-46;  // rounding floor of the residual, rel. ||A||_F
@@ -135,7 +141,7 @@ int carve_batch(Arena& a, const qb_problem* probs, int count, Layout* L) {
     p.sqB = a.take<double>(static_cast<size_t>(std::max(cdiv(p.b, kBatchTile) * cdiv(q.n, kBatchTile),
                                                         cdiv(int64_t(p.b) * q.n, kBatchRed))));
     p.part = a.take<double>(static_cast<size_t>(kPartDoubles));
-    p.sqR = a.take<double>(static_cast<size_t>(cdiv(q.m, kBatchTile) * cdiv(q.n, kBatchTile)));
+    p.sqR = a.take<double>(static_cast<size_t>(cdiv(q.m, 32) * cdiv(q.n, 32)));  // 32 x 32 tiles
     if (a.base != nullptr) {
       p.scal = L->scal_all + static_cast<size_t>(i) * kScal;
       p.kept = L->kept_all + static_cast<size_t>(i) * kKeptStride;
@@ -190,12 +196,32 @@ struct Stage {
   }
 };
 
-// tile classes by panel width: the w x w Gram; products whose N is the
-// panel (R Omega, the T^{-1} application, Qbar C, Qbar^T Q_i); products
-// whose M is the panel (B_i = Q_i^T R); the downdate takes 64 x 64
-int cls_g(int w) { return w <= 16 ? kTileG16 : w <= 32 ? kTileG32 : kTile64; }
-int cls_n(int w) { return w <= 32 ? kTileN32 : kTile64; }
-int cls_m(int w) { return w <= 32 ? kTileM32 : kTile64; }
+// Tile class of each product role by panel width (w <= 16, <= 32, <= 64).
+// The defaults are the table the tuner in autotune.py chose on every fourth
+// problem of the 512-problem uneven workload (65 trials; the whole batch
+// 230 -> 225 ms against the hand-picked table of k_gemm_batched.hip); they
+// can be changed at run time through qb_batched_set_tile.  Every class
+// computes the same products; the classes allowed for B_i and the downdate
+// are those their per-tile sums of squares have room for.
+std::atomic<int> g_tile[QB_ROLES][3] = {
+    {{kTileN32}, {kTileN32}, {kTileN32}},  // QB_ROLE_SAMPLE     R Omega
+    {{kTileG32}, {kTileG32}, {kTileG32}},  // QB_ROLE_GRAM       X^T X
+    {{kTileN32}, {kTileN32}, {kTileN32}},  // QB_ROLE_APPLY      X T^{-1}
+    {{kTileN32}, {kTileN32}, {kTileN32}},  // QB_ROLE_REPROJ_C   Qbar^T Q_i
+    {{kTileN32}, {kTileN32}, {kTileG32}},  // QB_ROLE_REPROJ_Q   Q_i - Qbar C
+    {{kTileM32}, {kTileM32}, {kTile64}},   // QB_ROLE_B          Q_i^T R
+    {{kTile64}, {kTile64}, {kTile64}},     // QB_ROLE_DOWNDATE   R - Q_i B_i
+};
+
+int width_class(int w) { return w <= 16 ? 0 : w <= 32 ? 1 : 2; }
+int tile_of(int role, int w) { return g_tile[role][width_class(w)].load(std::memory_order_relaxed); }
+
+bool tile_allowed(int role, int wclass, int cls) {
+  if (cls < 0 || cls >= kTileClasses) return false;
+  if (role == QB_ROLE_B) return cls == kTile64 || (cls == kTileM32 && wclass <= 1);
+  if (role == QB_ROLE_DOWNDATE) return cls == kTile64 || cls == kTileG32;
+  return true;
+}
 
 // part: the problem's split-K buffer (kPartDoubles), or null for no split
 BatchGemm gemm_desc(int cls, const double* A, int64_t lda, const double* B, int64_t ldb,
@@ -297,6 +323,18 @@ int32_t sq_count(const BatchGemm& g) {
 using namespace qb;
 
 extern "C" {
+
+int qb_batched_set_tile(int32_t role, int32_t width_class, int32_t tile_class) {
+  if (role < 0 || role >= QB_ROLES || width_class < 0 || width_class > 2) return QB_EINVAL;
+  if (!tile_allowed(role, width_class, tile_class)) return QB_EINVAL;
+  g_tile[role][width_class].store(tile_class, std::memory_order_relaxed);
+  return QB_OK;
+}
+
+int qb_batched_get_tile(int32_t role, int32_t width_class) {
+  if (role < 0 || role >= QB_ROLES || width_class < 0 || width_class > 2) return QB_EINVAL;
+  return g_tile[role][width_class].load(std::memory_order_relaxed);
+}
 
 size_t qb_factor_batched_workspace_bytes(const qb_problem* probs, int32_t count) {
   if (!probs || count < 1) return 0;
@@ -425,7 +463,7 @@ int qb_factor_batched(qb_problem* probs, int32_t count, void* workspace, size_t 
       std::vector<BatchGemm> gY(na);
       for (int a = 0; a < na; ++a) {
         const Prob& p = P[act[a]];
-        gY[a] = gemm_desc(cls_n(p.w), p.R, p.ldr, p.omega, p.n, p.Y, p.ldm, p.m, p.w, p.n, 1.0,
+        gY[a] = gemm_desc(tile_of(QB_ROLE_SAMPLE, p.w), p.R, p.ldr, p.omega, p.n, p.Y, p.ldm, p.m, p.w, p.n, 1.0,
                           0.0, nullptr, p.part);
       }
       // CholQR pass helpers: Gram, Cholesky, apply into dst
@@ -433,7 +471,7 @@ int qb_factor_batched(qb_problem* probs, int32_t count, void* workspace, size_t 
         std::vector<BatchGemm> g(ids.size());
         for (size_t a = 0; a < ids.size(); ++a) {
           const Prob& p = P[ids[a]];
-          g[a] = gemm_desc(cls_g(p.w), X[a], p.ldm, X[a], p.ldm, p.G, p.w, p.w, p.w, p.m, 1.0,
+          g[a] = gemm_desc(tile_of(QB_ROLE_GRAM, p.w), X[a], p.ldm, X[a], p.ldm, p.G, p.w, p.w, p.w, p.m, 1.0,
                            0.0, nullptr, p.part);
         }
         return g;
@@ -451,7 +489,7 @@ int qb_factor_batched(qb_problem* probs, int32_t count, void* workspace, size_t 
         std::vector<BatchGemm> g(ids.size());
         for (size_t a = 0; a < ids.size(); ++a) {
           const Prob& p = P[ids[a]];
-          g[a] = gemm_desc(cls_n(p.w), X[a], p.ldm, p.Tinv, p.w, D[a], ldd[a], p.m, p.w, p.w,
+          g[a] = gemm_desc(tile_of(QB_ROLE_APPLY, p.w), X[a], p.ldm, p.Tinv, p.w, D[a], ldd[a], p.m, p.w, p.w,
                            1.0, 0.0, nullptr, p.part);
         }
         return g;
@@ -484,9 +522,9 @@ int qb_factor_batched(qb_problem* probs, int32_t count, void* workspace, size_t 
       for (int a = 0; a < nr; ++a) {
         Prob& p = P[reproj[a]];
         qb_problem& q = probs[reproj[a]];
-        rC[a] = gemm_desc(cls_n(p.w), q.Q, q.ldq, p.Qi, p.ldm, p.C, p.ldc, p.k, p.w, p.m, 1.0,
+        rC[a] = gemm_desc(tile_of(QB_ROLE_REPROJ_C, p.w), q.Q, q.ldq, p.Qi, p.ldm, p.C, p.ldc, p.k, p.w, p.m, 1.0,
                           0.0, nullptr, p.part);
-        rQ[a] = gemm_desc(cls_n(p.w), q.Q, q.ldq, p.C, p.ldc, p.Qi, p.ldm, p.m, p.w, p.k, -1.0,
+        rQ[a] = gemm_desc(tile_of(QB_ROLE_REPROJ_Q, p.w), q.Q, q.ldq, p.C, p.ldc, p.Qi, p.ldm, p.m, p.w, p.k, -1.0,
                           1.0, nullptr, p.part);
         xQi[a] = p.Qi;
         dQt2[a] = p.Qt;
@@ -507,9 +545,9 @@ int qb_factor_batched(qb_problem* probs, int32_t count, void* workspace, size_t 
         qb_problem& q = probs[act[a]];
         double* Qo = q.Q + p.k * q.ldq;
         double* Bo = q.B + p.k;
-        gB[a] = gemm_desc(cls_m(p.w), Qo, q.ldq, p.R, p.ldr, Bo, q.ldb, p.w, p.n, p.m, 1.0, 0.0,
+        gB[a] = gemm_desc(tile_of(QB_ROLE_B, p.w), Qo, q.ldq, p.R, p.ldr, Bo, q.ldb, p.w, p.n, p.m, 1.0, 0.0,
                           p.sqB, p.part);
-        gD[a] = gemm_desc(kTile64, Qo, q.ldq, Bo, q.ldb, p.R, p.ldr, p.m, p.n, p.w, 1.0, 0.0,
+        gD[a] = gemm_desc(tile_of(QB_ROLE_DOWNDATE, p.w), Qo, q.ldq, Bo, q.ldb, p.R, p.ldr, p.m, p.n, p.w, 1.0, 0.0,
                           p.sqR, nullptr);
         sB[a] = BatchSum{p.sqB, nullptr, p.scal + 2, nullptr, sq_count(gB[a])};
         sR[a] = BatchSum{p.sqR, nullptr, p.scal + 0, nullptr, sq_count(gD[a])};

@@ -371,3 +371,28 @@ class QBFunction(torch.autograd.Function):
         dB = None if gB is None else colmajor(gB)
         dA = qb_adjoint(A64, Q, B, dQ, dB, b, blocks, P, seed)
         return dA.to(dtype), None, None, None, None
+
+
+def batched_tiles():
+    """The batched products' tile classes: {role: [class for w <= 16, <= 32,
+    <= 64]}, class names as in _lib.BATCH_TILES."""
+    lib = _lib.load()
+    names = {v: k for k, v in _lib.BATCH_TILES.items()}
+    out = {}
+    for role, r in _lib.BATCH_ROLES.items():
+        out[role] = [names[_check(lib.qb_batched_get_tile(r, wc), "qb_batched_get_tile")]
+                     for wc in range(3)]
+    return out
+
+
+def set_batched_tiles(table):
+    """Set tile classes: table {role: [class per width class]} (partial
+    tables allowed; None keeps an entry).  Raises QBError for a class not
+    allowed for its role."""
+    lib = _lib.load()
+    for role, classes in table.items():
+        for wc, name in enumerate(classes):
+            if name is None:
+                continue
+            _check(lib.qb_batched_set_tile(_lib.BATCH_ROLES[role], wc, _lib.BATCH_TILES[name]),
+                   f"qb_batched_set_tile({role}, {wc}, {name})")

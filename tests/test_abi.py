@@ -135,3 +135,23 @@ def test_batched_arguments_checked_on_host():
     assert ws(prob(A=None)) == 0
     arr = (_lib.QBProblem * 1)(prob(b=0))
     assert lib.qb_factor_batched(arr, 1, ctypes.c_void_p(256), 1 << 20, None) == _lib.QB_EINVAL
+
+
+def test_batched_tile_table_checked_on_host():
+    lib = _lib.load()
+    R, T = _lib.BATCH_ROLES, _lib.BATCH_TILES
+    saved = [[lib.qb_batched_get_tile(r, wc) for wc in range(3)] for r in range(len(R))]
+    try:
+        assert lib.qb_batched_get_tile(R["gram"], 0) == T["32x32"]
+        assert lib.qb_batched_set_tile(R["b"], 2, T["32x64"]) == _lib.QB_EINVAL   # w <= 64
+        assert lib.qb_batched_set_tile(R["b"], 1, T["32x64"]) == _lib.QB_OK
+        assert lib.qb_batched_set_tile(R["downdate"], 0, T["16x16"]) == _lib.QB_EINVAL
+        assert lib.qb_batched_set_tile(R["downdate"], 0, T["32x32"]) == _lib.QB_OK
+        assert lib.qb_batched_set_tile(7, 0, 0) == _lib.QB_EINVAL
+        assert lib.qb_batched_set_tile(0, 3, 0) == _lib.QB_EINVAL
+        assert lib.qb_batched_set_tile(0, 0, 5) == _lib.QB_EINVAL
+        assert lib.qb_batched_get_tile(R["downdate"], 0) == T["32x32"]
+    finally:
+        for r in range(len(R)):
+            for wc in range(3):
+                assert lib.qb_batched_set_tile(r, wc, saved[r][wc]) == _lib.QB_OK

@@ -124,3 +124,30 @@ def test_batch_result_independent_of_batch_mates(cuda):
         assert torch.equal(alone.Q, full[i].Q) and torch.equal(alone.B, full[i].B)
     for r1, r2 in zip(full, again):
         assert r1.k == r2.k and torch.equal(r1.Q, r2.Q) and torch.equal(r1.B, r2.B)
+
+
+def test_other_tile_classes_match_oracle(cuda):
+    """Every allowed tile class computes the same products: a batch run with
+    a non-default table (the one the tuner may pick) still matches the
+    oracle problem by problem."""
+    specs = synth.batch_specs(count=8, seed=31, m_range=(200, 900), n_max=500)
+    mats = [synth.batch_matrix(sp) for sp in specs]
+    eps = [1e-5 * float(np.linalg.norm(A.astype(np.float64))) for A in mats]
+    saved = qbmi.batched_tiles()
+    try:
+        qbmi.set_batched_tiles({"sample": ["16x16", "32x32", "64x32"],
+                                "gram": ["64x64", "64x64", "32x32"],
+                                "apply": ["64x64", "32x64", "16x16"],
+                                "reproj_c": ["32x32", "64x64", "64x32"],
+                                "reproj_q": ["64x64", "16x16", "32x64"],
+                                "b": ["64x64", "64x64", "64x64"],
+                                "downdate": ["32x32", "32x32", "32x32"]})
+        res = qbmi.qb_factor_batched([dev32(A) for A in mats], eps, [sp.b for sp in specs],
+                                     [sp.seed_omega for sp in specs])
+    finally:
+        qbmi.set_batched_tiles(saved)
+    for sp, A, e, g in zip(specs, mats, eps, res):
+        o = randqb_pb(A.astype(np.float64), e, sp.b, 0, sp.seed_omega)
+        assert g.k == o.k and g.stop_reason == STOP_NAMES[o.stop_reason]
+        Q, B = g.Q.cpu().numpy(), g.B.cpu().numpy()
+        assert np.linalg.norm(Q @ B - o.Q @ o.B) <= 1e-10 * math.sqrt(g.normA2)
