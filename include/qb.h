@@ -268,8 +268,8 @@ int qb_factor_batched(qb_problem* probs, int32_t count, void* workspace, size_t 
  * of a block iteration takes, per panel width class (0: w <= 16, 1: w <= 32,
  * 2: w <= 64), one output tile class.  Every allowed class computes the
  * same products (results may differ in the last bits, as the depth split
- * follows the tile count); B_i allows 64 x 64 and, for w <= 32, 32 x 64;
- * the downdate 64 x 64 and 32 x 32; the others any class.  For the tuner
+ * follows the tile count); B_i and the downdate allow every class but
+ * 16 x 16, the others any class.  For the tuner
  * (paper_1503_07157_amd/autotune.py) and for callers with their own
  * measurements; batched calls that start after a change use it.
  * qb_batched_set_tile returns QB_OK or QB_EINVAL (unknown role, class or

@@ -183,7 +183,7 @@ void batch_tile_dims(int cls, int* bm, int* bn) {
 int gemm_batched(int op, int cls, const BatchGemm* desc, int count, int64_t total_tiles,
                  int prof_id, double flops, double bytes, hipStream_t s) {
   if (count <= 0 || total_tiles <= 0) return kOk;
-  if (op == kBatchDD && cls != kTile64 && cls != kTileG32) return kEInval;
+  if (op == kBatchDD && cls == kTileG16) return kEInval;
   ProfScope ps(prof_id, flops, bytes, s);
   switch (cls) {
     case kTileG16: launch_batched<BatchG16>(op, desc, count, total_tiles, s); break;

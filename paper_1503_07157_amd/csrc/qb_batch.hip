@@ -138,10 +138,12 @@ int carve_batch(Arena& a, const qb_problem* probs, int count, Layout* L) {
     p.nconv = convert_blocks(q.m, q.n);
     p.sqA = a.take<double>(static_cast<size_t>(p.nconv));
     p.flA = a.take<int>(static_cast<size_t>(p.nconv));
-    p.sqB = a.take<double>(static_cast<size_t>(std::max(cdiv(p.b, kBatchTile) * cdiv(q.n, kBatchTile),
+    // per-tile sums of squares of B_i and of the downdate, for tiles of at
+    // least 32 x 32 (or per reduction workgroup of a split B_i)
+    p.sqB = a.take<double>(static_cast<size_t>(std::max(cdiv(p.b, 32) * cdiv(q.n, 32),
                                                         cdiv(int64_t(p.b) * q.n, kBatchRed))));
     p.part = a.take<double>(static_cast<size_t>(kPartDoubles));
-    p.sqR = a.take<double>(static_cast<size_t>(cdiv(q.m, 32) * cdiv(q.n, 32)));  // 32 x 32 tiles
+    p.sqR = a.take<double>(static_cast<size_t>(cdiv(q.m, 32) * cdiv(q.n, 32)));
     if (a.base != nullptr) {
       p.scal = L->scal_all + static_cast<size_t>(i) * kScal;
       p.kept = L->kept_all + static_cast<size_t>(i) * kKeptStride;
@@ -217,9 +219,11 @@ int width_class(int w) { return w <= 16 ? 0 : w <= 32 ? 1 : 2; }
 int tile_of(int role, int w) { return g_tile[role][width_class(w)].load(std::memory_order_relaxed); }
 
 bool tile_allowed(int role, int wclass, int cls) {
+  (void)wclass;
   if (cls < 0 || cls >= kTileClasses) return false;
-  if (role == QB_ROLE_B) return cls == kTile64 || (cls == kTileM32 && wclass <= 1);
-  if (role == QB_ROLE_DOWNDATE) return cls == kTile64 || cls == kTileG32;
+  // B_i and the downdate leave one sum of squares per tile; their buffers
+  // hold one per 32 x 32 tile
+  if (role == QB_ROLE_B || role == QB_ROLE_DOWNDATE) return cls != kTileG16;
   return true;
 }
 

@@ -143,8 +143,9 @@ def test_batched_tile_table_checked_on_host():
     saved = [[lib.qb_batched_get_tile(r, wc) for wc in range(3)] for r in range(len(R))]
     try:
         assert lib.qb_batched_get_tile(R["gram"], 0) == T["32x32"]
-        assert lib.qb_batched_set_tile(R["b"], 2, T["32x64"]) == _lib.QB_EINVAL   # w <= 64
+        assert lib.qb_batched_set_tile(R["b"], 2, T["16x16"]) == _lib.QB_EINVAL
         assert lib.qb_batched_set_tile(R["b"], 1, T["32x64"]) == _lib.QB_OK
+        assert lib.qb_batched_set_tile(R["downdate"], 2, T["64x32"]) == _lib.QB_OK
         assert lib.qb_batched_set_tile(R["downdate"], 0, T["16x16"]) == _lib.QB_EINVAL
         assert lib.qb_batched_set_tile(R["downdate"], 0, T["32x32"]) == _lib.QB_OK
         assert lib.qb_batched_set_tile(7, 0, 0) == _lib.QB_EINVAL

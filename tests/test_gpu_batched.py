@@ -140,8 +140,8 @@ def test_other_tile_classes_match_oracle(cuda):
                                 "apply": ["64x64", "32x64", "16x16"],
                                 "reproj_c": ["32x32", "64x64", "64x32"],
                                 "reproj_q": ["64x64", "16x16", "32x64"],
-                                "b": ["64x64", "64x64", "64x64"],
-                                "downdate": ["32x32", "32x32", "32x32"]})
+                                "b": ["32x32", "64x32", "64x64"],
+                                "downdate": ["32x32", "64x32", "32x64"]})
         res = qbmi.qb_factor_batched([dev32(A) for A in mats], eps, [sp.b for sp in specs],
                                      [sp.seed_omega for sp in specs])
     finally:
