@@ -239,7 +239,7 @@ def post_experiment():
     print(json.dumps({"experiment": "post", "rows": out}), flush=True)
 
 
-def batched_experiment(steps, warmup, no_cpu):
+def batched_experiment(steps, warmup, no_cpu, tune=True):
     """Many matrices of uneven sizes: 512 float32 matrices, m uniform in
     [256, 4096], n uniform in [128, min(m, 2048)], s_j = r^j with r uniform
     in [0.9, 0.995], b in {16, 32, 64}, eps = 1e-5 ||A||_F, P = 0, all
@@ -285,21 +285,24 @@ def batched_experiment(steps, warmup, no_cpu):
     default_tiles = qbmi.batched_tiles()
     res, sec_default = timed()
     log(f"[bench] batched: {sec_default * 1e3:.1f} ms per batch with the default tiles")
-    # tile classes tuned on every fourth problem of the batch, then the whole
-    # batch timed again with the tuned table
-    from paper_1503_07157_amd.autotune import tune_batched
-    sub = list(range(0, len(specs), 4))
-    t0 = time.perf_counter()
-    tuned, sub_before, sub_after, trials = tune_batched(
-        [As[i] for i in sub], [eps[i] for i in sub], [bs[i] for i in sub],
-        [seeds[i] for i in sub])
-    tune_s = time.perf_counter() - t0
-    log(f"[bench] batched: tuned on {len(sub)} problems in {tune_s:.1f} s ({trials} trials): "
-        f"{sub_before * 1e3:.1f} -> {sub_after * 1e3:.1f} ms")
-    res, sec = timed()
-    if sec_default < sec:  # keep whichever table ran the whole batch faster
-        qbmi.set_batched_tiles(default_tiles)
+    sec = sec_default
+    sub, tune_s, trials, sub_before, sub_after = [], 0.0, 0, None, None
+    if tune:
+        # tile classes tuned on every fourth problem of the batch, then the
+        # whole batch timed again with the tuned table
+        from paper_1503_07157_amd.autotune import tune_batched
+        sub = list(range(0, len(specs), 4))
+        t0 = time.perf_counter()
+        tuned, sub_before, sub_after, trials = tune_batched(
+            [As[i] for i in sub], [eps[i] for i in sub], [bs[i] for i in sub],
+            [seeds[i] for i in sub])
+        tune_s = time.perf_counter() - t0
+        log(f"[bench] batched: tuned on {len(sub)} problems in {tune_s:.1f} s ({trials} trials): "
+            f"{sub_before * 1e3:.1f} -> {sub_after * 1e3:.1f} ms")
         res, sec = timed()
+        if sec_default < sec:  # keep whichever table ran the whole batch faster
+            qbmi.set_batched_tiles(default_tiles)
+            res, sec = timed()
     ks = [r.k for r in res]
     nblk = [r.blocks for r in res]
     active = [sum(1 for v in nblk if v > it) for it in range(max(nblk))]
@@ -479,6 +482,8 @@ def main():
     ap.add_argument("--sample", default="f64", choices=["f64", "f32", "bf16x3"])
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="batched experiment: keep the default tile table (no tuning pass)")
     ap.add_argument("--cpu-blocks", type=int, default=16)
     ap.add_argument("--experiment", default=None, choices=["skip-reorth", "post", "batched", "adjoint"],
                     help="run the Section 6.4 comparison instead of the benchmark")
@@ -498,7 +503,7 @@ def main():
         post_experiment()
         return
     if args.experiment == "batched":
-        batched_experiment(args.steps, args.warmup, args.no_cpu)
+        batched_experiment(args.steps, args.warmup, args.no_cpu, tune=not args.no_tune)
         return
     if args.experiment == "adjoint":
         adjoint_experiment(args.steps, args.warmup, args.no_cpu)
