@@ -184,6 +184,7 @@ int gemm_batched(int op, int cls, const BatchGemm* desc, int count, int64_t tota
                  int prof_id, double flops, double bytes, hipStream_t s) {
   if (count <= 0 || total_tiles <= 0) return kOk;
   if (op == kBatchDD && cls == kTileG16) return kEInval;
+  if (total_tiles > INT32_MAX) return kEInval;  // one-dimensional grid
   ProfScope ps(prof_id, flops, bytes, s);
   switch (cls) {
     case kTileG16: launch_batched<BatchG16>(op, desc, count, total_tiles, s); break;
@@ -199,6 +200,7 @@ int gemm_batched(int op, int cls, const BatchGemm* desc, int count, int64_t tota
 int gemm_batched_reduce(int op, const BatchGemm* desc, int count, int64_t total_rblocks,
                         int prof_id, hipStream_t s) {
   if (count <= 0 || total_rblocks <= 0) return kOk;
+  if (total_rblocks > INT32_MAX) return kEInval;
   if (op == kBatchDD) return kEInval;
   const dim3 grid(static_cast<unsigned>(total_rblocks));
   ProfScope ps(prof_id, 0.0, 0.0, s);

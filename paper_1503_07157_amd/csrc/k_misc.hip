@@ -218,6 +218,7 @@ int64_t convert_blocks(int64_t m, int64_t n) {
 
 int convert_batched(const BatchConvert* desc, int count, int64_t total_blocks, hipStream_t s) {
   if (count <= 0 || total_blocks <= 0) return kOk;
+  if (total_blocks > INT32_MAX) return kEInval;  // one-dimensional grid
   ProfScope ps(kKBatchMisc, 0.0, 0.0, s);
   hipLaunchKernelGGL(convert_batched_kernel, dim3(static_cast<unsigned>(total_blocks)),
                      dim3(kSumThreads), 0, s, desc, count);

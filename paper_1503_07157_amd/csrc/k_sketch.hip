@@ -168,6 +168,7 @@ int64_t sketch_blocks(int64_t n, int w) { return ((n + 1) / 2 + 255) / 256 * w; 
 
 int sketch_batched(const BatchSketch* desc, int count, int64_t total_blocks, hipStream_t s) {
   if (count <= 0 || total_blocks <= 0) return kOk;
+  if (total_blocks > INT32_MAX) return kEInval;  // one-dimensional grid
   ProfScope ps(kKSketch, 0.0, 0.0, s);
   hipLaunchKernelGGL(sketch_batched_kernel, dim3(static_cast<unsigned>(total_blocks)), dim3(256),
                      0, s, desc, count);

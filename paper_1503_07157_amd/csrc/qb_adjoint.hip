@@ -122,7 +122,8 @@ void each_product(const Dims& d, F f) {
     f(n, w, m);            // A^T X
     f(w, n, m);            // Q_i^T R-bar
     f(w, w, std::max(m, n));  // Q^T G in the orth adjoint
-    f(m, w, w);            // (G - Q S) R^{-T}, Q S
+    f(m, w, w);            // (G - Q S) R^{-T}, Q S, on m rows
+    f(n, w, w);            // the same on n rows (power iterations)
     f(m, n, d.Kr);         // rank update of dA
     if (k > 0) {
       f(k, w, n);          // Bbar X

@@ -128,3 +128,19 @@ def test_adjoint_bitwise_reproducible(cuda):
     d1 = qbmi.qb_adjoint(A, Q, B, dQ, dB, b, s, 1, 4)
     d2 = qbmi.qb_adjoint(A, Q, B, dQ, dB, b, s, 1, 4)
     assert torch.equal(d1, d2)
+
+
+@pytest.mark.parametrize("m,n,b,s", [(400, 700, 128, 2), (900, 500, 160, 2)])
+def test_adjoint_wide_panels(cuda, m, n, b, s):
+    """Panels wider than 64 (split depth in the b x b products of the orth
+    adjoint, on m and on n rows) with one power iteration."""
+    A = synth.prescribed_svd(m, n, np.exp(-np.arange(1, min(m, n) + 1) / 60.0), 12, 13)
+    g = np.random.default_rng(4)
+    dQ, dB = g.standard_normal((m, b * s)), g.standard_normal((b * s, n))
+    _, _, dAo = qb_fixed_vjp(A, dQ, dB, b, s, 1, 8)
+    Ad = dev(A)
+    Q, B = qbmi.qb_fixed(Ad, b, s, 1, 8)
+    dA = qbmi.qb_adjoint(Ad, Q, B, dev(dQ), dev(dB), b, s, 1, 8).cpu().numpy()
+    e = rel(dA, dAo)
+    print(f"[case] {m}x{n} b={b}: rel err vs oracle {e:.2e}", flush=True)
+    assert e <= 1e-10
