@@ -472,6 +472,53 @@ def adjoint_experiment(steps, warmup, no_cpu):
                       "dtype": "f32 input, f64 arithmetic", "data": "synthetic"}), flush=True)
 
 
+def precision_experiment():
+    """The precision sweep: 20000 x 16000 matrices with s_j = 1/j and with a
+    spectral gap (s_j = 1 for j <= 500, 1e-6 after), b = 256, P = 0,
+    eps = 1e-8 ||A||_F, the sampling products and B_i in float64, FP32 and
+    bf16x3.  Reports per variant the seconds, rank, stop reason and the true
+    error ||A - Q B||_F / ||A||_F (computed on the GPU).  The float64 run is
+    the reference the others are read against; the oracle itself is pinned
+    to the float64 path on these matrices through the first block
+    (tests/test_gpu_fullsize.py).  Prints one JSON line."""
+    import torch
+    import paper_1503_07157_amd as qbmi
+    import synth
+
+    rows = []
+    variants = [("f64", "f64"), ("f32", "f64"), ("bf16x3", "f64"), ("f64", "f32"),
+                ("f64", "bf16x3")]
+    for name in ("inv1_20000x16000", "gap_20000x16000"):
+        wl = synth.workload(name)
+        log(f"[bench] precision: generating {name}")
+        A = synth.workload_matrix_gpu(name)
+        nA = float(torch.linalg.norm(A))
+        eps = wl.eps_rel * nA
+        ws = None
+        for sample, bgemm in variants:
+            res = qbmi.qb_factor(A, eps, wl.b, 0, wl.seed_omega, sample=sample, bgemm=bgemm,
+                                 workspace=ws)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = qbmi.qb_factor(A, eps, wl.b, 0, wl.seed_omega, sample=sample, bgemm=bgemm,
+                                 workspace=ws)
+            torch.cuda.synchronize()
+            sec = time.perf_counter() - t0
+            err = residual_rel(torch, A, res)
+            fl = nominal_flops(wl.m, wl.n, res.k, 0)
+            rows.append({"workload": name, "sample": sample, "bgemm": bgemm, "k": res.k,
+                         "stop": res.stop_reason, "status": res.status, "seconds": sec,
+                         "gflops": fl / sec / 1e9, "rel_err": err})
+            log(f"[bench] precision {name} sample={sample} B={bgemm}: k={res.k} "
+                f"{res.stop_reason} {sec * 1e3:.0f} ms rel_err={err:.2e}")
+            del res
+            torch.cuda.empty_cache()
+        del A
+        torch.cuda.empty_cache()
+    print(json.dumps({"experiment": "precision", "eps_rel": 1e-8, "b": 256, "power_iters": 0,
+                      "rows": rows, "data": "synthetic"}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -485,7 +532,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true",
                     help="batched experiment: keep the default tile table (no tuning pass)")
     ap.add_argument("--cpu-blocks", type=int, default=16)
-    ap.add_argument("--experiment", default=None, choices=["skip-reorth", "post", "batched", "adjoint"],
+    ap.add_argument("--experiment", default=None, choices=["skip-reorth", "post", "batched", "adjoint", "precision"],
                     help="run the Section 6.4 comparison instead of the benchmark")
     ap.add_argument("--matrix", default="workload", choices=["workload", "gaussian"],
                     help="gaussian: i.i.d. N(0, 1/m) entries of the workload's shape instead of "
@@ -507,6 +554,9 @@ def main():
         return
     if args.experiment == "adjoint":
         adjoint_experiment(args.steps, args.warmup, args.no_cpu)
+        return
+    if args.experiment == "precision":
+        precision_experiment()
         return
 
     import torch
