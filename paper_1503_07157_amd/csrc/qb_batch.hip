@@ -8,10 +8,11 @@
 // then copies every problem's scalars to the host at once and applies the
 // same stopping rule as qb_factor to each.  Problems stop independently;
 // the launches of an iteration cover only the active ones.  Products use
-// 64 x 64 MFMA tiles (problem sizes up to a few thousand, panels <= 64
-// wide), with a workgroup -> (problem, tile) table; the Cholesky runs one
-// workgroup per problem.  Inputs are float; every stored value and every
-// product is float64, so each problem follows the float64 oracle.
+// MFMA tiles of a class chosen per product role and panel width (a table,
+// see g_tile), one launch per class in use, with a workgroup -> (problem,
+// tile, depth chunk) mapping; the Cholesky runs one workgroup per problem.
+// Inputs are float; every stored value and every product is float64, so
+// each problem follows the float64 oracle.
 #include <algorithm>
 #include <atomic>
 #include <cmath>
