@@ -162,18 +162,22 @@ __device__ __forceinline__ double readlane_d(double v, int l) {
       static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
 }
 
-// 1 / sqrt(d) for d > 0: hardware estimate and two Newton steps
-// y <- y + (y/2)(1 - d y^2), accurate to a few ulps.  Arguments below
-// 2^-1000 (where the estimate loses range) take the IEEE path.
-__device__ __forceinline__ double rsqrt_refined(double d) {
-  if (d < 0x1p-1000) return 1.0 / sqrt(d);
-  double y = __builtin_amdgcn_rsq(d);
+// 1 / sqrt(d) for d > 0, without branches: the hardware estimate and two
+// Newton steps y <- y + (y/2)(1 - d y^2), accurate to a few ulps.  A d
+// below 2^-1000 (where the estimate loses range) is scaled by 2^256 first
+// and the result by 2^128, both exact.  hi is the upper word of d, passed
+// separately so that for a uniform d the range test is one 32-bit scalar
+// compare.  A d <= 0 gives a value the caller discards.
+__device__ __forceinline__ double rsqrt_refined(double d, unsigned hi) {
+  const bool tiny = hi < 0x01700000u;  // exponent field below that of 2^-1000
+  const double ds = d * (tiny ? 0x1p256 : 1.0);
+  double y = __builtin_amdgcn_rsq(ds);
 #pragma unroll
   for (int it = 0; it < 2; ++it) {
-    const double e = fma(-(d * y), y, 1.0);
+    const double e = fma(-(ds * y), y, 1.0);
     y = fma(0.5 * y, e, y);
   }
-  return y;
+  return y * (tiny ? 0x1p128 : 1.0);
 }
 
 constexpr int kPanel = 16;  // Cholesky panel width
@@ -201,12 +205,27 @@ __device__ __forceinline__ void chol_panel(double* Ts, int p, int w, double thre
       x[a][jj] = (i < WMAX) ? Ts[(p + jj) * TS + i] : 0.0;
     });
   });
+  // lane J collects flag and 1 / L[c][c] of column c = p + J, written once
+  // after the panel so that no lane-0 store sits in the column chain
+  int fl = 0;
+  double rd = 1.0;
   static_for<kPanel>([&](auto jj) {
     constexpr int J = decltype(jj)::value;
     const int c = p + J;
-    const double d = readlane_d(x[0][J], J);  // row c lives in lane J, slot 0
+    // pivot: row c lives in lane J, slot 0
+    const unsigned long long xu = static_cast<unsigned long long>(__double_as_longlong(x[0][J]));
+    const unsigned dlo = static_cast<unsigned>(
+        __builtin_amdgcn_readlane(static_cast<int>(static_cast<unsigned>(xu)), J));
+    unsigned dhi = static_cast<unsigned>(
+        __builtin_amdgcn_readlane(static_cast<int>(static_cast<unsigned>(xu >> 32)), J));
+    const double d = __longlong_as_double(
+        static_cast<long long>((static_cast<unsigned long long>(dhi) << 32) | dlo));
     const bool keep = (c < w) && gpos && (d > thresh);
-    const double r = keep ? rsqrt_refined(d) : 0.0;
+    // opaque copy of the upper word: keeps the range test a 32-bit scalar
+    // compare instead of a 64-bit vector compare of d
+    asm("" : "+s"(dhi));
+    const double rr = rsqrt_refined(d, dhi);  // computed always, selected below
+    const double r = keep ? rr : 0.0;
     static_for<RA>([&](auto a) { x[a][J] *= r; });
     // rank-one update of the panel's later columns
     static_for<kPanel - 1 - J>([&](auto t) {
@@ -219,11 +238,13 @@ __device__ __forceinline__ void chol_panel(double* Ts, int p, int w, double thre
         asm volatile("" : "+v"(x[a][K]));
       });
     });
-    if (lane == 0) {
-      flag[c] = keep ? 1 : 0;
-      rdiag[c] = keep ? r : 1.0;
-    }
+    fl = (lane == J) ? (keep ? 1 : 0) : fl;
+    rd = (lane == J) ? (keep ? r : 1.0) : rd;
   });
+  if (lane < kPanel) {
+    flag[p + lane] = fl;
+    rdiag[p + lane] = rd;
+  }
   static_for<kPanel>([&](auto jj) {
     static_for<RA>([&](auto a) {
       const int i = p + lane + 64 * a;
