@@ -162,39 +162,39 @@ __device__ __forceinline__ double readlane_d(double v, int l) {
       static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
 }
 
-// 1 / sqrt(d) for d > 0, without branches: the hardware estimate and two
-// Newton steps y <- y + (y/2)(1 - d y^2), accurate to a few ulps.  A d
-// below 2^-1000 (where the estimate loses range) is scaled by 2^256 first
-// and the result by 2^128, both exact.  hi is the upper word of d, passed
-// separately so that for a uniform d the range test is one 32-bit scalar
-// compare.  A d <= 0 gives a value the caller discards.
-__device__ __forceinline__ double rsqrt_refined(double d, unsigned hi) {
-  const bool tiny = hi < 0x01700000u;  // exponent field below that of 2^-1000
-  const double ds = d * (tiny ? 0x1p256 : 1.0);
-  double y = __builtin_amdgcn_rsq(ds);
-#pragma unroll
-  for (int it = 0; it < 2; ++it) {
-    const double e = fma(-(ds * y), y, 1.0);
-    y = fma(0.5 * y, e, y);
-  }
-  return y * (tiny ? 0x1p128 : 1.0);
-}
-
 constexpr int kPanel = 16;  // Cholesky panel width
 
 // Factor panel columns [p, p + 16) of the LDS matrix (Ts[j * TS + i] holds
 // L[i][j], i >= j; rows p.. hold the updated trailing part).  Run by one
 // wave: lane l holds rows p + l + 64 a.  Column c is kept when its pivot
 // exceeds thresh; a dropped column becomes zero.  Sets flag[c] and
-// rdiag[c] = 1 / L[c][c] (1 for a dropped or padding column).
+// rdiag[c] = 1 / L[c][c] (1 for a dropped or padding column).  G was scaled
+// so that every pivot above thresh lies in (2^-41, 2).
 //
 // The column loop needs no per-lane tests: scaling a whole column by
 // 1/sqrt(d) leaves sqrt(d) on the diagonal lane, and lanes above the
 // diagonal only carry values nobody reads (cleared when written back).
-template <int WMAX>
+//
+// Column chain.  With G' the matrix after the updates of the columns before
+// c, L[c+1][c] = G'[c+1][c] r_c and the next pivot is
+// d_{c+1} = G'[c+1][c+1] - L[c+1][c]^2: one product and one fma of broadcast
+// values, the same operations, in the same order, as the vector update of
+// column c+1 performs on lane c+1.  So r_{c+1} = 1/sqrt(d_{c+1}) is formed
+// while the vector updates of column c are issued, one stage between two
+// updates, and the wave's in-order issue hides the chain's latency.
+// 1/sqrt: the hardware estimate y (relative error below 2^-24) with one
+// third-order correction y + y e (1/2 + 3/8 e), e = 1 - d y^2, to about
+// one ulp.
+//
+// RA row slots per lane are live (rows p .. p + 64 RA - 1 cover the rows
+// left).  Rows past WMAX are read from and written to the padding row
+// (index WMAX) of each LDS column, which nothing else reads, so the loads
+// and stores need no masks.
+template <int WMAX, int RA>
 __device__ __forceinline__ void chol_panel(double* Ts, int p, int w, double thresh, bool gpos,
                                            int* flag, double* rdiag) {
-  constexpr int TS = WMAX + 1, RA = WMAX / 64;
+  constexpr int TS = WMAX + 1;
+  constexpr int kStages = 7;
   // opaque per call, so per-lane values are not hoisted out of the panel loop
   int lane = threadIdx.x & 63;
   asm volatile("" : "+v"(lane));
@@ -202,44 +202,79 @@ __device__ __forceinline__ void chol_panel(double* Ts, int p, int w, double thre
   static_for<kPanel>([&](auto jj) {
     static_for<RA>([&](auto a) {
       const int i = p + lane + 64 * a;
-      x[a][jj] = (i < WMAX) ? Ts[(p + jj) * TS + i] : 0.0;
+      const double v = Ts[(p + jj) * TS + (i < WMAX ? i : WMAX)];
+      x[a][jj] = (i < WMAX) ? v : 0.0;
     });
   });
   // lane J collects flag and 1 / L[c][c] of column c = p + J, written once
   // after the panel so that no lane-0 store sits in the column chain
   int fl = 0;
   double rd = 1.0;
+  // the first pivot and its reciprocal square root, unhidden
+  double r;
+  bool keep;
+  {
+    const double d = readlane_d(x[0][0], 0);
+    const double y = __builtin_amdgcn_rsq(d);
+    const double e = fma(-(d * y), y, 1.0);
+    const double yc = fma(y * e, fma(0.375, e, 0.5), y);
+    keep = (p < w) && gpos && (d > thresh);
+    r = keep ? yc : 0.0;
+  }
   static_for<kPanel>([&](auto jj) {
     constexpr int J = decltype(jj)::value;
-    const int c = p + J;
-    // pivot: row c lives in lane J, slot 0
-    const unsigned long long xu = static_cast<unsigned long long>(__double_as_longlong(x[0][J]));
-    const unsigned dlo = static_cast<unsigned>(
-        __builtin_amdgcn_readlane(static_cast<int>(static_cast<unsigned>(xu)), J));
-    unsigned dhi = static_cast<unsigned>(
-        __builtin_amdgcn_readlane(static_cast<int>(static_cast<unsigned>(xu >> 32)), J));
-    const double d = __longlong_as_double(
-        static_cast<long long>((static_cast<unsigned long long>(dhi) << 32) | dlo));
-    const bool keep = (c < w) && gpos && (d > thresh);
-    // opaque copy of the upper word: keeps the range test a 32-bit scalar
-    // compare instead of a 64-bit vector compare of d
-    asm("" : "+s"(dhi));
-    const double rr = rsqrt_refined(d, dhi);  // computed always, selected below
-    const double r = keep ? rr : 0.0;
+    // chain state for column J + 1 (its broadcast inputs read before this
+    // column's scaling and updates)
+    double g10 = 0.0, g11 = 0.0, t = 0.0, dn = 0.0, y = 0.0, u = 0.0, e = 0.0, q = 0.0, pc = 0.0;
+    if constexpr (J + 1 < kPanel) {
+      g10 = readlane_d(x[0][J], J + 1);
+      g11 = readlane_d(x[0][J + 1], J + 1);
+    }
+    auto stage = [&](auto sidx) {
+      constexpr int S = decltype(sidx)::value;
+      if constexpr (J + 1 < kPanel) {
+        if constexpr (S == 0) { t = g10 * r; asm volatile("" : "+v"(t)); }
+        if constexpr (S == 1) { dn = fma(-t, t, g11); asm volatile("" : "+v"(dn)); }
+        if constexpr (S == 2) { y = __builtin_amdgcn_rsq(dn); asm volatile("" : "+v"(y)); }
+        if constexpr (S == 3) { u = dn * y; asm volatile("" : "+v"(u)); }
+        if constexpr (S == 4) { e = fma(-u, y, 1.0); asm volatile("" : "+v"(e)); }
+        if constexpr (S == 5) {
+          q = y * e;
+          pc = fma(0.375, e, 0.5);
+          asm volatile("" : "+v"(q), "+v"(pc));
+        }
+        if constexpr (S == 6) { y = fma(q, pc, y); asm volatile("" : "+v"(y)); }
+      }
+    };
     static_for<RA>([&](auto a) { x[a][J] *= r; });
-    // rank-one update of the panel's later columns
-    static_for<kPanel - 1 - J>([&](auto t) {
-      constexpr int K = J + 1 + decltype(t)::value;
-      const double lk = readlane_d(x[0][J], K);  // L[p + K][c]
+    stage(std::integral_constant<int, 0>{});
+    // rank-one update of the panel's later columns, one chain stage after
+    // each; the multiplier of column c + 1 is the chain's t = L[c+1][c]
+    static_for<kPanel - 1 - J>([&](auto tt) {
+      constexpr int T = decltype(tt)::value;
+      constexpr int K = J + 1 + T;
+      double lk;  // L[p + K][c]
+      if constexpr (T == 0) lk = t;
+      else lk = readlane_d(x[0][J], K);
       static_for<RA>([&](auto a) {
         x[a][K] = fma(-x[a][J], lk, x[a][K]);
         // keep the update here; left to itself the compiler sinks it to the
         // use of column K and holds every broadcast value in scalar registers
         asm volatile("" : "+v"(x[a][K]));
       });
+      if constexpr (T + 1 < kStages) stage(std::integral_constant<int, T + 1>{});
+    });
+    // stages left over when fewer updates than stages remain
+    static_for<kStages>([&](auto sidx) {
+      constexpr int S = decltype(sidx)::value;
+      if constexpr (S >= 1 && S >= kPanel - J) stage(sidx);
     });
     fl = (lane == J) ? (keep ? 1 : 0) : fl;
     rd = (lane == J) ? (keep ? r : 1.0) : rd;
+    if constexpr (J + 1 < kPanel) {
+      keep = (p + J + 1 < w) && gpos && (dn > thresh);
+      r = keep ? y : 0.0;
+    }
   });
   if (lane < kPanel) {
     flag[p + lane] = fl;
@@ -248,7 +283,7 @@ __device__ __forceinline__ void chol_panel(double* Ts, int p, int w, double thre
   static_for<kPanel>([&](auto jj) {
     static_for<RA>([&](auto a) {
       const int i = p + lane + 64 * a;
-      if (i < WMAX) Ts[(p + jj) * TS + i] = (a > 0 || lane >= jj) ? x[a][jj] : 0.0;
+      Ts[(p + jj) * TS + (i < WMAX ? i : WMAX)] = (a > 0 || lane >= jj) ? x[a][jj] : 0.0;
     });
   });
 }
@@ -291,14 +326,22 @@ __device__ __forceinline__ void chol_trailing(double* Ts, int p, int w) {
 // Result in LDS: Ts[c * TS + i] = T[c][i] = L[i][c] (T = L^T upper
 // triangular, zero for i < c and in the padding up to WMAX); flag, rdiag,
 // the kept list and count, and the list of dropped or padding columns.
+//
+// G enters scaled by 2^(2 sexp), chosen so that its largest diagonal entry
+// lies in [1/2, 2) (sexp = 0 for a zero or non-finite maximum); the factor
+// of the scaled matrix is 2^sexp T, and its inverse 2^-sexp T^{-1}.  Power
+// of two scaling is exact and leaves every pivot test unchanged, and it
+// keeps every kept pivot inside the range of the hardware reciprocal square
+// root estimate.
 template <int WMAX, int NW>
 __device__ __forceinline__ void chol_blocked(const double* __restrict__ G, int w, double* Ts,
                                              int* flag, double* rdiag, int* klist, int* kcnt,
-                                             int* ulist, int* ucnt) {
+                                             int* ulist, int* ucnt, int& sexp) {
   constexpr int TS = WMAX + 1;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   // lower triangle of G into Ts, everything else zero; every load of a
-  // thread is issued before the first store
+  // thread is issued before the first store.  Each wave also reads the
+  // diagonal to find the scale.
   {
     constexpr int PER = WMAX * WMAX / (64 * NW);
     double v[PER];
@@ -308,10 +351,17 @@ __device__ __forceinline__ void chol_blocked(const double* __restrict__ G, int w
       const int i = idx % WMAX, j = idx / WMAX;
       v[q] = (i < w && j < w && i >= j) ? G[i + static_cast<int64_t>(j) * w] : 0.0;
     }
+    double gd = 0.0;
+    for (int c = lane; c < w; c += 64) gd = fmax(gd, G[c + static_cast<int64_t>(c) * w]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) gd = fmax(gd, __shfl_xor(gd, off));
+    int ex = 0;
+    if (gd > 0.0 && gd <= 0x1.fffffffffffffp+1023) (void)frexp(gd, &ex);
+    sexp = (gd > 0.0 && gd <= 0x1.fffffffffffffp+1023) ? ((1 - ex) >> 1) : 0;
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int idx = threadIdx.x + 64 * NW * q;
-      Ts[(idx / WMAX) * TS + idx % WMAX] = v[q];
+      Ts[(idx / WMAX) * TS + idx % WMAX] = ldexp(v[q], 2 * sexp);
     }
   }
   lds_barrier();
@@ -323,7 +373,12 @@ __device__ __forceinline__ void chol_blocked(const double* __restrict__ G, int w
   }
   const double thresh = kDropRel * gmax;
   for (int p = 0; p < w; p += kPanel) {
-    if (wave == 0) chol_panel<WMAX>(Ts, p, w, thresh, gmax > 0.0, flag, rdiag);
+    if (wave == 0) {
+      if (WMAX > 64 && p + 64 < WMAX)
+        chol_panel<WMAX, WMAX / 64>(Ts, p, w, thresh, gmax > 0.0, flag, rdiag);
+      else
+        chol_panel<WMAX, 1>(Ts, p, w, thresh, gmax > 0.0, flag, rdiag);
+    }
     lds_barrier();
     chol_trailing<WMAX, NW>(Ts, p, w);
     lds_barrier();
@@ -377,22 +432,28 @@ struct LdsInvShape {
 };
 
 // One 16 x 16 output block (bi, bj) of C = alpha * A B with S x S operands
-// in LDS (row stride TS): A at (ra, ka), B at (kb, cb), C at (rc, cc).
-template <int TS, int S>
+// in LDS (row stride TS): A at (ra, ka), B at (kb, cb), C at (rc, cc).  The
+// sum runs over the 16-deep slices [k0, k1) only; the caller passes the
+// range outside which one triangular operand is zero.
+template <int TS>
 __device__ __forceinline__ void lds_block16(double* M, int ra, int ka, int kb, int cb, int rc,
-                                            int cc, double alpha, int bi, int bj) {
+                                            int cc, double alpha, int bi, int bj, int k0, int k1) {
   typedef double d4 __attribute__((ext_vector_type(4)));
   const int lane = threadIdx.x & 63;
-  double a[S / 4], b[S / 4];
-#pragma unroll
-  for (int k4 = 0; k4 < S / 4; ++k4) {
-    a[k4] = M[(ra + 16 * bi + (lane & 15)) * TS + ka + 4 * k4 + (lane >> 4)];
-    b[k4] = M[(kb + 4 * k4 + (lane >> 4)) * TS + cb + 16 * bj + (lane & 15)];
-  }
+  const double* pa = M + (ra + 16 * bi + (lane & 15)) * TS + ka + (lane >> 4);
+  const double* pb = M + (kb + (lane >> 4)) * TS + cb + 16 * bj + (lane & 15);
   d4 acc = (d4){0.0, 0.0, 0.0, 0.0};
+  for (int k16 = k0; k16 < k1; ++k16) {
+    double a[4], b[4];
 #pragma unroll
-  for (int k4 = 0; k4 < S / 4; ++k4)
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[k4], b[k4], acc, 0, 0, 0);
+    for (int k4 = 0; k4 < 4; ++k4) {
+      a[k4] = pa[16 * k16 + 4 * k4];
+      b[k4] = pb[(16 * k16 + 4 * k4) * TS];
+    }
+#pragma unroll
+    for (int k4 = 0; k4 < 4; ++k4)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[k4], b[k4], acc, 0, 0, 0);
+  }
 #pragma unroll
   for (int r = 0; r < 4; ++r)
     M[(rc + 16 * bi + (lane >> 4) + 4 * r) * TS + cc + 16 * bj + (lane & 15)] = alpha * acc[r];
@@ -412,7 +473,8 @@ __device__ __forceinline__ void chol_inv_lds_body(const double* __restrict__ G, 
   __shared__ int kcnt, ucnt;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 
-  chol_blocked<WMAX, NW>(G, w, Ts, flag, rdiag, klist, &kcnt, ulist, &ucnt);
+  int sexp;
+  chol_blocked<WMAX, NW>(G, w, Ts, flag, rdiag, klist, &kcnt, ulist, &ucnt, sexp);
   // T' = T with every dropped or padding index u turned into a unit row and
   // column (its inverse restricted to the kept indices is T_kept^{-1})
   const int nu = ucnt;
@@ -450,18 +512,28 @@ __device__ __forceinline__ void chol_inv_lds_body(const double* __restrict__ G, 
     constexpr int pairs = WMAX / (2 * s);
     constexpr int nb = s / 16;
     constexpr int jobs = pairs * nb * nb;
-    // M = T_AB X_B, stored at rows [ob, ob + s), columns [oa, oa + s)
-    for (int job = wave; job < jobs; job += NW) {
+    // jobs are dealt in snake order (every other round reversed) so that
+    // each wave gets a long and a short triangular sum
+    auto job_at = [&](int j) {
+      const int t = j / NW, i = j % NW;
+      return (t & 1) ? t * NW + (NW - 1 - i) : j;
+    };
+    // M = T_AB X_B, stored at rows [ob, ob + s), columns [oa, oa + s);
+    // X_B is upper triangular, so slice k of column block bj needs k <= bj
+    for (int j = wave; j < jobs; j += NW) {
+      const int job = job_at(j);
       const int pr = job / (nb * nb), q = job % (nb * nb);
       const int oa = 2 * s * pr, ob = oa + s;
-      lds_block16<TS, s>(Ts, oa, ob, ob, ob, ob, oa, 1.0, q / nb, q % nb);
+      lds_block16<TS>(Ts, oa, ob, ob, ob, ob, oa, 1.0, q / nb, q % nb, 0, q % nb + 1);
     }
     lds_barrier();
-    // X_AB = -X_A M over T_AB: A = X_A at (oa, oa), B = M at (ob, oa)
-    for (int job = wave; job < jobs; job += NW) {
+    // X_AB = -X_A M over T_AB: A = X_A at (oa, oa), B = M at (ob, oa);
+    // X_A is upper triangular, so row block bi needs slices k >= bi
+    for (int j = wave; j < jobs; j += NW) {
+      const int job = job_at(j);
       const int pr = job / (nb * nb), q = job % (nb * nb);
       const int oa = 2 * s * pr, ob = oa + s;
-      lds_block16<TS, s>(Ts, oa, oa, ob, oa, oa, ob, -1.0, q / nb, q % nb);
+      lds_block16<TS>(Ts, oa, oa, ob, oa, oa, ob, -1.0, q / nb, q % nb, q / nb, nb);
     }
     lds_barrier();
     // clear M: the joined 2s x 2s block must be upper triangular again
@@ -473,13 +545,14 @@ __device__ __forceinline__ void chol_inv_lds_body(const double* __restrict__ G, 
     lds_barrier();
   });
 
-  // expanded inverse: column a <- column kept[a] of T'^{-1}, zero for a >= count
+  // expanded inverse: column a <- column kept[a] of T'^{-1} (undoing the
+  // scale of G), zero for a >= count
   const int wk = kcnt;
   for (int a = wave; a < w; a += NW) {
     double* col = Tinv + static_cast<int64_t>(a) * w;
     if (a < wk) {
       const int kc = klist[a];
-      for (int r = lane; r < w; r += 64) col[r] = Ts[r * TS + kc];
+      for (int r = lane; r < w; r += 64) col[r] = ldexp(Ts[r * TS + kc], sexp);
     } else {
       for (int r = lane; r < w; r += 64) col[r] = 0.0;
     }
