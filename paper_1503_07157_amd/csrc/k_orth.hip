@@ -289,37 +289,34 @@ __device__ __forceinline__ void chol_panel(double* Ts, int p, int w, double thre
 }
 
 // Trailing update after panel p: L[i][j] -= sum_t L[i][p + t] L[j][p + t]
-// for p + 16 <= j <= i < 16 ceil(w / 16), as 16 x 16 MFMA blocks spread
-// over the waves (diagonal blocks are updated whole; their upper halves are
-// cleared when their own panel is written).
-template <int WMAX, int NW>
-__device__ __forceinline__ void chol_trailing(double* Ts, int p, int w) {
+// for p + 16 <= j <= i < 16 ceil(w / 16), as 16 x 16 MFMA blocks (diagonal
+// blocks are updated whole; their upper halves are cleared when their own
+// panel is written).  Block (bi, bj), bj <= bi, counts from q = p + 16.
+__device__ __forceinline__ void chol_trail_block(double* Ts, int TS, int p, int bi, int bj) {
   typedef double d4 __attribute__((ext_vector_type(4)));
-  constexpr int TS = WMAX + 1;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
   const int q = p + kPanel;
-  if (q >= w) return;
-  const int nb = (w - q + 15) / 16;
-  const int jobs = nb * (nb + 1) / 2;
   const int lr = lane & 15, lk = lane >> 4;
-  for (int job = wave; job < jobs; job += NW) {
-    int bi = static_cast<int>((sqrtf(8.0f * job + 1.0f) - 1.0f) * 0.5f);
-    while ((bi + 1) * (bi + 2) / 2 <= job) ++bi;
-    while (bi * (bi + 1) / 2 > job) --bi;
-    const int bj = job - bi * (bi + 1) / 2;
-    double a[4], b[4];
+  double a[4], b[4];
 #pragma unroll
-    for (int k4 = 0; k4 < 4; ++k4) {
-      a[k4] = Ts[(p + 4 * k4 + lk) * TS + q + 16 * bi + lr];
-      b[k4] = Ts[(p + 4 * k4 + lk) * TS + q + 16 * bj + lr];
-    }
-    d4 acc = (d4){0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int k4 = 0; k4 < 4; ++k4) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[k4], b[k4], acc, 0, 0, 0);
-    double* col = Ts + (q + 16 * bj + lr) * TS + q + 16 * bi + lk;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) col[4 * r] -= acc[r];
+  for (int k4 = 0; k4 < 4; ++k4) {
+    a[k4] = Ts[(p + 4 * k4 + lk) * TS + q + 16 * bi + lr];
+    b[k4] = Ts[(p + 4 * k4 + lk) * TS + q + 16 * bj + lr];
   }
+  d4 acc = (d4){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k4 = 0; k4 < 4; ++k4) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[k4], b[k4], acc, 0, 0, 0);
+  double* col = Ts + (q + 16 * bj + lr) * TS + q + 16 * bi + lk;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) col[4 * r] -= acc[r];
+}
+
+// (bi, bj) of lower-triangle index job = bi (bi + 1) / 2 + bj, bj <= bi
+__device__ __forceinline__ void tri_index(int job, int& bi, int& bj) {
+  bi = static_cast<int>((sqrtf(8.0f * job + 1.0f) - 1.0f) * 0.5f);
+  while ((bi + 1) * (bi + 2) / 2 <= job) ++bi;
+  while (bi * (bi + 1) / 2 > job) --bi;
+  bj = job - bi * (bi + 1) / 2;
 }
 
 // Blocked Cholesky with dropping of the w x w matrix G (column-major, ld w).
@@ -372,15 +369,32 @@ __device__ __forceinline__ void chol_blocked(const double* __restrict__ G, int w
     for (int off = 32; off > 0; off >>= 1) gmax = fmax(gmax, __shfl_xor(gmax, off));
   }
   const double thresh = kDropRel * gmax;
-  for (int p = 0; p < w; p += kPanel) {
-    if (wave == 0) {
-      if (WMAX > 64 && p + 64 < WMAX)
-        chol_panel<WMAX, WMAX / 64>(Ts, p, w, thresh, gmax > 0.0, flag, rdiag);
-      else
-        chol_panel<WMAX, 1>(Ts, p, w, thresh, gmax > 0.0, flag, rdiag);
-    }
+  auto panel = [&](int p) {
+    if (WMAX > 64 && p + 64 < WMAX)
+      chol_panel<WMAX, WMAX / 64>(Ts, p, w, thresh, gmax > 0.0, flag, rdiag);
+    else
+      chol_panel<WMAX, 1>(Ts, p, w, thresh, gmax > 0.0, flag, rdiag);
+  };
+  // Look-ahead: after panel p, all waves first update the block column of
+  // the next panel; then wave 0 factors that panel while the other waves
+  // finish the trailing update of panel p (blocks bj >= 1, which neither
+  // read nor write the next panel's columns).
+  if (wave == 0) panel(0);
+  lds_barrier();
+  for (int p = 0; p + kPanel < w; p += kPanel) {
+    const int nb = (w - p - kPanel + 15) / 16;
+    for (int bi = wave; bi < nb; bi += NW) chol_trail_block(Ts, TS, p, bi, 0);
     lds_barrier();
-    chol_trailing<WMAX, NW>(Ts, p, w);
+    if (wave == 0) {
+      panel(p + kPanel);
+    } else {
+      const int rest = (nb - 1) * nb / 2;  // triangle of blocks with bj >= 1
+      for (int job = wave - 1; job < rest; job += NW - 1) {
+        int bi, bj;
+        tri_index(job, bi, bj);
+        chol_trail_block(Ts, TS, p, bi + 1, bj + 1);
+      }
+    }
     lds_barrier();
   }
   // padding columns: dropped, unit pivots
