@@ -47,7 +47,10 @@ def _rng(seed):
 
 
 @pytest.mark.parametrize("m,K,w", [(300, 500, 50), (129, 1000, 128), (2000, 1000, 50),
-                                   (1, 1, 1), (257, 33, 200), (1000, 4100, 256)])
+                                   (1, 1, 1), (257, 33, 200), (1000, 4100, 256),
+                                   # stream-K split of 256-row tiles, ragged rows,
+                                   # width and depth (runs cross tile boundaries)
+                                   (10037, 5003, 100), (4000, 2500, 128)])
 def test_sample_product(cuda, m, K, w):
     r = _rng(m + K + w)
     X = np.asfortranarray(r.standard_normal((m, K)))
