@@ -139,12 +139,14 @@ __host__ __device__ inline int64_t sk_start(const StreamK& k, int64_t g) {
   return g * k.units / k.groups;
 }
 
-// workgroup whose run holds slice u
+// workgroup whose run holds slice u: the largest g with
+// floor(g units / groups) <= u, i.e. ceil((u + 1) groups / units) - 1; in
+// 32-bit arithmetic when the products fit
 __host__ __device__ inline int64_t sk_owner(const StreamK& k, int64_t u) {
-  int64_t g = u * k.groups / k.units;
-  while (g + 1 < k.groups && sk_start(k, g + 1) <= u) ++g;
-  while (g > 0 && sk_start(k, g) > u) --g;
-  return g;
+  if (k.units * k.groups <= int64_t(0xffffffff))
+    return static_cast<int64_t>((static_cast<uint32_t>(u + 1) * static_cast<uint32_t>(k.groups) - 1u) /
+                                static_cast<uint32_t>(k.units));
+  return ((u + 1) * k.groups - 1) / k.units;
 }
 
 // partial slices that tile t receives
@@ -213,7 +215,16 @@ __global__ __launch_bounds__(256) void reduce_kernel(const double* __restrict__ 
   const int64_t total = M * N;
   double sq = 0.0;
   if (idx < total) {
-    const int64_t i = idx % M, j = idx / M;
+    // (row, column) of the element; 32-bit division when the output fits
+    int64_t i, j;
+    if (total <= int64_t(0xffffffff)) {
+      const uint32_t u = static_cast<uint32_t>(idx), mm = static_cast<uint32_t>(M);
+      i = u % mm;
+      j = u / mm;
+    } else {
+      i = idx % M;
+      j = idx / M;
+    }
     const int64_t pidx = i + j * ldp, pstride = ldp * N;
     const int64_t nzs = sk.ut > 0 ? sk_pieces(sk, (j / bn) * sk.tiles_m + i / bm) : split;
     double s = 0.0;
