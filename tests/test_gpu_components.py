@@ -50,7 +50,9 @@ def _rng(seed):
                                    (1, 1, 1), (257, 33, 200), (1000, 4100, 256),
                                    # stream-K split of 256-row tiles, ragged rows,
                                    # width and depth (runs cross tile boundaries)
-                                   (10037, 5003, 100), (4000, 2500, 128)])
+                                   (10037, 5003, 100), (4000, 2500, 128),
+                                   # unsplit, the T^{-1} application shape
+                                   (10000, 128, 128), (9999, 128, 100)])
 def test_sample_product(cuda, m, K, w):
     r = _rng(m + K + w)
     X = np.asfortranarray(r.standard_normal((m, K)))
