@@ -8,13 +8,14 @@
 // kept columns of Q come first, in their original order, followed by zero
 // columns, and the kept count is left on the device.
 //
-// Cholesky, panels up to 128 wide: one workgroup, G in LDS, right-looking
-// and blocked by 16 columns.  One wave factors a 16-column panel in
-// registers, exchanging values across lanes with readlane (no barrier
-// inside the panel); then all waves apply the trailing update
-// G22 -= L21 L21^T with v_mfma_f64_16x16x4_f64.  Pivots use the hardware
-// reciprocal square root refined by two Newton steps, so each column costs
-// one short dependent chain.  Wider panels (up to 256) keep the lower
+// Cholesky, panels up to 128 wide: one workgroup, G in LDS (scaled by an
+// exact power of two), right-looking and blocked by 16 columns.  One wave
+// factors a 16-column panel in registers, exchanging values across lanes
+// with readlane (no barrier inside the panel), with the next pivot's
+// reciprocal square root computed while the current column's updates
+// issue; the trailing update G22 -= L21 L21^T runs on
+// v_mfma_f64_16x16x4_f64 over the other waves while wave 0 factors the
+// next panel (look-ahead).  Wider panels (up to 256) keep the lower
 // triangle in registers with a rank-one update per column.
 //
 // Inverse: T^{-1} of the kept part, blocked in LDS (16 x 16 diagonal blocks
