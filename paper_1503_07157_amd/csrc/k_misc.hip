@@ -64,6 +64,9 @@ __device__ __forceinline__ void sum_partials_body(const double* __restrict__ par
   __shared__ int fs[kSumThreads];
   double hi = 0.0, lo = 0.0;
   int f = 0;
+  // unrolled so that the loads issue ahead of the compensated sums (whose
+  // order, and so the result, is unchanged)
+#pragma unroll 8
   for (int i = threadIdx.x; i < count; i += kSumThreads) {
     double s, e;
     two_sum(hi, part[i], s, e);
