@@ -125,6 +125,23 @@ def test_orth_matches_oracle(cuda, m, w, cond):
     assert np.linalg.norm(Qg - Qo) < 1e-13 * cond * w
 
 
+@pytest.mark.parametrize("m,w", [(2000, 128), (700, 64), (3000, 100)])
+def test_orth_power_of_two_scale_invariance(cuda, m, w):
+    """orth(2^s X) equals orth(X) bit for bit: the Gram scales by exactly
+    2^2s, the Cholesky works on G brought to a fixed power-of-two range, and
+    T^{-1} comes back scaled by exactly 2^-s (no rounding while every
+    intermediate stays in the normal range, as it does for |s| <= 400
+    here).  Grams of 1e-240 and 1e240 take the same path as Grams near 1."""
+    X = _cond_matrix(m, w, 1e3, seed=w)
+    Q0, k0 = qbmi.orth(dev(X))
+    Q0 = host(Q0)
+    assert k0 == w
+    for s in (-400, -100, 7, 100, 400):
+        Qs, ks = qbmi.orth(dev(np.asfortranarray(np.ldexp(X, s))))
+        assert ks == k0
+        assert np.array_equal(host(Qs).view(np.uint64), Q0.view(np.uint64)), s
+
+
 def test_orth_drops_dependent_and_zero_columns(cuda):
     r = _rng(6)
     x = r.standard_normal((400, 5))
