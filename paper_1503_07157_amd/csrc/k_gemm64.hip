@@ -226,7 +226,12 @@ __global__ __launch_bounds__(256) void reduce_kernel(const double* __restrict__ 
       j = idx / M;
     }
     const int64_t pidx = i + j * ldp, pstride = ldp * N;
-    const int64_t nzs = sk.ut > 0 ? sk_pieces(sk, (j / bn) * sk.tiles_m + i / bm) : split;
+    // tile of the element: row and column below 2^31, so 32-bit division
+    const int64_t nzs =
+        sk.ut > 0 ? sk_pieces(sk, int64_t(static_cast<uint32_t>(j) / static_cast<uint32_t>(bn)) *
+                                          sk.tiles_m +
+                                      static_cast<uint32_t>(i) / static_cast<uint32_t>(bm))
+                  : split;
     double s = 0.0;
     for (int64_t z = 0; z < nzs; ++z) s += part[z * pstride + pidx];
     const int64_t o = transpose_out ? (j + i * ldo) : (i + j * ldo);
@@ -389,6 +394,7 @@ dim3 launch_tn(const double* Qm, int64_t ldq, const double* X, int64_t ldx, doub
 template <class S>
 StreamK plan_sk(int64_t M, int64_t N, int64_t K, int split) {
   const StreamK none{0, 0, 0, 0};
+  if (M >= (int64_t(1) << 31) || N >= (int64_t(1) << 31)) return none;  // 32-bit tile index
   const int64_t tm = cdiv(M, S::BM), tiles = tm * cdiv(N, S::BN);
   const int64_t ut = cdiv(K, BK);
   int64_t g = int64_t(kNumCU) * S::OCC;
