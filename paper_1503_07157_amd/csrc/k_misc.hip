@@ -54,20 +54,21 @@ __global__ __launch_bounds__(kSumThreads) void sumsq_kernel(const double* __rest
   }
 }
 
-// one workgroup: out[0] = hi, out[1] = lo of the sum of part[0..count);
-// iflag[0] = OR of flags[0..count) when flags is non-null
+// one workgroup of NT threads: out[0] = hi, out[1] = lo of the sum of
+// part[0..count); iflag[0] = OR of flags[0..count) when flags is non-null
+template <int NT>
 __device__ __forceinline__ void sum_partials_body(const double* __restrict__ part, int count,
                                                   const int* __restrict__ flags,
                                                   double* __restrict__ out,
                                                   int* __restrict__ iflag) {
-  __shared__ double hs[kSumThreads], ls[kSumThreads];
-  __shared__ int fs[kSumThreads];
+  __shared__ double hs[NT], ls[NT];
+  __shared__ int fs[NT];
   double hi = 0.0, lo = 0.0;
   int f = 0;
   // unrolled so that the loads issue ahead of the compensated sums (whose
   // order, and so the result, is unchanged)
 #pragma unroll 8
-  for (int i = threadIdx.x; i < count; i += kSumThreads) {
+  for (int i = threadIdx.x; i < count; i += NT) {
     double s, e;
     two_sum(hi, part[i], s, e);
     hi = s;
@@ -78,7 +79,7 @@ __device__ __forceinline__ void sum_partials_body(const double* __restrict__ par
   ls[threadIdx.x] = lo;
   fs[threadIdx.x] = f;
   __syncthreads();
-  for (int stride = kSumThreads / 2; stride > 0; stride >>= 1) {
+  for (int stride = NT / 2; stride > 0; stride >>= 1) {
     if (threadIdx.x < stride) {
       double s, e;
       two_sum(hs[threadIdx.x], hs[threadIdx.x + stride], s, e);
@@ -97,18 +98,20 @@ __device__ __forceinline__ void sum_partials_body(const double* __restrict__ par
   }
 }
 
-__global__ __launch_bounds__(kSumThreads) void sum_partials_kernel(const double* __restrict__ part,
-                                                                   int count,
-                                                                   const int* __restrict__ flags,
-                                                                   double* __restrict__ out,
-                                                                   int* __restrict__ iflag) {
-  sum_partials_body(part, count, flags, out, iflag);
+// the per-tile sums of one factorisation (up to 25k for a 10^4 x 10^4
+// downdate) take a wide workgroup
+constexpr int kPartialSumThreads = 1024;
+
+__global__ __launch_bounds__(kPartialSumThreads) void sum_partials_kernel(
+    const double* __restrict__ part, int count, const int* __restrict__ flags,
+    double* __restrict__ out, int* __restrict__ iflag) {
+  sum_partials_body<kPartialSumThreads>(part, count, flags, out, iflag);
 }
 
 // one workgroup per problem of a batch
 __global__ __launch_bounds__(kSumThreads) void sum_batched_kernel(const BatchSum* __restrict__ d) {
   const BatchSum b = d[blockIdx.x];
-  sum_partials_body(b.part, b.count, b.flags, b.out, b.iflag);
+  sum_partials_body<kSumThreads>(b.part, b.count, b.flags, b.out, b.iflag);
 }
 
 constexpr int kConvPer = 8;  // elements per thread in convert_batched_kernel
@@ -208,8 +211,8 @@ int sum_partials_ex(const double* part, int count, const int* flags, double* out
                     hipStream_t s) {
   {
     ProfScope ps(kKNorm, double(count), 8.0 * count, s);
-    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(kSumThreads), 0, s, part, count, flags,
-                       out, out_flag);
+    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(kPartialSumThreads), 0, s, part, count,
+                       flags, out, out_flag);
   }
   QB_HIP_TRY(hipGetLastError());
   return kOk;
