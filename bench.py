@@ -541,7 +541,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
-              f"(this build has no multi-GPU path)", file=sys.stderr)
+              f"(the library has no multi-GPU path)", file=sys.stderr)
         sys.exit(2)
     if args.experiment == "skip-reorth":
         skip_reorth_experiment()

@@ -1,7 +1,7 @@
 """orth(X): orthonormal basis of the column space of X (Section 2.4).
 
-The paper computes orth with a packaged unpivoted QR.  The reading taken for
-this build is Cholesky QR applied twice ("CholQR2"): with G = X^T X = T^T T
+The paper computes orth with a packaged unpivoted QR.  The reading taken here
+is Cholesky QR applied twice ("CholQR2"): with G = X^T X = T^T T
 (T upper triangular with positive diagonal), Q = X T^{-1} is the Q factor of
 the unique thin QR of X with positive diagonal R.  One pass loses
 orthonormality in proportion to cond(X)^2 * u; the second pass, applied to

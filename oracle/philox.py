@@ -2,7 +2,7 @@
 easy as 1, 2, 3", SC'11), written from its published definition.
 
 The paper draws its sketch with Matlab's randn (Figures 3, 4 and 6); it does
-not fix a generator.  This build fixes one counter-based generator so that the
+not fix a generator.  This library fixes one counter-based generator so that the
 sketch is a pure function of (seed, row, global column) and can be reproduced
 bit for bit by the CPU oracle and by the GPU.
 
