@@ -4,19 +4,26 @@ tolerance of 1e-8 on one MI355X.
 
 One step = one complete factorisation (every row of the hot path: sketch,
 sampling product, orth, power iteration, re-projection, B = Q^T A, downdate,
-stopping rule) of a 10000 x 10000 float64 matrix A = U diag(j^-2) V^T
-(U, V: Q factors of seeded Gaussian matrices), block b = 128, with the input
-already resident in HBM.  `value` is nominal GFLOP/s,
+stopping rule) of a 20000 x 16000 float64 matrix A = U diag(1/j) V^T
+(U, V: Q factors of seeded Gaussian matrices), block b = 256, P = 0, with
+the input already resident in HBM.  At eps = 1e-8 ||A||_F the run needs
+every column: k = 16000 in 63 blocks.  `value` is nominal GFLOP/s,
 (6 + 4P) m n k + 2 m k^2 over the measured seconds (the paper's cost model,
-Sections 4.5 and 5.3, with two flops per multiply-add).
+Sections 4.4 and 5.3, with two flops per multiply-add).
 
 The JSON line also carries
-  roofline      the dominant kernel's algorithmic rate, timed with HIP events
-                on its launch stream over one extra profiled factorisation
-                (kept out of the timed steps), against MI355X peak
-  cpu_baseline  the CPU oracle timed on the host on a bounded sample of the
-                same factorisation (the first blocks, same matrix)
-  variants      P = 0 and the mixed-precision sampling forms, same workload
+  roofline        the dominant kernel's algorithmic rate, timed with HIP
+                  events on its launch stream over one extra profiled
+                  factorisation (kept out of the timed steps), against MI355X
+                  peak
+  cpu_baseline    the CPU oracle timed on the host on a bounded sample of the
+                  same factorisation (its first blocks, same matrix), and the
+                  GPU's first blocks compared with it
+  variants        mixed-precision sampling on the same matrix; the
+                  spectral-gap matrix of the same size; the 10000 x 10000
+                  j^-2 workload at P = 0 and 1
+  small_workload  the 2000 x 1000 exp(-j/40) workload: GPU and oracle medians
+                  of 3, the oracle also on one thread
 """
 from __future__ import annotations
 
@@ -133,27 +140,8 @@ def residual_rel(torch, A, res):
     return float(torch.linalg.norm(R) / torch.linalg.norm(A))
 
 
-def cpu_baseline(A_host, eps, wl, P, blocks):
-    import threadpoolctl
-    from oracle import randqb_pb
-
-    kmax = min(blocks * wl.b, min(A_host.shape))
-    t0 = time.perf_counter()
-    res = randqb_pb(A_host, eps, wl.b, P, wl.seed_omega, kmax=kmax)
-    dt = time.perf_counter() - t0
-    info = threadpoolctl.threadpool_info()
-    cores = max([d.get("num_threads", 1) for d in info if d.get("user_api") == "blas"] or [1])
-    m, n = A_host.shape
-    fl = nominal_flops(m, n, res.k, P)
-    return {"value": fl / dt / 1e9, "unit": "GFLOP/s", "cores": int(cores), "kind": "oracle",
-            "seconds": dt, "k": res.k,
-            "sample": f"first {res.blocks} blocks (k={res.k}) of the same {m}x{n} factorisation, "
-                      f"b={wl.b}, P={P}, float64 numpy/OpenBLAS on the host; GFLOP/s by the "
-                      f"same nominal count as the GPU value"}
-
-
 def skip_reorth_experiment():
-    """Section 6.4 / Figure 8 on the GPU: Matrix 1 (800 x 600, singular values
+    """Section 6.3 / Figure 8 on the GPU: Matrix 1 (800 x 600, singular values
     from 0.59 down to 1e-18), error of the single pass (randQB_p, l columns)
     and of the blocked scheme (b = 10), with and without orthonormalisation
     between applications of A and A^T.  Prints one JSON line."""
@@ -519,21 +507,134 @@ def precision_experiment():
                       "rows": rows, "data": "synthetic"}), flush=True)
 
 
+def host_cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def blas_threads():
+    import threadpoolctl
+    info = threadpoolctl.threadpool_info()
+    return max([d.get("num_threads", 1) for d in info if d.get("user_api") == "blas"] or [1])
+
+
+def small_workload_timing(qbmi, torch, no_cpu):
+    """The 2000 x 1000 exp(-j/40) workload (b = 50, P = 0, eps = 1e-6 ||A||):
+    median of 3 GPU runs (HIP events around each call), the oracle's median
+    of 3 on all host threads and one run on one thread, same input bytes;
+    k and Q B compared between the two."""
+    import numpy as np
+    import synth
+
+    wl = synth.workload("exp40_2000x1000")
+    Ah = synth.workload_matrix(wl.name)
+    A = qbmi.colmajor(torch.from_numpy(np.ascontiguousarray(Ah)).cuda())
+    nA = float(np.linalg.norm(Ah))
+    eps = wl.eps_rel * nA
+    r = min(wl.m, wl.n)
+    Q = torch.empty((r, wl.m), dtype=torch.float64, device="cuda").t()
+    B = torch.empty((wl.n, r), dtype=torch.float64, device="cuda").t()
+    ws = torch.empty(qbmi.workspace_bytes(wl.m, wl.n, wl.b, r) + 512, dtype=torch.uint8,
+                     device="cuda")
+    stream = torch.cuda.current_stream()
+    gpu_ms = []
+    res = None
+    for i in range(4):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        res = qbmi.qb_factor(A, eps, wl.b, 0, wl.seed_omega, workspace=ws, Q=Q, B=B)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        if i > 0:                         # the first call is a warm-up
+            gpu_ms.append(e0.elapsed_time(e1))
+    gpu_ms.sort()
+    out = {"workload": wl.name, "m": wl.m, "n": wl.n, "b": wl.b, "power_iters": 0,
+           "eps_rel": wl.eps_rel, "k": res.k, "stop": res.stop_reason,
+           "gpu_s_median3": gpu_ms[1] / 1e3, "gpu_s_runs": [v / 1e3 for v in gpu_ms],
+           "gpu_gflops": nominal_flops(wl.m, wl.n, res.k, 0) / (gpu_ms[1] * 1e-3) / 1e9}
+    if not no_cpu:
+        import threadpoolctl
+        from oracle import randqb_pb
+        times = []
+        o = None
+        for _ in range(3):
+            t0 = time.perf_counter()
+            o = randqb_pb(Ah, eps, wl.b, 0, wl.seed_omega)
+            times.append(time.perf_counter() - t0)
+        times.sort()
+        with threadpoolctl.threadpool_limits(limits=1, user_api="blas"):
+            t0 = time.perf_counter()
+            randqb_pb(Ah, eps, wl.b, 0, wl.seed_omega)
+            one = time.perf_counter() - t0
+        d = float(np.linalg.norm(res.Q.cpu().numpy() @ res.B.cpu().numpy() - o.Q @ o.B)) / nA
+        out.update({"oracle_k": o.k, "qb_rel_diff_vs_oracle": d,
+                    "oracle_s_median3": times[1], "oracle_threads": int(blas_threads()),
+                    "oracle_s_one_thread": one, "host_cpu": host_cpu_model()})
+    log(f"[bench] {wl.name}: k={res.k} GPU {gpu_ms[1]:.2f} ms (median of 3)"
+        + ("" if no_cpu else f", oracle {out['oracle_s_median3']:.2f} s "
+                             f"({out['oracle_threads']} threads), {out['oracle_s_one_thread']:.2f} s "
+                             f"(1 thread), k {out['oracle_k']}, QB diff {out['qb_rel_diff_vs_oracle']:.1e}"))
+    del A, Q, B, ws
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline_parity(qbmi, torch, A, eps, wl, P, blocks, sample="f64"):
+    """The oracle on the first `blocks` blocks of the same factorisation
+    (timed on all host threads), and the GPU's first blocks compared with
+    it element by element: the oracle's Q B moved to the GPU and subtracted
+    from the GPU's own Q B for the same kmax."""
+    import numpy as np
+    from oracle import randqb_pb
+
+    m, n = wl.m, wl.n
+    kmax = min(blocks * wl.b, min(m, n))
+    A_host = A.cpu().numpy()
+    t0 = time.perf_counter()
+    o = randqb_pb(A_host, eps, wl.b, P, wl.seed_omega, kmax=kmax)
+    dt = time.perf_counter() - t0
+    del A_host
+    g = qbmi.qb_factor(A, eps, wl.b, P, wl.seed_omega, kmax=kmax, sample=sample)
+    Qo = torch.from_numpy(np.ascontiguousarray(o.Q)).cuda()
+    Bo = torch.from_numpy(np.ascontiguousarray(o.B)).cuda()
+    nA = float(torch.linalg.norm(A))
+    diff = float(torch.linalg.norm(g.Q @ g.B - Qo @ Bo)) / nA
+    del Qo, Bo, g
+    torch.cuda.empty_cache()
+    fl = nominal_flops(m, n, o.k, P)
+    return {"value": fl / dt / 1e9, "unit": "GFLOP/s", "cores": int(blas_threads()),
+            "kind": "oracle", "seconds": dt, "k": o.k, "host_cpu": host_cpu_model(),
+            "qb_rel_diff_vs_gpu": diff,
+            "sample": f"first {o.blocks} blocks (k={o.k}) of the same {m}x{n} factorisation, "
+                      f"b={wl.b}, P={P}, float64 numpy/OpenBLAS on the host; GFLOP/s by the "
+                      f"same nominal count as the GPU value; the GPU's first {o.blocks} blocks "
+                      f"differ from it by qb_rel_diff_vs_gpu relative to ||A||_F"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="pow2_10000x10000")
-    ap.add_argument("--power-iters", type=int, default=1)
+    ap.add_argument("--workload", default="inv1_20000x16000")
+    ap.add_argument("--power-iters", type=int, default=0)
     ap.add_argument("--sample", default="f64", choices=["f64", "f32", "bf16x3"])
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true",
                     help="batched experiment: keep the default tile table (no tuning pass)")
-    ap.add_argument("--cpu-blocks", type=int, default=16)
+    ap.add_argument("--cpu-blocks", type=int, default=3)
+    ap.add_argument("--variant-steps", type=int, default=2,
+                    help="timed steps per variant (at most --steps)")
     ap.add_argument("--experiment", default=None, choices=["skip-reorth", "post", "batched", "adjoint", "precision"],
-                    help="run the Section 6.4 comparison instead of the benchmark")
+                    help="run one of the side experiments instead of the benchmark")
     ap.add_argument("--matrix", default="workload", choices=["workload", "gaussian"],
                     help="gaussian: i.i.d. N(0, 1/m) entries of the workload's shape instead of "
                          "the prescribed spectrum (no QR in the process; used for hardware-counter "
@@ -564,30 +665,38 @@ def main():
     import synth
 
     lib = qbmi.load()
-    wl = synth.workload(args.workload)
+
+    def make_matrix(name):
+        w = synth.workload(name)
+        if args.matrix == "gaussian":
+            log(f"[bench] generating a Gaussian {w.m}x{w.n} matrix on the GPU")
+            gen = torch.Generator(device="cuda")
+            gen.manual_seed(w.seed_u)
+            X = torch.randn((w.n, w.m), generator=gen, dtype=torch.float64, device="cuda").t()
+            X.mul_(1.0 / math.sqrt(w.m))
+        else:
+            log(f"[bench] generating {w.name} on the GPU")
+            X = synth.workload_matrix_gpu(w.name)
+        torch.cuda.synchronize()
+        return w, X
+
+    def buffers(w):
+        r = min(w.m, w.n)
+        Qb = torch.empty((r, w.m), dtype=torch.float64, device="cuda").t()
+        Bb = torch.empty((w.n, r), dtype=torch.float64, device="cuda").t()
+        need = qbmi.workspace_bytes(w.m, w.n, w.b, r)
+        wsb = torch.empty(need + 512, dtype=torch.uint8, device="cuda")
+        return Qb, Bb, wsb
+
+    wl, A = make_matrix(args.workload)
     m, n = wl.m, wl.n
-    r = min(m, n)
-    if args.matrix == "gaussian":
-        log(f"[bench] generating a Gaussian {m}x{n} matrix on the GPU")
-        gen = torch.Generator(device="cuda")
-        gen.manual_seed(wl.seed_u)
-        A = torch.randn((n, m), generator=gen, dtype=torch.float64, device="cuda").t()
-        A.mul_(1.0 / math.sqrt(m))
-    else:
-        log(f"[bench] generating {wl.name} on the GPU")
-        A = synth.workload_matrix_gpu(wl.name)
-    torch.cuda.synchronize()
     nA2, bad = qbmi.frob2(A)
     assert not bad
     eps = wl.eps_rel * math.sqrt(nA2)
-    Q = torch.empty((r, m), dtype=torch.float64, device="cuda").t()
-    B = torch.empty((n, r), dtype=torch.float64, device="cuda").t()
-    need = qbmi.workspace_bytes(m, n, wl.b, r)
-    ws = torch.empty(need + 512, dtype=torch.uint8, device="cuda")
-    bufs = (Q, B, ws)
+    bufs = buffers(wl)
 
     P = args.power_iters
-    log(f"[bench] timing P={P} sample={args.sample}: warmup {args.warmup}, steps {args.steps}")
+    log(f"[bench] timing {wl.name} P={P} sample={args.sample}: warmup {args.warmup}, steps {args.steps}")
     res, ms, prof = run_variant(qbmi, lib, torch, A, eps, wl, P, args.sample, args.steps,
                                 args.warmup, bufs, profile=True)
     k = res.k
@@ -596,7 +705,7 @@ def main():
     rel = residual_rel(torch, A, res)
     log(f"[bench] k={k} stop={res.stop_reason} {ms:.1f} ms/step {gflops:.0f} GFLOP/s rel_err={rel:.3e}")
 
-    # dominant kernel by total time inside the timed steps
+    # dominant kernel by total time inside the profiled step
     dom_name, dom = max(prof.items(), key=lambda kv: kv[1]["ms"])
     dom_tflops = dom["flops"] / (dom["ms"] * 1e-3) / 1e12 if dom["ms"] > 0 else 0.0
     traffic, traffic_src = committed_traffic(dom_name)
@@ -614,34 +723,66 @@ def main():
                       "gbs": (v["bytes"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] > 0 else None}
                for name, v in prof.items()}
 
+    vsteps = max(1, min(args.steps, args.variant_steps))
     variants = []
-    if not args.no_variants:
-        todo = [(0, "f64", True), (P, "f32", True), (P, "bf16x3", True), (0, "f32", True),
-                (0, "bf16x3", True)]
-        if P > 0:
-            todo.append((P, "f64", False))   # no orth between A and A^T (Section 5.4)
-        for (vp, vs, vo) in todo:
-            if (vp, vs, vo) == (P, args.sample, True):
-                continue
-            try:
-                vres, vms, _ = run_variant(qbmi, lib, torch, A, eps, wl, vp, vs, args.steps,
-                                           args.warmup, bufs, profile=False, power_orth=vo)
-            except qbmi.QBError as e:
-                variants.append({"power_iters": vp, "sample": vs, "power_orth": vo,
-                                 "error": str(e)})
-                continue
-            vfl = nominal_flops(m, n, vres.k, vp)
-            variants.append({"power_iters": vp, "sample": vs, "power_orth": vo, "k": vres.k,
-                             "solve_s": vms / 1e3, "gflops": vfl / (vms * 1e-3) / 1e9,
-                             "rel_err": residual_rel(torch, A, vres), "stop": vres.stop_reason})
-            log(f"[bench] variant P={vp} {vs}{'' if vo else ' no-orth'}: k={vres.k} {vms:.1f} ms")
 
+    def variant(w, X, e, vp, vs, vbufs, vo=True, ref=None):
+        try:
+            vres, vms, _ = run_variant(qbmi, lib, torch, X, e, w, vp, vs, vsteps, 1, vbufs,
+                                       profile=False, power_orth=vo)
+        except qbmi.QBError as ex:
+            variants.append({"workload": w.name, "power_iters": vp, "sample": vs,
+                             "power_orth": vo, "error": str(ex)})
+            return None
+        vfl = nominal_flops(w.m, w.n, vres.k, vp)
+        row = {"workload": w.name, "power_iters": vp, "sample": vs, "power_orth": vo,
+               "k": vres.k, "solve_s": vms / 1e3, "gflops": vfl / (vms * 1e-3) / 1e9,
+               "rel_err": residual_rel(torch, X, vres), "stop": vres.stop_reason,
+               "status": vres.status}
+        if ref is not None:
+            row["qb_rel_diff_vs_f64"] = float(torch.linalg.norm(vres.Q @ vres.B - ref)) / \
+                float(torch.linalg.norm(X))
+        variants.append(row)
+        log(f"[bench] variant {w.name} P={vp} {vs}{'' if vo else ' no-orth'}: k={vres.k} "
+            f"{vms:.1f} ms rel_err={row['rel_err']:.2e} {vres.stop_reason}")
+        return vres
+
+    if not args.no_variants:
+        # mixed-precision sampling on the same matrix, read against the float64 run
+        ref = (res.Q @ res.B) if args.sample == "f64" else None
+        for vs in ("f32", "bf16x3"):
+            if vs != args.sample:
+                variant(wl, A, eps, P, vs, bufs, ref=ref)
+        del ref
+        torch.cuda.empty_cache()
     cpu = None
     if not args.no_cpu:
         log(f"[bench] timing the CPU oracle on the first {args.cpu_blocks} blocks")
-        A_host = A.cpu().numpy()
-        cpu = cpu_baseline(A_host, eps, wl, P, args.cpu_blocks)
-        log(f"[bench] cpu oracle: {cpu['seconds']:.1f} s, {cpu['value']:.1f} GFLOP/s on {cpu['cores']} threads")
+        cpu = cpu_baseline_parity(qbmi, torch, A, eps, wl, P, args.cpu_blocks, args.sample)
+        log(f"[bench] cpu oracle: {cpu['seconds']:.1f} s, {cpu['value']:.1f} GFLOP/s on "
+            f"{cpu['cores']} threads; GPU first blocks differ by {cpu['qb_rel_diff_vs_gpu']:.1e}")
+    if not args.no_variants:
+        # the other workloads of the sweep: the gap matrix at the same size,
+        # the square 10^4 workload at P = 0 and 1
+        for name, ps in (("gap_20000x16000", (0,)), ("pow2_10000x10000", (0, 1))):
+            if name == wl.name:
+                continue
+            del bufs
+            torch.cuda.empty_cache()
+            w2, X2 = make_matrix(name)
+            e2 = w2.eps_rel * float(torch.linalg.norm(X2))
+            bufs = buffers(w2)
+            for vp in ps:
+                r64 = variant(w2, X2, e2, vp, "f64", bufs)
+                ref = (r64.Q @ r64.B) if r64 is not None else None
+                del r64
+                for vs in ("f32", "bf16x3"):
+                    variant(w2, X2, e2, vp, vs, bufs, ref=ref)
+                del ref
+                torch.cuda.empty_cache()
+            del X2
+            torch.cuda.empty_cache()
+    small = small_workload_timing(qbmi, torch, args.no_cpu) if not args.no_variants else None
 
     line = {
         "metric": METRIC, "value": gflops, "unit": "GFLOP/s", "n_gpus": 1,
@@ -657,6 +798,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "variants": variants,
+        "small_workload": small,
         "kernels": kernels,
     }
     print(json.dumps(line), flush=True)

@@ -7,7 +7,7 @@
  * randQB_pb (Figure 6, Section 5.2).  Given an m x n matrix A and a
  * tolerance eps, it returns Q (m x k, orthonormal columns), B (k x n) and
  * the rank k, built b columns at a time, such that ||A - Q B||_F <= eps
- * (Section 1.1, problem statement; Section 4.3, adaptive rank).
+ * (Section 1.1, problem statement; Section 4.2, adaptive rank).
  *
  * Conventions for every entry point
  *   - matrices are column-major (LAPACK order); an m x n matrix X with
@@ -84,6 +84,15 @@ extern "C" {
  * (Figure 3) and randQB_p (Figure 5) with l = b.  Returns QB_KMAX (stop
  * reason QB_STOP_KMAX) unless the tolerance was met. */
 #define QB_SINGLE_BLOCK   (1u << 9)
+/* Queue no work past the stop decision.  By default qb_factor, while the
+ * host reads block i's stop quantities, already queues the sketch and the
+ * sampling product of block i + 1 on `stream` (assuming no column was
+ * dropped); when the run stops there, that work is left queued and writes
+ * the workspace (sketch, sample and split-K partial areas; never A, Q or B)
+ * after qb_factor has returned.  Work ordered after `stream` is unaffected;
+ * a caller that hands the workspace to another stream without ordering it
+ * after `stream` must pass this flag. */
+#define QB_NO_SPECULATE   (1u << 10)
 
 /* Per-call report.  The trace arrays are optional HOST arrays owned by the
  * caller (set the pointers to NULL or trace_cap to 0 to skip).  Entry i
@@ -103,8 +112,9 @@ typedef struct qb_info {
   double* trace_D;        /* D_i per block                                 */
 } qb_info;
 
-/* Bytes of device workspace qb_factor needs for these sizes.
- * kmax <= 0 means min(m, n).  Returns 0 for invalid sizes. */
+/* Bytes of device workspace qb_factor needs for these sizes.  kmax < 0
+ * means min(m, n); kmax = 0 is a capacity of zero columns.  Returns 0 for
+ * sizes qb_factor rejects (see qb_factor: m, n, b, kmax). */
 size_t qb_workspace_bytes(int64_t m, int64_t n, int32_t b, int64_t kmax, uint32_t flags);
 
 /*
@@ -113,6 +123,8 @@ size_t qb_workspace_bytes(int64_t m, int64_t n, int32_t b, int64_t kmax, uint32_
  *
  *  A            m x n input, lda >= m.  Read-only unless QB_OVERWRITE_A, in
  *               which case it holds the final residual A - Q B on return.
+ *               1 <= m < 2^24 - 1, 1 <= n <= 65535 * 64 (the limits of the
+ *               kernels' 32-bit tile offsets and of the downdate grid).
  *  eps          Frobenius tolerance, finite and >= 0.
  *  b            block size >= 1.  Each block adds at most b columns.
  *  power_iters  P >= 0 power iterations per block (Figure 6 steps (4)-(7)).
@@ -122,15 +134,22 @@ size_t qb_workspace_bytes(int64_t m, int64_t n, int32_t b, int64_t kmax, uint32_
  *               sketch columns [k, k + w) whatever b is.
  *  Q, ldq       output, m x kmax, ldq >= m.  Columns [0, k) are written.
  *  B, ldb       output, kmax x n, ldb >= kmax.  Rows [0, k) are written.
+ *               lda, ldq and ldb are below 2^24; 1 <= b <= 256.
  *  kmax         capacity (max rank), 0 <= kmax <= min(m, n); kmax < 0 means
  *               min(m, n) (then Q and B must hold min(m, n) columns/rows).
  *  k            HOST out: the rank.
  *  info         HOST in/out, may be NULL.
  *  workspace    device buffer of at least qb_workspace_bytes(...) bytes,
  *               256-byte aligned.
- *  flags        QB_OVERWRITE_A | one QB_SAMPLE_* value.
+ *  flags        QB_OVERWRITE_A, one QB_SAMPLE_* and one QB_BGEMM_* value,
+ *               QB_POWER_NO_ORTH, QB_SINGLE_BLOCK, QB_NO_SPECULATE.
  *
- * Synchronises `stream` once per block (to read the stop quantities).
+ * Synchronises `stream` once per block (to read the stop quantities).  On
+ * return the stream may still hold the speculative sketch and sample of
+ * one further block, which write only the workspace (QB_NO_SPECULATE).
+ * Errors: QB_EINVAL (arguments, sizes), QB_EWORKSPACE (NULL or too small),
+ * QB_ENODEVICE (no current device, or not a gfx950), QB_ENONFINITE,
+ * QB_EHIP.
  */
 int qb_factor(const double* A, int64_t m, int64_t n, int64_t lda,
               double eps, int32_t b, int32_t power_iters, uint64_t seed,
@@ -141,7 +160,9 @@ int qb_factor(const double* A, int64_t m, int64_t n, int64_t lda,
 /* Human-readable name of a status code (static string). */
 const char* qb_status_string(int status);
 
-/* ---- component entry points (same kernels the factorisation uses) ------ */
+/* ---- component entry points (same kernels the factorisation uses) ------
+ * Leading dimensions are below 2^24.  Like qb_factor they return
+ * QB_ENODEVICE when the current device is not a gfx950. */
 
 /* Columns [col0, col0 + w) of the Gaussian sketch (Figure 4 step (2);
  * Section 4.1 eq. (OmegaBlock)): out is n x w, ld >= n, device. */
@@ -294,7 +315,7 @@ int qb_batched_get_tile(int32_t role, int32_t width_class);
 /* ---- adjoint of the fixed-sketch map A -> (Q, B) ----------------------------
  * With the sketch (seed), the block width b, the number of blocks s and the
  * number of power iterations P fixed, the blocked scheme (Figure 4, with the
- * power iterations of Figure 6 and the re-projection of Section 4.4) maps A
+ * power iterations of Figure 6 and the re-projection of Section 4.3) maps A
  * to Q = [Q_1 .. Q_s] (m x s b) and B = [B_1; ..; B_s] (s b x n) smoothly
  * wherever every orthonormalisation sees a full-column-rank matrix; that
  * map is qb_factor(A, eps = 0, b, P, seed) with kmax = s b when no column

@@ -12,7 +12,7 @@ with positive diagonal, Section 2.4):
     for i = 1 .. s:
         Q_i = orth(R Omega_i)
         P times:  Z = orth(R^T Q_i);  Q_i = orth(R Z)          (Figure 6)
-        i > 1:    Q_i = orth(Q_i - Qbar Qbar^T Q_i)           (Section 4.4)
+        i > 1:    Q_i = orth(Q_i - Qbar Qbar^T Q_i)           (Section 4.3)
         B_i = Q_i^T R;  R = R - Q_i B_i                       (Figure 4)
     Q = [Q_1 .. Q_s],  B = [B_1; .. ; B_s]
 

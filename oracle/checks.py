@@ -3,13 +3,21 @@
   eckart_young(s, k)     optimal rank-k Frobenius error (eq. minerrors,
                          Section 2.2): sqrt(sum_{j>k} s_j^2)
   expectation_bound(s, k, p)  (1 + k/(p-1)) * EY(k) for a sketch with k + p
-                         columns (Section 3.2, from Halko-Martinsson-Tropp
-                         Thm. 10.5)
+                         columns (Section 3.2, quoting Halko-Martinsson-Tropp
+                         Thm. 10.5; the paper's factor has no square root,
+                         a weaker but still valid bound, and is taken as
+                         printed)
   eps_rank(s, eps)       smallest k with EY(k) <= eps
-  orth_defect(Q)         ||Q^T Q - I||_F  (Proposition 3.1(a))
+  orth_defect(Q)         ||Q^T Q - I||_F  (Proposition 4.1(a))
   unblocked_qb(A, Om)    Figure 3 (randQB): Q = orth(A Omega), B = Q^T A via
                          Householder QR (numpy), for the blocked-vs-unblocked
                          identity of Section 4.1
+
+Parity pinned by tests/test_oracle_checks.py: EY(k) against the error of
+the rank-k truncation rebuilt from numpy's SVD factors for every k, and no
+orthonormal rank-k basis doing better; eps_rank as the smallest such k
+(ties included); expectation_bound at hand-computed values and above the
+Monte-Carlo mean error of randQB; planted off-by-one slips fail them.
 """
 from __future__ import annotations
 

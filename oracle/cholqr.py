@@ -8,7 +8,7 @@ orthonormality in proportion to cond(X)^2 * u; the second pass, applied to
 the output of the first, restores it to rounding level whenever
 cond(X) < u^{-1/2}.
 
-The paper assumes every sample block has full column rank (Proposition 3.1
+The paper assumes every sample block has full column rank (Proposition 4.1
 assumes rank(A) >= s b).  For blocks that are numerically rank deficient the
 reading taken is a Cholesky factorisation with column dropping, in natural
 column order: column c is kept when its pivot, the part of G_cc left after

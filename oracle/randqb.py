@@ -1,15 +1,15 @@
 """Blocked adaptive randomized QB with a Frobenius tolerance: randQB_b
-(Figure 4, Section 4.2-4.3) and its power-iteration form randQB_pb
+(Figure 4, Sections 4.1-4.3) and its power-iteration form randQB_pb
 (Figure 6, Section 5.2).  Plain float64 CPU reference; test infrastructure.
 
 For i = 1, 2, ... (A is overwritten by the residual A^(i), eq. def3):
   (2)  Omega_i = columns [k, k+w) of the Gaussian sketch     (gaussian.py)
   (3)  Q_i = orth(A Omega_i)                                   (cholqr.py)
   (4-7) P times: Q_i = orth(A^T Q_i); Q_i = orth(A Q_i)         (Fig. 6)
-  (3') Q_i = orth(Q_i - Qbar Qbar^T Q_i)   re-projection, Section 4.4
+  (3') Q_i = orth(Q_i - Qbar Qbar^T Q_i)   re-projection, Section 4.3
   (4)  B_i = Q_i^T A
   (5)  A = A - Q_i B_i
-  (6)  stop once the residual norm is at most eps (Section 4.3)
+  (6)  stop once the residual norm is at most eps (Section 4.2)
 Output Q = [Q_1 ... Q_s], B = [B_1; ...; B_s].
 
 Readings of points the paper leaves open (each also listed in the design
@@ -20,21 +20,21 @@ notes of the repository):
     w' <= w columns; when w' = 0 nothing is added and the run stops
     ("exhausted");
   * stopping quantity: the paper tests the norm of the updated A directly
-    (Section 4.3 and step (6)).  Proposition 3.1 (a),(b) with Pythagoras
+    (Section 4.2 and step (6)).  Proposition 4.1 (a),(b) with Pythagoras
     gives ||A^(i)||^2 = ||A||^2 - sum_j ||B_j||^2, which is tracked as E_i.
     E_i cancels catastrophically near eps^2 when eps is close to
     sqrt(u)||A||, so the rule is hybrid: stop when E_i <= eps^2 - delta;
     continue when E_i > eps^2 + delta; otherwise stop iff the direct
     D_i = ||A^(i)||^2 <= eps^2, with delta = 1e-13 ||A||^2;
-  * "at most eps" (non-strict), as in Algorithm 1 and Section 4.3; the same
+  * "at most eps" (non-strict), as in Algorithm 1 and Section 4.2; the same
     test is applied before the first block (k = 0 when ||A|| <= eps);
   * when the residual has fallen to the rounding level of the downdate,
     D_i <= (2^-46 ||A||)^2, further blocks would only sample rounding noise
     and the run stops ("exhausted").
 
 Parity pinned by tests/test_oracle_randqb.py: orthonormality of Qbar
-(Prop. 3.1(a)), residual identity A^(i) = A - Qbar Bbar and Bbar = Qbar^T A
-(Prop. 3.1(b)), range identity (Prop. 3.1(c)), independence of the projector
+(Proposition 4.1(a)), residual identity A^(i) = A - Qbar Bbar and Bbar = Qbar^T A
+(Proposition 4.1(b)), range identity (Proposition 4.1(c)), independence of the projector
 from the block size for a fixed sketch (Section 4.1), Eckart-Young lower
 bound and the expectation bound (Section 3.2), deterministic residuals of
 sigma * orthonormal inputs, exact-rank inputs, brute force against LAPACK on
@@ -104,7 +104,7 @@ def randqb_pb(A: np.ndarray, eps: float, b: int, power_iters: int = 0, seed: int
 
     omega_fn(n, col0, w) -> n x w, if given, replaces the Philox sketch (used
     by tests that need a prescribed Omega).  reorth=False skips step (3')
-    (Section 4.4).  power_orth=False skips the orthonormalisation between
+    (Section 4.3).  power_orth=False skips the orthonormalisation between
     applications of A and A^T (the variant examined in Sections 5.4 and
     6.4): Y = (A A^T)^P A Omega_i, then Q_i = orth(Y).  max_blocks=1 with
     b = l is the unblocked scheme: randQB (Figure 3) for P = 0 and randQB_p

@@ -41,6 +41,7 @@ QB_SAMPLE = {"f64": 0 << 4, "f32": 1 << 4, "bf16x3": 2 << 4}
 QB_BGEMM = {"f64": 0 << 6, "f32": 1 << 6, "bf16x3": 2 << 6}
 QB_POWER_NO_ORTH = 1 << 8
 QB_SINGLE_BLOCK = 1 << 9
+QB_NO_SPECULATE = 1 << 10
 
 
 class QBInfo(ctypes.Structure):

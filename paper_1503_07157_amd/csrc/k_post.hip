@@ -472,6 +472,7 @@ int qb_svd(const double* Q, int64_t m, int64_t k, int64_t ldq, const double* B, 
   if (ldq < m || ldb < k || ldu < m || ldv < n) return QB_EINVAL;
   if (workspace == nullptr) return QB_EWORKSPACE;
   if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return QB_EINVAL;
+  if (const int dv = device_ready()) return dv;
   SvdWork w;
   Arena arena{static_cast<char*>(workspace), ws_bytes, 0};
   if (svd_carve(arena, m, n, k, &w) != kOk) return QB_EWORKSPACE;
@@ -528,6 +529,7 @@ int qb_pivoted_qr(const double* Q, int64_t m, int64_t k, int64_t ldq, const doub
   if (ldq < m || ldb < k || ldqh < m || ldr < k) return QB_EINVAL;
   if (workspace == nullptr) return QB_EWORKSPACE;
   if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return QB_EINVAL;
+  if (const int dv = device_ready()) return dv;
   QrWork w;
   Arena arena{static_cast<char*>(workspace), ws_bytes, 0};
   if (qr_carve(arena, m, n, k, &w) != kOk) return QB_EWORKSPACE;

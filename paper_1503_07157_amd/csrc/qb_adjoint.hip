@@ -9,7 +9,7 @@
 //   R_0 = A;  for i = 1 .. s:
 //     Q^0 = orth(R_{i-1} Omega_i)
 //     p = 1 .. P:  Z^p = orth(R_{i-1}^T Q^{p-1});  Q^p = orth(R_{i-1} Z^p)
-//     i > 1:  C = Qbar^T Q^P,  Q_i = orth(Q^P - Qbar C)      (Section 4.4)
+//     i > 1:  C = Qbar^T Q^P,  Q_i = orth(Q^P - Qbar C)      (Section 4.3)
 //     i = 1:  Q_i = Q^P
 //     B_i = Q_i^T R_{i-1};  R_i = R_{i-1} - Q_i B_i
 //
@@ -256,6 +256,7 @@ int qb_adjoint(const double* A, int64_t m, int64_t n, int64_t lda, int32_t b, in
   if (dB && (lddb < ktot || lddb >= (int64_t(1) << 24))) return QB_EINVAL;
   if (!workspace) return QB_EWORKSPACE;
   if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return QB_EINVAL;
+  if (const int dv = device_ready()) return dv;
   Arena arena{static_cast<char*>(workspace), ws_bytes, 0};
   AdjWork W;
   if (carve_adj(arena, d, &W) != kOk) return QB_EWORKSPACE;

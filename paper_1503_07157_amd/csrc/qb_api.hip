@@ -2,7 +2,7 @@
 // (randQB_b, Figure 4; randQB_pb, Figure 6).  All device work is issued on
 // the caller's stream from carved caller workspace; the only host
 // synchronisation is one small device-to-host read per block for the
-// stopping rule (Section 4.3), plus one at the start for ||A||_F.
+// stopping rule (Section 4.2), plus one at the start for ||A||_F.
 //
 // Per block (A is the residual, overwritten as in eq. (def3)):
 //   Omega_i = sketch columns [k, k+w)                          Fig. 4 (2)
@@ -12,10 +12,11 @@
 //   B_i = Q_i^T A;  A = A - Q_i B_i  (+ ||A||_F^2)              Fig. 4 (4),(5)
 //   stop when the residual norm is at most eps                  Fig. 4 (6)
 // The stopping quantity is tracked as E_i = ||A||^2 - sum_j ||B_j||^2
-// (Proposition 3.1 (a),(b) and Pythagoras) and, inside a band of
+// (Proposition 4.1 (a),(b) and Pythagoras) and, inside a band of
 // half-width 1e-13 ||A||^2 around eps^2 where E_i cannot resolve the
 // threshold, decided by the directly computed D_i = ||A^(i)||_F^2.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 
@@ -119,9 +120,12 @@ int carve(Arena& a, int64_t m, int64_t n, int b, int64_t kcap, int power_iters, 
   return rc;
 }
 
+// Sizes every kernel of the factorisation can launch: m x b and n x b
+// panels (leading dimensions even_up(m) and n) below kMaxLd, and the
+// downdate's column tiles within one grid dimension.
 bool valid_sizes(int64_t m, int64_t n, int32_t b) {
-  return m >= 1 && n >= 1 && b >= 1 && b <= kMaxPanel && m < (int64_t(1) << 31) &&
-         n < (int64_t(1) << 31);
+  return m >= 1 && n >= 1 && b >= 1 && b <= kMaxPanel && even_up(m) < kMaxLd && n < kMaxLd &&
+         n <= kMaxDowndateCols;
 }
 
 // Per-thread pinned host mailbox for the per-block scalars and an event that
@@ -172,6 +176,28 @@ int project_t(uint32_t prec, const double* Qm, int64_t ldq, const double* X, int
 }
 
 }  // namespace
+
+int device_ready() {
+  constexpr int kMaxDevices = 64;
+  static std::atomic<signed char> known[kMaxDevices];
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) {
+    (void)hipGetLastError();
+    return kENoDevice;
+  }
+  signed char v = dev < kMaxDevices ? known[dev].load(std::memory_order_relaxed) : 0;
+  if (v == 0) {
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, dev) != hipSuccess) {
+      (void)hipGetLastError();
+      return kENoDevice;
+    }
+    v = std::strncmp(p.gcnArchName, "gfx950", 6) == 0 ? 1 : -1;
+    if (dev < kMaxDevices) known[dev].store(v, std::memory_order_relaxed);
+  }
+  return v > 0 ? kOk : kENoDevice;
+}
+
 }  // namespace qb
 
 using namespace qb;
@@ -194,7 +220,7 @@ const char* qb_status_string(int status) {
 }
 
 size_t qb_workspace_bytes(int64_t m, int64_t n, int32_t b, int64_t kmax, uint32_t flags) {
-  if (!valid_sizes(m, n, b)) return 0;
+  if (!valid_sizes(m, n, b) || kmax > std::min(m, n)) return 0;
   const int64_t r = std::min(m, n);
   const int64_t kcap = (kmax < 0) ? r : std::min(kmax, r);
   Arena a{nullptr, 0, 0};
@@ -222,8 +248,10 @@ int qb_factor(const double* A, int64_t m, int64_t n, int64_t lda, double eps, in
   if (kmax > r) return QB_EINVAL;
   const int64_t kcap = (kmax < 0) ? r : kmax;
   if (lda < m || ldq < m || ldb < std::max<int64_t>(kcap, 1)) return QB_EINVAL;
+  if (lda >= kMaxLd || ldq >= kMaxLd || ldb >= kMaxLd) return QB_EINVAL;
   if (workspace == nullptr) return QB_EWORKSPACE;
   if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return QB_EINVAL;
+  if (const int dv = device_ready()) return dv;
   const int bw = static_cast<int>(std::min<int64_t>(b, r));
 
   Work wk;
@@ -363,7 +391,7 @@ int qb_factor(const double* A, int64_t m, int64_t n, int64_t lda, double eps, in
     {
       const int64_t kn = k + w;
       const int wn = static_cast<int>(std::min<int64_t>(bw, kcap - kn));
-      if (wn > 0 && !single_block) {
+      if (wn > 0 && !single_block && !(flags & QB_NO_SPECULATE)) {
         if (launch_sketch(seed, n, kn, wn, wk.omega, n, st)) return QB_EHIP;
         if (sample(prec, R, ldr, wk.omega, n, wk.Y, ldm, m, wn, n, wk.part, st)) return QB_EHIP;
         spec_k = kn;
@@ -401,6 +429,7 @@ int qb_sketch(uint64_t seed, int64_t n, int64_t col0, int32_t w, double* out, in
               void* stream) {
   if (!out || n < 1 || w < 1 || col0 < 0 || ld < n || col0 + w > (int64_t(1) << 32))
     return QB_EINVAL;
+  if (const int dv = device_ready()) return dv;
   return launch_sketch(seed, n, col0, w, out, ld, static_cast<hipStream_t>(stream)) ? QB_EHIP
                                                                                     : QB_OK;
 }
@@ -414,8 +443,10 @@ int qb_orth(const double* X, int64_t m, int32_t w, int64_t ldx, double* Q, int64
             int32_t* kept, void* workspace, size_t ws_bytes, void* stream) {
   if (kept) *kept = 0;
   if (!X || !Q || m < 1 || w < 1 || w > kMaxPanel || ldx < m || ldq < m) return QB_EINVAL;
+  if (even_up(m) >= kMaxLd || ldx >= kMaxLd || ldq >= kMaxLd) return QB_EINVAL;
   if (Q == X && ldq != ldx) return QB_EINVAL;
   if (!workspace) return QB_EWORKSPACE;
+  if (const int dv = device_ready()) return dv;
   Arena a{static_cast<char*>(workspace), ws_bytes, 0};
   OrthWork ow;
   if (orth_carve(a, m, w, &ow) != kOk) return QB_EWORKSPACE;
@@ -440,9 +471,11 @@ int qb_sample(const double* X, int64_t m, int64_t K, int64_t ldx, const double* 
               size_t ws_bytes, void* stream) {
   if (!X || !W || !Y || m < 1 || K < 1 || w < 1 || w > kMaxPanel || ldx < m || ldw < K || ldy < m)
     return QB_EINVAL;
+  if (ldx >= kMaxLd || ldw >= kMaxLd || ldy >= kMaxLd) return QB_EINVAL;
   if (precision != QB_SAMPLE_F64 && precision != QB_SAMPLE_F32 && precision != QB_SAMPLE_BF16X3)
     return QB_EINVAL;
   if (!workspace || ws_bytes < qb_gemm_workspace_bytes(m, K, w)) return QB_EWORKSPACE;
+  if (const int dv = device_ready()) return dv;
   double* part = reinterpret_cast<double*>((reinterpret_cast<uintptr_t>(workspace) + 255) & ~uintptr_t(255));
   return sample(precision, X, ldx, W, ldw, Y, ldy, m, w, K, part, static_cast<hipStream_t>(stream))
              ? QB_EHIP : QB_OK;
@@ -453,9 +486,11 @@ int qb_project(const double* Qm, int64_t K, int32_t w, int64_t ldq, const double
                size_t ws_bytes, void* stream) {
   if (!Qm || !X || !C || K < 1 || N < 1 || w < 1 || w > kMaxPanel || ldq < K || ldx < K || ldc < w)
     return QB_EINVAL;
+  if (ldq >= kMaxLd || ldx >= kMaxLd || ldc >= kMaxLd) return QB_EINVAL;
   if (precision != QB_SAMPLE_F64 && precision != QB_SAMPLE_F32 && precision != QB_SAMPLE_BF16X3)
     return QB_EINVAL;
   if (!workspace || ws_bytes < qb_gemm_workspace_bytes(N, K, w)) return QB_EWORKSPACE;
+  if (const int dv = device_ready()) return dv;
   double* part = reinterpret_cast<double*>((reinterpret_cast<uintptr_t>(workspace) + 255) & ~uintptr_t(255));
   return project_t(precision, Qm, ldq, X, ldx, C, ldc, w, N, K, false, part, nullptr, nullptr,
                    static_cast<hipStream_t>(stream)) ? QB_EHIP : QB_OK;
@@ -483,10 +518,12 @@ int qb_downdate(double* R, int64_t m, int64_t n, int64_t ldr, const double* Qm, 
                 size_t ws_bytes, void* stream) {
   if (!R || !Qm || !B || m < 1 || n < 1 || w < 1 || ldr < m || ldq < m || ldb < w)
     return QB_EINVAL;
+  if (ldq >= kMaxLd || ldb >= kMaxLd || n > kMaxDowndateCols) return QB_EINVAL;
   if (!workspace) return QB_EWORKSPACE;
   double *sq, *scal;
   int *fl, *iscal;
   if (small_scratch(workspace, ws_bytes, m, n, &sq, &fl, &scal, &iscal)) return QB_EWORKSPACE;
+  if (const int dv = device_ready()) return dv;
   hipStream_t st = static_cast<hipStream_t>(stream);
   int cnt = 0;
   if (downdate(R, ldr, Qm, ldq, B, ldb, m, n, w, sq, &cnt, st)) return QB_EHIP;
@@ -508,6 +545,7 @@ int qb_frob2(const double* X, int64_t m, int64_t n, int64_t ldx, double* out, in
   double *sq, *scal;
   int *fl, *iscal;
   if (small_scratch(workspace, ws_bytes, m, n, &sq, &fl, &scal, &iscal)) return QB_EWORKSPACE;
+  if (const int dv = device_ready()) return dv;
   hipStream_t st = static_cast<hipStream_t>(stream);
   int cnt = 0;
   if (sumsq_partials(X, ldx, m, n, sq, &cnt, fl, st)) return QB_EHIP;

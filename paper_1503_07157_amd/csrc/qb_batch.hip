@@ -358,6 +358,7 @@ int qb_factor_batched(qb_problem* probs, int32_t count, void* workspace, size_t 
     if (!problem_ok(probs[i])) return QB_EINVAL;
   if (workspace == nullptr) return QB_EWORKSPACE;
   if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return QB_EINVAL;
+  if (const int dv = device_ready()) return dv;
   Layout L;
   Arena arena{static_cast<char*>(workspace), ws_bytes, 0};
   if (carve_batch(arena, probs, count, &L) != kOk) return QB_EWORKSPACE;

@@ -42,6 +42,16 @@ constexpr int64_t kSplitMinDepth = 128;         // smallest reduction depth per 
 constexpr int64_t kPartialCapDoubles = int64_t(16) << 20;  // 128 MiB of partials at most
 constexpr int kMaxPanel = 256;   // widest block (b) supported by orth
 
+// Leading dimensions and the row counts of panels stay below 2^24: the tile
+// loads use 32-bit element offsets over up to 256 rows or columns.
+constexpr int64_t kMaxLd = int64_t(1) << 24;
+// The downdate grid puts the column tiles (64 wide) in grid.y.
+constexpr int64_t kMaxDowndateCols = int64_t(65535) * 64;
+
+// QB_ENODEVICE unless the current HIP device is a gfx950; the answer is
+// cached per device, so only the first call on a device queries it.
+int device_ready();
+
 // Workspace arena: bump allocator over a caller buffer, 256-byte aligned.
 struct Arena {
   char* base;

@@ -15,7 +15,7 @@ import torch
 
 from . import _lib
 from ._lib import (QBError, QBInfo, QBProblem, QB_BGEMM, QB_SAMPLE, QB_OVERWRITE_A, QB_POWER_NO_ORTH,
-                   QB_SINGLE_BLOCK, QB_STOP)
+                   QB_SINGLE_BLOCK, QB_NO_SPECULATE, QB_STOP)
 
 
 def _stream(device) -> int:
@@ -88,13 +88,14 @@ def qb_factor(A: torch.Tensor, eps: float, b: int, power_iters: int = 0, seed: i
               trace_cap: int = 4096, workspace: torch.Tensor | None = None,
               Q: torch.Tensor | None = None, B: torch.Tensor | None = None,
               bgemm: str = "f64", power_orth: bool = True,
-              single_block: bool = False) -> QBResult:
+              single_block: bool = False, speculate: bool = True) -> QBResult:
     """Blocked adaptive randomized QB (randQB_pb) of the column-major float64
     device matrix A to Frobenius tolerance eps.  Returns Q[:, :k], B[:k, :].
     sample / bgemm: precision of the sampling products and of B_i = Q_i^T A
     ("f64", "f32", "bf16x3").  power_orth=False skips the orthonormalisation
     between applications of A and A^T; single_block=True stops after the
-    first block (the unblocked scheme with l = b)."""
+    first block (the unblocked scheme with l = b).  speculate=False queues no
+    work past the stop decision (QB_NO_SPECULATE)."""
     lib = _lib.load()
     lda = _ld(A, "A")
     m, n = A.shape
@@ -107,7 +108,8 @@ def qb_factor(A: torch.Tensor, eps: float, b: int, power_iters: int = 0, seed: i
         B = torch.empty((n, max(kcap, 1)), dtype=torch.float64, device=dev).t()
     ldq, ldb = _ld(Q, "Q"), _ld(B, "B")
     flags = (QB_SAMPLE[sample] | QB_BGEMM[bgemm] | (QB_OVERWRITE_A if overwrite else 0)
-             | (0 if power_orth else QB_POWER_NO_ORTH) | (QB_SINGLE_BLOCK if single_block else 0))
+             | (0 if power_orth else QB_POWER_NO_ORTH) | (QB_SINGLE_BLOCK if single_block else 0)
+             | (0 if speculate else QB_NO_SPECULATE))
     need = int(lib.qb_workspace_bytes(m, n, b, kcap, flags))
     if need == 0:
         raise QBError(_lib.QB_EINVAL, "qb_workspace_bytes")

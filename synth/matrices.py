@@ -1,9 +1,9 @@
 """Seeded synthetic matrices with prescribed singular values.
 
-The construction follows the paper's accuracy test matrices (Section 5.2,
+The construction follows the paper's accuracy test matrices (Section 6.2,
 "Matrix 1", "Matrix 2", "Matrix 5"): A = U diag(d) V^T where U and V are
 random matrices with orthonormal columns obtained from the QR factorisation
-of Gaussian matrices.  The speed experiments of Section 5.1 note that the
+of Gaussian matrices.  The speed experiments of Section 6.1 note that the
 choice of matrix does not matter for run time, so the timed workloads use the
 same family with the singular-value profiles of the benchmark configurations.
 

@@ -156,3 +156,48 @@ def test_batched_tile_table_checked_on_host():
         for r in range(len(R)):
             for wc in range(3):
                 assert lib.qb_batched_set_tile(r, wc, saved[r][wc]) == _lib.QB_OK
+
+
+def test_size_limits_rejected_up_front():
+    """Sizes the kernels cannot launch (32-bit tile offsets, the downdate
+    grid) are refused before any device work, not midway through a run."""
+    lib = _lib.load()
+    assert lib.qb_workspace_bytes((1 << 24) - 1, 64, 64, -1, 0) == 0   # even_up(m) = 2^24
+    assert lib.qb_workspace_bytes((1 << 24) - 2, 64, 64, -1, 0) > 0
+    assert lib.qb_workspace_bytes(64, 65535 * 64 + 1, 64, -1, 0) == 0  # downdate grid
+    assert lib.qb_workspace_bytes(64, 65535 * 64, 64, -1, 0) > 0
+    assert lib.qb_workspace_bytes(100, 80, 16, 81, 0) == 0              # kmax > min(m, n)
+    assert lib.qb_workspace_bytes(100, 80, 16, 0, 0) > 0                # capacity 0 is valid
+    k = ctypes.c_int64(7)
+    fake = ctypes.c_void_p(4096)
+    ws = ctypes.c_void_p(1 << 20)
+    for lda, ldq, ldb in ((1 << 24, 100, 80), (100, 1 << 24, 80), (100, 100, 1 << 24)):
+        assert lib.qb_factor(fake, 100, 80, lda, 0.1, 16, 0, 1, fake, ldq, fake, ldb, -1,
+                             ctypes.byref(k), None, ws, 1 << 30, None, 0) == _lib.QB_EINVAL
+    assert lib.qb_factor(fake, 64, 65535 * 64 + 1, 64, 0.1, 16, 0, 1, fake, 64, fake, 64, -1,
+                         ctypes.byref(k), None, ws, 1 << 30, None, 0) == _lib.QB_EINVAL
+
+
+def _no_gpu_here() -> bool:
+    import torch
+    return torch.cuda.device_count() == 0
+
+
+@pytest.mark.skipif(not _no_gpu_here(), reason="checks the answer on a machine without a GPU")
+def test_no_device_is_reported():
+    """With valid arguments and no usable device, every entry point that
+    would launch work returns QB_ENODEVICE before touching a pointer."""
+    lib = _lib.load()
+    k = ctypes.c_int64(7)
+    fake = ctypes.c_void_p(4096)
+    ws = ctypes.c_void_p(1 << 20)
+    assert lib.qb_factor(fake, 100, 80, 100, 0.1, 16, 0, 1, fake, 100, fake, 80, -1,
+                         ctypes.byref(k), None, ws, 1 << 30, None, 0) == _lib.QB_ENODEVICE
+    assert k.value == 0
+    assert lib.qb_sketch(1, 10, 0, 4, fake, 10, None) == _lib.QB_ENODEVICE
+    kept = ctypes.c_int32(3)
+    assert lib.qb_orth(fake, 100, 8, 100, fake, 100, ctypes.byref(kept), ws, 1 << 30,
+                       None) == _lib.QB_ENODEVICE
+    assert lib.qb_frob2(fake, 10, 10, 10, ctypes.byref(ctypes.c_double()), None, ws, 1 << 30,
+                        None) == _lib.QB_ENODEVICE
+    assert lib.qb_status_string(_lib.QB_ENODEVICE).startswith(b"QB_ENODEVICE")

@@ -56,6 +56,29 @@ def test_first_blocks_match_oracle(pow2, P, prec):
         assert abs(Eg - Eo) <= max(TOL[prec], 1e-13) * nA ** 2
 
 
+@pytest.mark.parametrize("P", [0, 1])
+def test_first_16_blocks_match_oracle(pow2, P):
+    """The first 16 blocks (k = 2048) of the benchmark's float64 run against
+    the oracle: the re-projection products at k up to 1920 in their
+    128 x 128 and split-depth forms, at full m and n."""
+    wl, A, Ah = pow2
+    nA = float(np.linalg.norm(Ah))
+    eps = wl.eps_rel * nA
+    kmax = 16 * wl.b
+    g = qbmi.qb_factor(A, eps, wl.b, P, wl.seed_omega, kmax=kmax)
+    o = randqb_pb(Ah, eps, wl.b, P, wl.seed_omega, kmax=kmax)
+    print(f"[case] pow2 16 blocks P={P} k={g.k}/{o.k}", flush=True)
+    assert g.k == o.k == kmax and g.widths == o.widths and g.stop_reason == "KMAX"
+    Q, B = g.Q.cpu().numpy(), g.B.cpu().numpy()
+    assert np.linalg.norm(Q.T @ Q - np.eye(g.k)) < 1e-12
+    rel = np.linalg.norm(Q @ B - o.Q @ o.B) / nA
+    print(f"[case] |QB - QB_oracle|/|A| = {rel:.3e}", flush=True)
+    assert rel <= TOL["f64"]
+    for Eg, Eo, Dg, Do in zip(g.E, o.E, g.D, o.D):
+        assert abs(Eg - Eo) <= 1e-13 * nA ** 2
+        assert abs(Dg - Do) <= 1e-13 * nA ** 2
+
+
 @pytest.mark.parametrize("P,prec", [(0, "f64"), (1, "f64"), (0, "bf16x3")])
 def test_full_run_properties(pow2, P, prec):
     wl, A, Ah = pow2

@@ -131,3 +131,18 @@ def test_deterministic_bitwise(cuda):
     g2 = qbmi.qb_factor(Ad, 1e-3 * np.linalg.norm(A), 32, 1, 9)
     assert g1.k == g2.k
     assert torch.equal(g1.Q, g2.Q) and torch.equal(g1.B, g2.B)
+
+
+@pytest.mark.parametrize("P", [0, 1])
+def test_full_rank_run_with_wide_reprojection(cuda, P):
+    """4000 x 3000, b = 128, tolerance below the smallest singular value: all
+    24 blocks run (23 of 128 columns, the last 56 wide) and k reaches
+    min(m, n).  Once k w > 256^2 the coefficients Qbar^T Q_i take the
+    128 x 128 tiles and Qbar C the split-depth (stream-K) form with
+    alpha = -1, beta = 1; the last, narrow block runs at full m."""
+    s = synth.spectrum("exp", 3000, scale=400.0)
+    A = synth.prescribed_svd(4000, 3000, s, 41, 42)
+    nA = math.sqrt(sumsq(A))
+    g, o = run_both(A, 1e-12 * nA, 128, P, seed=77)
+    assert g.k == 3000 and g.blocks == 24 and g.widths[-1] == 56
+    assert math.sqrt(g.D[-1]) <= 1e-12 * nA

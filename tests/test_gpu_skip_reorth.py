@@ -1,5 +1,5 @@
 """GPU parity of the skip-re-orthonormalisation and single-pass forms
-(Section 5.4, Section 6.4 / Figure 8; randQB_p of Figure 5) against the
+(Section 5.4, Section 6.3 / Figure 8; randQB_p of Figure 5) against the
 oracle's power_orth=False / max_blocks=1 paths, through the C ABI.
 
 Bars: same rank, widths and stop reason; Q B within 1e-10 ||A|| where the

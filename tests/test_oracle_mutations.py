@@ -34,7 +34,7 @@ def mutant(modname: str, old: str, new: str) -> types.ModuleType:
 
 
 def _invariants_hold(randqb_pb) -> bool:
-    """The Prop. 3.1 / Pythagoras / Eckart-Young pins of test_oracle_randqb."""
+    """The Proposition 4.1 / Pythagoras / Eckart-Young pins of test_oracle_randqb."""
     s = synth.spectrum("exp", 120, scale=6.0)
     A = synth.prescribed_svd(160, 120, s, 1, 2)
     nA = float(np.linalg.norm(A))

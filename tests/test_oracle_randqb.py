@@ -2,9 +2,9 @@
 
 Each test checks a fact the paper or the mathematics fixes, independent of
 the oracle's own arithmetic:
-  Prop. 3.1(a)   Qbar orthonormal
-  Prop. 3.1(b)   A^(i) = A - Qbar Bbar  and  Bbar = Qbar^T A
-  Prop. 3.1(c)   R(Qbar) = R(A [Omega_1 ... Omega_i])          (P = 0)
+  Proposition 4.1(a)   Qbar orthonormal
+  Proposition 4.1(b)   A^(i) = A - Qbar Bbar  and  Bbar = Qbar^T A
+  Proposition 4.1(c)   R(Qbar) = R(A [Omega_1 ... Omega_i])          (P = 0)
   Section 4.1    for a fixed Omega the projector does not depend on b
                  (b = k is Figure 3, b = 1 is Algorithm 1 with (4a)-(4c))
   eq. minerrors  error >= Eckart-Young optimum

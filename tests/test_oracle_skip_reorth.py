@@ -1,5 +1,5 @@
 """Pins of the oracle's unblocked and skip-re-orthonormalisation paths
-(Section 5.4, Section 6.4 and Figure 8; randQB_p of Figure 5).
+(Section 5.4, Section 6.3 and Figure 8; randQB_p of Figure 5).
 
 * single pass with orth between applications = subspace iteration started
   from A Omega with a Householder QR (numpy) at each step: same projector;
@@ -86,7 +86,7 @@ TAU = 2.0 ** -20   # relative column size CholQR with the 2^-40 Gram test resolv
 
 @pytest.mark.parametrize("P", [1, 2])
 def test_floor_without_reorth_single_pass_but_not_blocked(P):
-    """Matrix 1 of Section 6.3 (800 x 600, singular values down to 1e-18).
+    """Matrix 1 of Section 6.2 (800 x 600, singular values down to 1e-18).
 
     A single pass resolves nothing below sigma_1 tau^(1/(2P+1)) without
     re-orthonormalisation (Section 5.4 with the orth's resolution tau in
