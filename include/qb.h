@@ -47,6 +47,8 @@ extern "C" {
 #define QB_EWORKSPACE      -3   /* workspace NULL or smaller than required */
 #define QB_EHIP            -4   /* a HIP runtime call failed               */
 #define QB_ENODEVICE       -5   /* no usable gfx950 device                 */
+#define QB_ETOOBIG         -6   /* qb_factor_noalloc: the problem needs more
+                                   workspace than its fixed scratch        */
 
 /* ---- stop reasons (qb_info.stop_reason) -------------------------------- */
 #define QB_STOP_TOL_TRACKED 0   /* ||A||^2 - sum ||B_i||^2 <= eps^2 - delta */
@@ -156,6 +158,32 @@ int qb_factor(const double* A, int64_t m, int64_t n, int64_t lda,
               double* Q, int64_t ldq, double* B, int64_t ldb, int64_t kmax,
               int64_t* k, qb_info* info, void* workspace, size_t ws_bytes,
               void* stream, uint32_t flags);
+
+/*
+ * qb_factor_noalloc -- qb_factor for callers that cannot allocate: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, results and errors as qb_factor, with no
+ * workspace argument: the workspace is a fixed device array of
+ * QB_NOALLOC_SCRATCH_BYTES inside the library, one per device, held from
+ * the library's load until the process ends.  The call allocates nothing
+ * (no hipMalloc, hipFree, pinned host memory or events): the per-block
+ * stop quantities are copied to a host stack buffer and the stream is
+ * synchronised instead, and the stream is idle when the call returns.
+ * Keep qb_profile_enable off, as its events are created on demand.
+ *
+ * Limit: problems for which qb_workspace_bytes(m, n, b, kmax, flags)
+ * exceeds QB_NOALLOC_SCRATCH_BYTES are rejected with QB_ETOOBIG before any
+ * device work (QB_OVERWRITE_A saves the m x n residual copy).  Every call
+ * on a device shares that device's scratch, which keeps the last call's
+ * contents (no result depends on them): calls that overlap on one device,
+ * from different streams or threads, race and must be serialised by the
+ * caller.
+ */
+#define QB_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+int qb_factor_noalloc(const double* A, int64_t m, int64_t n, int64_t lda,
+                      double eps, int32_t b, int32_t power_iters, uint64_t seed,
+                      double* Q, int64_t ldq, double* B, int64_t ldb, int64_t kmax,
+                      int64_t* k, qb_info* info, void* stream, uint32_t flags);
 
 /* Human-readable name of a status code (static string). */
 const char* qb_status_string(int status);

@@ -30,6 +30,8 @@ QB_ENONFINITE = -2
 QB_EWORKSPACE = -3
 QB_EHIP = -4
 QB_ENODEVICE = -5
+QB_ETOOBIG = -6
+QB_NOALLOC_SCRATCH_BYTES = 128 << 20
 
 BATCH_ROLES = {"sample": 0, "gram": 1, "apply": 2, "reproj_c": 3, "reproj_q": 4, "b": 5,
                "downdate": 6}
@@ -90,6 +92,10 @@ SIGNATURES = {
                                  c_vp, c_i64, c_vp, c_i64, c_i64,
                                  ctypes.POINTER(c_i64), ctypes.POINTER(QBInfo), c_vp, c_size,
                                  c_vp, c_u32]),
+    "qb_factor_noalloc": (ctypes.c_int, [c_vp, c_i64, c_i64, c_i64, c_dbl, c_i32, c_i32, c_u64,
+                                         c_vp, c_i64, c_vp, c_i64, c_i64,
+                                         ctypes.POINTER(c_i64), ctypes.POINTER(QBInfo), c_vp,
+                                         c_u32]),
     "qb_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "qb_sketch": (ctypes.c_int, [c_u64, c_i64, c_i64, c_i32, c_vp, c_i64, c_vp]),
     "qb_orth_workspace_bytes": (c_size, [c_i64, c_i32]),

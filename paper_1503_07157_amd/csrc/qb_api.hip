@@ -215,6 +215,8 @@ const char* qb_status_string(int status) {
     case QB_EWORKSPACE: return "QB_EWORKSPACE: workspace missing or too small";
     case QB_EHIP: return "QB_EHIP: HIP runtime error";
     case QB_ENODEVICE: return "QB_ENODEVICE: no usable device";
+    case QB_ETOOBIG:
+      return "QB_ETOOBIG: the problem needs more workspace than qb_factor_noalloc's fixed scratch";
     default: return "QB_UNKNOWN";
   }
 }
@@ -229,10 +231,18 @@ size_t qb_workspace_bytes(int64_t m, int64_t n, int32_t b, int64_t kmax, uint32_
   return a.used + 256;
 }
 
-int qb_factor(const double* A, int64_t m, int64_t n, int64_t lda, double eps, int32_t b,
-              int32_t power_iters, uint64_t seed, double* Q, int64_t ldq, double* B, int64_t ldb,
-              int64_t kmax, int64_t* k_out, qb_info* info, void* workspace, size_t ws_bytes,
-              void* stream, uint32_t flags) {
+}  // extern "C"
+
+namespace {
+
+// The factorisation behind qb_factor and qb_factor_noalloc.  With `pinned`
+// the per-block scalars go through the thread's pinned mailbox (allocated on
+// its first use) and an event; without it they are copied into a host stack
+// buffer and the stream is synchronised, so nothing is allocated.
+int factor_impl(const double* A, int64_t m, int64_t n, int64_t lda, double eps, int32_t b,
+                int32_t power_iters, uint64_t seed, double* Q, int64_t ldq, double* B,
+                int64_t ldb, int64_t kmax, int64_t* k_out, qb_info* info, void* workspace,
+                size_t ws_bytes, void* stream, uint32_t flags, bool pinned) {
   if (k_out) *k_out = 0;
   if (!k_out || !A || !Q || !B) return QB_EINVAL;
   if (!valid_sizes(m, n, b) || power_iters < 0 || !(eps >= 0.0) || !std::isfinite(eps))
@@ -313,8 +323,15 @@ int qb_factor(const double* A, int64_t m, int64_t n, int64_t lda, double eps, in
     if (copy_matrix(A, lda, R, ldr, m, n, st)) return QB_EHIP;
   }
 
-  Mailbox* mb = mailbox();
-  if (mb == nullptr) return QB_EHIP;
+  Mailbox* mb = nullptr;
+  double hbox[4] = {0.0, 0.0, 0.0, 0.0};
+  int hkept = 0;
+  if (pinned) {
+    mb = mailbox();
+    if (mb == nullptr) return QB_EHIP;
+  }
+  double* box_scal = mb ? mb->scal : hbox;
+  int* box_kept = mb ? mb->kept : &hkept;
   DD sigB{0.0, 0.0};
   const int64_t ldm = wk.ldm;
   // sketch and sample of a block already queued behind the previous block's
@@ -379,11 +396,11 @@ int qb_factor(const double* A, int64_t m, int64_t n, int64_t lda, double eps, in
     if (sum_partials(wk.sq1, nb, wk.scal + 2, st)) return QB_EHIP;
     if (downdate(R, ldr, Qout, ldq, B + k, ldb, m, n, w, wk.sq2, &nd, st)) return QB_EHIP;
     if (sum_partials(wk.sq2, nd, wk.scal + 0, st)) return QB_EHIP;
-    if (hipMemcpyAsync(mb->scal, wk.scal, 4 * sizeof(double), hipMemcpyDeviceToHost, st) !=
+    if (hipMemcpyAsync(box_scal, wk.scal, 4 * sizeof(double), hipMemcpyDeviceToHost, st) !=
             hipSuccess ||
-        hipMemcpyAsync(mb->kept, wk.ow.kept, sizeof(int), hipMemcpyDeviceToHost, st) !=
+        hipMemcpyAsync(box_kept, wk.ow.kept, sizeof(int), hipMemcpyDeviceToHost, st) !=
             hipSuccess ||
-        hipEventRecord(mb->ev, st) != hipSuccess)
+        (mb && hipEventRecord(mb->ev, st) != hipSuccess))
       return QB_EHIP;
     // Queue the next block's sketch and sample (they read only R, already
     // downdated, and write only Omega and Y) assuming no column is dropped;
@@ -398,10 +415,11 @@ int qb_factor(const double* A, int64_t m, int64_t n, int64_t lda, double eps, in
         spec_w = wn;
       }
     }
-    if (hipEventSynchronize(mb->ev) != hipSuccess) return QB_EHIP;
+    if ((mb ? hipEventSynchronize(mb->ev) : hipStreamSynchronize(st)) != hipSuccess)
+      return QB_EHIP;
     double hs[4];
-    std::memcpy(hs, mb->scal, sizeof(hs));
-    const int wkept = *mb->kept;
+    std::memcpy(hs, box_scal, sizeof(hs));
+    const int wkept = *box_kept;
     if (wkept <= 0) { reason = QB_STOP_EXHAUSTED; break; }
     k += wkept;
     ++blocks;
@@ -423,6 +441,58 @@ int qb_factor(const double* A, int64_t m, int64_t n, int64_t lda, double eps, in
     if (k >= kcap) { reason = (kcap < r) ? QB_STOP_KMAX : QB_STOP_RANK_CAP; break; }
   }
   return finish(reason);
+}
+
+// Fixed device scratch of qb_factor_noalloc: one copy per device, held from
+// the library's load until the process ends.  Host code never uses the
+// symbol's name as an address: the device address comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+__device__ __align__(256) char scratch[QB_NOALLOC_SCRATCH_BYTES];
+
+void* scratch_address() {
+  constexpr int kMaxDevices = 64;
+  static std::atomic<void*> addr[kMaxDevices];
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  void* p = addr[dev].load(std::memory_order_acquire);
+  if (p == nullptr) {
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    addr[dev].store(p, std::memory_order_release);  // same value from any racing thread
+  }
+  return p;
+}
+
+}  // namespace
+
+extern "C" {
+
+int qb_factor(const double* A, int64_t m, int64_t n, int64_t lda, double eps, int32_t b,
+              int32_t power_iters, uint64_t seed, double* Q, int64_t ldq, double* B, int64_t ldb,
+              int64_t kmax, int64_t* k_out, qb_info* info, void* workspace, size_t ws_bytes,
+              void* stream, uint32_t flags) {
+  return factor_impl(A, m, n, lda, eps, b, power_iters, seed, Q, ldq, B, ldb, kmax, k_out, info,
+                     workspace, ws_bytes, stream, flags, /*pinned=*/true);
+}
+
+int qb_factor_noalloc(const double* A, int64_t m, int64_t n, int64_t lda, double eps, int32_t b,
+                      int32_t power_iters, uint64_t seed, double* Q, int64_t ldq, double* B,
+                      int64_t ldb, int64_t kmax, int64_t* k_out, qb_info* info, void* stream,
+                      uint32_t flags) {
+  if (k_out) *k_out = 0;
+  const size_t need = qb_workspace_bytes(m, n, b, kmax, flags);
+  if (need == 0) return QB_EINVAL;
+  if (need > QB_NOALLOC_SCRATCH_BYTES) return QB_ETOOBIG;
+  if (const int dv = device_ready()) return dv;
+  void* ws = scratch_address();
+  if (ws == nullptr) return QB_EHIP;
+  return factor_impl(A, m, n, lda, eps, b, power_iters, seed, Q, ldq, B, ldb, kmax, k_out, info,
+                     ws, QB_NOALLOC_SCRATCH_BYTES, stream, flags, /*pinned=*/false);
 }
 
 int qb_sketch(uint64_t seed, int64_t n, int64_t col0, int32_t w, double* out, int64_t ld,

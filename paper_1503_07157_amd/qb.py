@@ -88,14 +88,18 @@ def qb_factor(A: torch.Tensor, eps: float, b: int, power_iters: int = 0, seed: i
               trace_cap: int = 4096, workspace: torch.Tensor | None = None,
               Q: torch.Tensor | None = None, B: torch.Tensor | None = None,
               bgemm: str = "f64", power_orth: bool = True,
-              single_block: bool = False, speculate: bool = True) -> QBResult:
+              single_block: bool = False, speculate: bool = True,
+              noalloc: bool = False) -> QBResult:
     """Blocked adaptive randomized QB (randQB_pb) of the column-major float64
     device matrix A to Frobenius tolerance eps.  Returns Q[:, :k], B[:k, :].
     sample / bgemm: precision of the sampling products and of B_i = Q_i^T A
     ("f64", "f32", "bf16x3").  power_orth=False skips the orthonormalisation
     between applications of A and A^T; single_block=True stops after the
     first block (the unblocked scheme with l = b).  speculate=False queues no
-    work past the stop decision (QB_NO_SPECULATE)."""
+    work past the stop decision (QB_NO_SPECULATE).  noalloc=True calls
+    qb_factor_noalloc, which runs in the library's fixed device scratch
+    (`workspace` is then ignored; Q and B are still allocated here unless
+    passed)."""
     lib = _lib.load()
     lda = _ld(A, "A")
     m, n = A.shape
@@ -110,11 +114,12 @@ def qb_factor(A: torch.Tensor, eps: float, b: int, power_iters: int = 0, seed: i
     flags = (QB_SAMPLE[sample] | QB_BGEMM[bgemm] | (QB_OVERWRITE_A if overwrite else 0)
              | (0 if power_orth else QB_POWER_NO_ORTH) | (QB_SINGLE_BLOCK if single_block else 0)
              | (0 if speculate else QB_NO_SPECULATE))
-    need = int(lib.qb_workspace_bytes(m, n, b, kcap, flags))
-    if need == 0:
-        raise QBError(_lib.QB_EINVAL, "qb_workspace_bytes")
-    if workspace is None or workspace.numel() < need + 256:
-        workspace = _workspace(need, dev)
+    if not noalloc:
+        need = int(lib.qb_workspace_bytes(m, n, b, kcap, flags))
+        if need == 0:
+            raise QBError(_lib.QB_EINVAL, "qb_workspace_bytes")
+        if workspace is None or workspace.numel() < need + 256:
+            workspace = _workspace(need, dev)
     info = QBInfo()
     tw = (ctypes.c_int32 * trace_cap)()
     tE = (ctypes.c_double * trace_cap)()
@@ -124,11 +129,18 @@ def qb_factor(A: torch.Tensor, eps: float, b: int, power_iters: int = 0, seed: i
     info.trace_E = ctypes.cast(tE, ctypes.POINTER(ctypes.c_double))
     info.trace_D = ctypes.cast(tD, ctypes.POINTER(ctypes.c_double))
     k = ctypes.c_int64(0)
-    code = lib.qb_factor(A.data_ptr(), m, n, lda, float(eps), int(b), int(power_iters),
-                         int(seed) & 0xFFFFFFFFFFFFFFFF, Q.data_ptr(), ldq, B.data_ptr(), ldb,
-                         kcap, ctypes.byref(k), ctypes.byref(info), _aligned_ptr(workspace),
-                         need, _stream(dev), flags)
-    _check(code, "qb_factor")
+    if noalloc:
+        code = lib.qb_factor_noalloc(A.data_ptr(), m, n, lda, float(eps), int(b),
+                                     int(power_iters), int(seed) & 0xFFFFFFFFFFFFFFFF,
+                                     Q.data_ptr(), ldq, B.data_ptr(), ldb, kcap, ctypes.byref(k),
+                                     ctypes.byref(info), _stream(dev), flags)
+        _check(code, "qb_factor_noalloc")
+    else:
+        code = lib.qb_factor(A.data_ptr(), m, n, lda, float(eps), int(b), int(power_iters),
+                             int(seed) & 0xFFFFFFFFFFFFFFFF, Q.data_ptr(), ldq, B.data_ptr(), ldb,
+                             kcap, ctypes.byref(k), ctypes.byref(info), _aligned_ptr(workspace),
+                             need, _stream(dev), flags)
+        _check(code, "qb_factor")
     kk = int(k.value)
     L = info.trace_len
     return QBResult(Q=Q[:, :kk], B=B[:kk, :], k=kk, status=code,

@@ -36,7 +36,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_status_strings():
     lib = _lib.load()
-    for code in (0, 1, 2, -1, -2, -3, -4, -5):
+    for code in (0, 1, 2, -1, -2, -3, -4, -5, -6):
         assert lib.qb_status_string(code).startswith(b"QB_")
     assert lib.qb_status_string(12345) == b"QB_UNKNOWN"
 
@@ -201,3 +201,23 @@ def test_no_device_is_reported():
     assert lib.qb_frob2(fake, 10, 10, 10, ctypes.byref(ctypes.c_double()), None, ws, 1 << 30,
                         None) == _lib.QB_ENODEVICE
     assert lib.qb_status_string(_lib.QB_ENODEVICE).startswith(b"QB_ENODEVICE")
+
+
+def test_noalloc_limits_checked_on_host():
+    """qb_factor_noalloc rejects invalid sizes (QB_EINVAL) and problems whose
+    workspace exceeds its fixed scratch (QB_ETOOBIG) before touching a
+    device or a pointer."""
+    lib = _lib.load()
+    k = ctypes.c_int64(7)
+    fake = ctypes.c_void_p(4096)
+    # 4000 x 4000: the residual copy alone is 128 MB
+    assert lib.qb_workspace_bytes(4000, 4000, 64, -1, 0) > _lib.QB_NOALLOC_SCRATCH_BYTES
+    assert lib.qb_factor_noalloc(fake, 4000, 4000, 4000, 0.1, 64, 0, 1, fake, 4000, fake, 4000,
+                                 -1, ctypes.byref(k), None, None, 0) == _lib.QB_ETOOBIG
+    assert k.value == 0
+    assert lib.qb_factor_noalloc(fake, 0, 10, 1, 0.1, 4, 0, 1, fake, 1, fake, 10, -1,
+                                 ctypes.byref(k), None, None, 0) == _lib.QB_EINVAL
+    assert lib.qb_status_string(_lib.QB_ETOOBIG).startswith(b"QB_ETOOBIG")
+    if _no_gpu_here():
+        assert lib.qb_factor_noalloc(fake, 100, 80, 100, 0.1, 16, 0, 1, fake, 100, fake, 80, -1,
+                                     ctypes.byref(k), None, None, 0) == _lib.QB_ENODEVICE
