@@ -49,6 +49,7 @@ import numpy as np
 
 from .gaussian import omega_block
 from .cholqr import cholqr2, DROP_REL
+from .intsplit import sample_exact
 
 STOP = {
     "TOL_TRACKED": 0,
@@ -99,7 +100,7 @@ def _stop_decision(E: float, D: float, eps2: float, delta: float):
 def randqb_pb(A: np.ndarray, eps: float, b: int, power_iters: int = 0, seed: int = 0,
               kmax: int | None = None, omega_fn=None, drop_rel: float = DROP_REL,
               reorth: bool = True, power_orth: bool = True,
-              max_blocks: int | None = None) -> QBResult:
+              max_blocks: int | None = None, sample: str = "f64") -> QBResult:
     """Blocked adaptive QB of A (m x n) to Frobenius tolerance eps.
 
     omega_fn(n, col0, w) -> n x w, if given, replaces the Philox sketch (used
@@ -110,7 +111,10 @@ def randqb_pb(A: np.ndarray, eps: float, b: int, power_iters: int = 0, seed: int
     b = l is the unblocked scheme: randQB (Figure 3) for P = 0 and randQB_p
     (Figure 5) for P >= 1, one pass of width l with no continuation when
     orth drops columns; the run then ends with stop reason KMAX unless the
-    tolerance was met.
+    tolerance was met.  sample="int8x8" forms the sample of step (3) as the
+    exact-range product of intsplit.py (the residual on a fixed-point grid
+    times the sketch on a 1/16 grid, exponent from the previous block's
+    ||A^(i-1)||_F^2); the products of the power iterations stay float64.
     """
     A = np.asarray(A, dtype=np.float64)
     m, n = A.shape
@@ -118,6 +122,8 @@ def randqb_pb(A: np.ndarray, eps: float, b: int, power_iters: int = 0, seed: int
     if not (np.isfinite(eps) and eps >= 0) or b < 1 or power_iters < 0:
         raise ValueError("invalid argument")
     if max_blocks is not None and max_blocks < 1:
+        raise ValueError("invalid argument")
+    if sample not in ("f64", "int8x8"):
         raise ValueError("invalid argument")
     if not np.all(np.isfinite(A)):
         raise FloatingPointError("non-finite entry in A")
@@ -148,7 +154,10 @@ def randqb_pb(A: np.ndarray, eps: float, b: int, power_iters: int = 0, seed: int
             break
         # (2)-(3): sample the current residual and orthonormalise
         Om = omega_fn(n, k, w)
-        Y = R @ Om
+        if sample == "int8x8":
+            Y = sample_exact(R, Om, res.D[-1] if res.D else sA)
+        else:
+            Y = R @ Om
         if power_orth:
             Qi, kept = cholqr2(Y, drop_rel)
             # (4)-(7): power iterations on the residual, orth after every product
