@@ -625,7 +625,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="inv1_20000x16000")
     ap.add_argument("--power-iters", type=int, default=0)
-    ap.add_argument("--sample", default="f64", choices=["f64", "f32", "bf16x3"])
+    ap.add_argument("--sample", default="f64", choices=["f64", "f32", "bf16x3", "int8x8"])
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true",
@@ -684,7 +684,8 @@ def main():
         r = min(w.m, w.n)
         Qb = torch.empty((r, w.m), dtype=torch.float64, device="cuda").t()
         Bb = torch.empty((w.n, r), dtype=torch.float64, device="cuda").t()
-        need = qbmi.workspace_bytes(w.m, w.n, w.b, r)
+        need = max(qbmi.workspace_bytes(w.m, w.n, w.b, r, sample=sm)
+                   for sm in ("f64", "int8x8"))
         wsb = torch.empty(need + 512, dtype=torch.uint8, device="cuda")
         return Qb, Bb, wsb
 
@@ -747,12 +748,32 @@ def main():
             f"{vms:.1f} ms rel_err={row['rel_err']:.2e} {vres.stop_reason}")
         return vres
 
+    mixed = None
     if not args.no_variants:
-        # mixed-precision sampling on the same matrix, read against the float64 run
+        # mixed-precision sampling on the same matrix, read against the float64
+        # run: the exact-range int8 sample first (the mixed form that reaches
+        # the float64 tolerance at k = min(m, n) < m), then the rounded f32 and
+        # bf16x3 samples; then P + 1 power iterations, where the last product
+        # of each block runs in float64 in every mode
         ref = (res.Q @ res.B) if args.sample == "f64" else None
-        for vs in ("f32", "bf16x3"):
+        for vs in ("int8x8", "f32", "bf16x3"):
             if vs != args.sample:
-                variant(wl, A, eps, P, vs, bufs, ref=ref)
+                vr = variant(wl, A, eps, P, vs, bufs, ref=ref)
+                if vs == "int8x8" and vr is not None and args.sample == "f64":
+                    row = variants[-1]
+                    mixed = {"sample": vs, "power_iters": P, "solve_s": row["solve_s"],
+                             "gflops": row["gflops"], "k": row["k"], "stop": row["stop"],
+                             "rel_err": row["rel_err"], "reaches_eps": row["status"] == 0,
+                             "speedup_vs_f64": (ms / 1e3) / row["solve_s"],
+                             "f64_solve_s": ms / 1e3}
+                del vr
+        del ref
+        torch.cuda.empty_cache()
+        r64 = variant(wl, A, eps, P + 1, "f64", bufs)
+        ref = (r64.Q @ r64.B) if r64 is not None else None
+        del r64
+        for vs in ("f32", "bf16x3"):
+            variant(wl, A, eps, P + 1, vs, bufs, ref=ref)
         del ref
         torch.cuda.empty_cache()
     cpu = None
@@ -776,7 +797,7 @@ def main():
                 r64 = variant(w2, X2, e2, vp, "f64", bufs)
                 ref = (r64.Q @ r64.B) if r64 is not None else None
                 del r64
-                for vs in ("f32", "bf16x3"):
+                for vs in ("int8x8", "f32", "bf16x3"):
                     variant(w2, X2, e2, vp, vs, bufs, ref=ref)
                 del ref
                 torch.cuda.empty_cache()
@@ -797,6 +818,7 @@ def main():
                    "seeds": {"U": wl.seed_u, "V": wl.seed_v, "omega": wl.seed_omega}},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "mixed": mixed,
         "variants": variants,
         "small_workload": small,
         "kernels": kernels,

@@ -61,10 +61,25 @@ extern "C" {
 /* ---- flags ------------------------------------------------------------- */
 #define QB_OVERWRITE_A    (1u << 0)  /* A becomes the residual (Figure 4
                                         overwrites A); no copy is made     */
-/* precision of the sampling products A*Omega, A^T*Q, A*Z (Fig. 6 (3),(5),(6)) */
+/* precision of the sampling products A*Omega, A^T*Q, A*Z (Fig. 6 (3),(5),(6)).
+ * With P >= 1 the last A*Z of each block, whose columns span Q_i, runs in
+ * float64 in every mode: a rounded product would leave in Q_i a component
+ * outside range(A) that no later block removes once k = min(m, n) < m. */
 #define QB_SAMPLE_F64     (0u << 4)
 #define QB_SAMPLE_F32     (1u << 4)
 #define QB_SAMPLE_BF16X3  (2u << 4)
+/* Exact-range sample: A Omega_i is formed as the exact product, on the int8
+ * MFMA with int32 sums, of A on a fixed-point grid (2^(E-55), E fixed by
+ * ||A||_F so every entry lies below 2^(E-1); eight base-128 int8 digits per
+ * entry) and the sketch rounded to a grid of 1/16 (int8, clipped at
+ * +-127/16), then rounded once to float64.  The sample thus lies in range(A)
+ * to float64 accuracy, so the factorisation reaches the tolerances of the
+ * float64 form even at k = min(m, n) < m, where a rounded low-precision
+ * sample floors at its own accuracy.  The sketch is the quantised Gaussian,
+ * a different (equally valid) sketch from the float64 form's.  Power
+ * iterations, if any, run in float64 in this mode.  Depth (n) per call is
+ * unlimited (split in chunks of at most 2^17). */
+#define QB_SAMPLE_INT8X8  (3u << 4)
 #define QB_SAMPLE_MASK    (3u << 4)
 /* precision of the projection B_i = Q_i^T A^(i-1) (Fig. 4 (4), Fig. 6 (9)).
  * The downdate, the residual norm and the stopping rule stay float64, so
@@ -208,8 +223,11 @@ int qb_orth(const double* X, int64_t m, int32_t w, int64_t ldx,
 
 /* Y = X * W (m x w) in the requested sampling precision (QB_SAMPLE_*):
  * X m x K (ldx), W K x w (ldw), Y m x w (ldy); w <= 256.  This is the
- * product of Figure 4 step (3) and Figure 6 step (6).
- * Workspace: qb_gemm_workspace_bytes(m, K, w). */
+ * product of Figure 4 step (3) and Figure 6 step (6).  QB_SAMPLE_INT8X8
+ * computes the exact product of W rounded to the 1/16 grid (clipped at
+ * +-127/16) with X on the fixed-point grid that ||X||_F fixes (see the
+ * flag), rounded once to float64.
+ * Workspace: qb_gemm_workspace_bytes(m, K, w), 256-byte aligned. */
 size_t qb_gemm_workspace_bytes(int64_t m, int64_t K, int32_t w);
 int qb_sample(const double* X, int64_t m, int64_t K, int64_t ldx,
               const double* W, int32_t w, int64_t ldw,
@@ -218,7 +236,8 @@ int qb_sample(const double* X, int64_t m, int64_t K, int64_t ldx,
 
 /* C = Q^T X (w x N) in the requested precision: Q is K x w (ldq), X is
  * K x N (ldx), C is w x N (ldc); w <= 256.  Figure 4 step (4), Figure 6
- * steps (5) and (9).  Workspace: qb_gemm_workspace_bytes(N, K, w). */
+ * steps (5) and (9).  precision: QB_SAMPLE_F64, _F32 or _BF16X3.
+ * Workspace: qb_gemm_workspace_bytes(N, K, w), 256-byte aligned. */
 int qb_project(const double* Qm, int64_t K, int32_t w, int64_t ldq,
                const double* X, int64_t N, int64_t ldx,
                double* C, int64_t ldc, uint32_t precision,

@@ -39,7 +39,7 @@ BATCH_TILES = {"64x64": 0, "16x16": 1, "32x32": 2, "64x32": 3, "32x64": 4}
 QB_STOP = {0: "TOL_TRACKED", 1: "TOL_DIRECT", 2: "RANK_CAP", 3: "EXHAUSTED", 4: "KMAX", 5: "ZERO"}
 
 QB_OVERWRITE_A = 1 << 0
-QB_SAMPLE = {"f64": 0 << 4, "f32": 1 << 4, "bf16x3": 2 << 4}
+QB_SAMPLE = {"f64": 0 << 4, "f32": 1 << 4, "bf16x3": 2 << 4, "int8x8": 3 << 4}
 QB_BGEMM = {"f64": 0 << 6, "f32": 1 << 6, "bf16x3": 2 << 6}
 QB_POWER_NO_ORTH = 1 << 8
 QB_SINGLE_BLOCK = 1 << 9

@@ -33,7 +33,7 @@ PER_FILE = {
 }
 SOURCES = ["k_sketch.hip", "k_gemm64.hip", "k_gemm_batched.hip", "k_gemm_lowp.hip", "k_orth.hip",
            "k_misc.hip", "qb_api.hip",
-           "k_post.hip", "qb_batch.hip", "qb_adjoint.hip", "prof.hip"]
+           "k_post.hip", "qb_batch.hip", "qb_adjoint.hip", "prof.hip", "k_sample_i8.hip"]
 
 
 def hipcc() -> str:

@@ -62,7 +62,8 @@ const char* kNames[kKCount] = {"sketch", "gemm_nn", "gemm_tn", "reduce", "downda
                                "chol_drop", "trinv", "norm", "copy", "gemm_nn_lowp",
                                "gemm_tn_lowp", "gemm_nn_64", "gemm_tn_64", "gemm_nn_256",
                                "batch_sample", "batch_gram", "batch_apply", "batch_reproj",
-                               "batch_b", "batch_downdate", "chol_batched", "batch_misc"};
+                               "batch_b", "batch_downdate", "chol_batched", "batch_misc",
+                               "sample_i8"};
 
 }  // namespace
 

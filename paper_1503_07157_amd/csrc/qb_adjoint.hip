@@ -173,6 +173,7 @@ int carve_adj(Arena& a, const Dims& d, AdjWork* W) {
   size_t part = 1;
   each_product(d, [&](int64_t M, int64_t N, int64_t K) {
     part = std::max(part, partial_doubles(M, N, choose_split(M, N, K)));
+    part = std::max(part, partial_doubles(M, N, choose_split(M, N, K, 2, true)));
   });
   W->part = a.take<double>(part);
   W->dropped = a.take<int>(2);
@@ -186,7 +187,8 @@ struct Mm {
   hipStream_t s;
   int nn(const double* X, int64_t ldx, const double* Wm, int64_t ldw, double* Y, int64_t ldy,
          int64_t M, int64_t N, int64_t K, double alpha, double beta) const {
-    return gemm_nn(X, ldx, Wm, ldw, Y, ldy, M, N, K, alpha, beta, choose_split(M, N, K), part, s);
+    return gemm_nn(X, ldx, Wm, ldw, Y, ldy, M, N, K, alpha, beta, choose_split(M, N, K, 2, true),
+                   part, s);
   }
   int tn(const double* Qm, int64_t ldq, const double* X, int64_t ldx, double* C, int64_t ldc,
          int64_t P, int64_t N, int64_t K) const {

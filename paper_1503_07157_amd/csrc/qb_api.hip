@@ -68,15 +68,18 @@ struct Work {
   int* flags = nullptr;     // per-workgroup non-finite flags
   double* scal = nullptr;   // [0,1] D_i (hi, lo); [2,3] ||B_i||^2; [4,5] ||A||^2
   int* iscal = nullptr;     // [0] non-finite flag
+  int8_t* omq = nullptr;    // int8 sketch of the exact-range sample (QB_SAMPLE_INT8X8)
   OrthWork ow{};
 };
 
-size_t max_partials(int64_t m, int64_t n, int b, int64_t kcap) {
-  size_t best = 1;
+size_t max_partials(int64_t m, int64_t n, int b, int64_t kcap, bool exact) {
+  size_t best = exact ? sample_i8_partials(m, b, n) : 1;
   auto upd = [&](int64_t rows, int64_t cols, int64_t K) {
-    const int s = choose_split(rows, cols, K);
-    const size_t v = partial_doubles(rows, cols, s);
-    if (v > best) best = v;
+    for (bool nn : {false, true}) {
+      const int s = choose_split(rows, cols, K, 2, nn);
+      const size_t v = partial_doubles(rows, cols, s);
+      if (v > best) best = v;
+    }
   };
   upd(m, b, n);                // Y = A Omega, Y = A Z
   upd(b, n, m);                // B_i = Q^T A, (A^T Q)^T
@@ -108,7 +111,9 @@ int carve(Arena& a, int64_t m, int64_t n, int b, int64_t kcap, int power_iters, 
   if (power_iters > 0) w->Z = a.take<double>(static_cast<size_t>(n) * b);
   w->ldc = kcap > 0 ? kcap : 1;
   w->C = a.take<double>(static_cast<size_t>(w->ldc) * b);
-  w->part = a.take<double>(max_partials(m, n, b, kcap));
+  const bool exact = (flags & QB_SAMPLE_MASK) == QB_SAMPLE_INT8X8;
+  w->part = a.take<double>(max_partials(m, n, b, kcap, exact));
+  if (exact) w->omq = a.take<int8_t>(static_cast<size_t>(sample_i8_kp(n)) * b);
   const size_t nsq = max_sq(m, n, b);
   w->sq1 = a.take<double>(nsq);
   w->sq2 = a.take<double>(nsq);
@@ -156,10 +161,19 @@ Mailbox* mailbox() {
   return &mb;
 }
 
+// Y = X W in the sampling precision.  QB_SAMPLE_INT8X8: the exact-range
+// product of the quantised W with X on its fixed-point grid, the exponent
+// taken from the device scalar *xnorm2 (||X||_F^2); omq holds the int8 W.
 int sample(uint32_t prec, const double* X, int64_t ldx, const double* W, int64_t ldw, double* Y,
-           int64_t ldy, int64_t M, int64_t N, int64_t K, double* part, hipStream_t s) {
+           int64_t ldy, int64_t M, int64_t N, int64_t K, double* part, hipStream_t s,
+           const double* xnorm2 = nullptr, int8_t* omq = nullptr) {
+  if (prec == QB_SAMPLE_INT8X8) {
+    if (xnorm2 == nullptr || omq == nullptr) return kEInval;
+    if (quantize_sketch(W, ldw, K, static_cast<int>(N), omq, s)) return kEHip;
+    return sample_i8(X, ldx, omq, Y, ldy, M, static_cast<int>(N), K, xnorm2, 0, part, s);
+  }
   // the bf16x3 form of this product runs one workgroup per CU
-  const int split = choose_split(M, N, K, prec == QB_SAMPLE_BF16X3 ? 1 : 2);
+  const int split = choose_split(M, N, K, prec == QB_SAMPLE_BF16X3 ? 1 : 2, prec == QB_SAMPLE_F64);
   if (prec == QB_SAMPLE_F64) return gemm_nn(X, ldx, W, ldw, Y, ldy, M, N, K, 1.0, 0.0, split, part, s);
   return gemm_nn_lowp(prec == QB_SAMPLE_F32 ? 1 : 2, X, ldx, W, ldw, Y, ldy, M, N, K, split,
                       part, s);
@@ -248,11 +262,20 @@ int factor_impl(const double* A, int64_t m, int64_t n, int64_t lda, double eps, 
   if (!valid_sizes(m, n, b) || power_iters < 0 || !(eps >= 0.0) || !std::isfinite(eps))
     return QB_EINVAL;
   const uint32_t prec = flags & QB_SAMPLE_MASK;
-  if (prec == QB_SAMPLE_MASK) return QB_EINVAL;
   // the B precision in the sampling encoding (QB_BGEMM_x >> 2 == QB_SAMPLE_x)
   const uint32_t bprec = (flags & QB_BGEMM_MASK) >> 2;
   if (bprec == QB_SAMPLE_MASK) return QB_EINVAL;
   const bool power_orth = (flags & QB_POWER_NO_ORTH) == 0;
+  // The product whose columns span Q_i decides whether Q_i lies in the
+  // range of the residual.  With power iterations, the last R Z runs in
+  // float64 whatever the sampling precision: a rounded product leaves in
+  // Q_i a component outside range(R) of the product's relative accuracy,
+  // which no later block removes once k reaches min(m, n) < m.  The
+  // products before it only steer the subspace and keep the low precision.
+  const uint32_t range_prec = QB_SAMPLE_F64;
+  // the exact-range sample serves the first product only; the products of
+  // the power iterations run in float64 in that mode
+  const uint32_t pow_prec = prec == QB_SAMPLE_INT8X8 ? QB_SAMPLE_F64 : prec;
   const bool single_block = (flags & QB_SINGLE_BLOCK) != 0;
   const int64_t r = std::min(m, n);
   if (kmax > r) return QB_EINVAL;
@@ -344,27 +367,34 @@ int factor_impl(const double* A, int64_t m, int64_t n, int64_t lda, double eps, 
     // (2)-(3) sample the residual and orthonormalise
     if (spec_k != k || spec_w != w) {
       if (launch_sketch(seed, n, k, w, wk.omega, n, st)) return QB_EHIP;
-      if (sample(prec, R, ldr, wk.omega, n, wk.Y, ldm, m, w, n, wk.part, st)) return QB_EHIP;
+      // ||R||_F^2 of the residual being sampled: ||A||^2, then D of the last block
+      if (sample(prec, R, ldr, wk.omega, n, wk.Y, ldm, m, w, n, wk.part, st,
+                 k == 0 ? wk.scal + 4 : wk.scal + 0, wk.omq))
+        return QB_EHIP;
     }
     spec_k = -1;
     if (power_orth) {
       if (orth_cholqr2(wk.Y, ldm, wk.Qi, ldm, m, w, wk.ow, st)) return QB_EHIP;
       // (4)-(7) power iterations on the residual
       for (int p = 0; p < power_iters; ++p) {
-        if (project_t(prec, wk.Qi, ldm, R, ldr, wk.Z, n, w, n, m, true, wk.part, nullptr,
+        if (project_t(pow_prec, wk.Qi, ldm, R, ldr, wk.Z, n, w, n, m, true, wk.part, nullptr,
                       nullptr, st))
           return QB_EHIP;
         if (orth_cholqr2(wk.Z, n, wk.Z, n, n, w, wk.ow, st)) return QB_EHIP;
-        if (sample(prec, R, ldr, wk.Z, n, wk.Y, ldm, m, w, n, wk.part, st)) return QB_EHIP;
+        if (sample(p + 1 == power_iters ? range_prec : pow_prec, R, ldr, wk.Z, n, wk.Y, ldm, m, w,
+                   n, wk.part, st))
+          return QB_EHIP;
         if (orth_cholqr2(wk.Y, ldm, wk.Qi, ldm, m, w, wk.ow, st)) return QB_EHIP;
       }
     } else {
       // Section 5.4: Y = (R R^T)^P R Omega_i without intermediate orth
       for (int p = 0; p < power_iters; ++p) {
-        if (project_t(prec, wk.Y, ldm, R, ldr, wk.Z, n, w, n, m, true, wk.part, nullptr, nullptr,
+        if (project_t(pow_prec, wk.Y, ldm, R, ldr, wk.Z, n, w, n, m, true, wk.part, nullptr, nullptr,
                       st))
           return QB_EHIP;
-        if (sample(prec, R, ldr, wk.Z, n, wk.Y, ldm, m, w, n, wk.part, st)) return QB_EHIP;
+        if (sample(p + 1 == power_iters ? range_prec : pow_prec, R, ldr, wk.Z, n, wk.Y, ldm, m, w,
+                   n, wk.part, st))
+          return QB_EHIP;
       }
       if (orth_cholqr2(wk.Y, ldm, wk.Qi, ldm, m, w, wk.ow, st)) return QB_EHIP;
     }
@@ -374,7 +404,7 @@ int factor_impl(const double* A, int64_t m, int64_t n, int64_t lda, double eps, 
       const int sp = choose_split(w, k, m);
       if (gemm_tn(wk.Qi, ldm, Q, ldq, wk.C, wk.ldc, w, k, m, true, sp, wk.part, nullptr, nullptr, st))
         return QB_EHIP;
-      const int sq = choose_split(m, w, k);
+      const int sq = choose_split(m, w, k, 2, true);
       if (gemm_nn(Q, ldq, wk.C, wk.ldc, wk.Qi, ldm, m, w, k, -1.0, 1.0, sq, wk.part, st))
         return QB_EHIP;
       if (orth_cholqr2(wk.Qi, ldm, Qout, ldq, m, w, wk.ow, st)) return QB_EHIP;
@@ -410,7 +440,9 @@ int factor_impl(const double* A, int64_t m, int64_t n, int64_t lda, double eps, 
       const int wn = static_cast<int>(std::min<int64_t>(bw, kcap - kn));
       if (wn > 0 && !single_block && !(flags & QB_NO_SPECULATE)) {
         if (launch_sketch(seed, n, kn, wn, wk.omega, n, st)) return QB_EHIP;
-        if (sample(prec, R, ldr, wk.omega, n, wk.Y, ldm, m, wn, n, wk.part, st)) return QB_EHIP;
+        if (sample(prec, R, ldr, wk.omega, n, wk.Y, ldm, m, wn, n, wk.part, st, wk.scal + 0,
+                   wk.omq))
+          return QB_EHIP;
         spec_k = kn;
         spec_w = wn;
       }
@@ -530,10 +562,43 @@ int qb_orth(const double* X, int64_t m, int32_t w, int64_t ldx, double* Q, int64
   return QB_OK;
 }
 
+}  // extern "C"
+
+namespace {
+// Workspace of qb_sample / qb_project: split-K partials (float64 and the
+// exact-range form), the int8 sketch, and the ||X||_F^2 pass of the exact
+// form (per-workgroup sums, flags, scalars).
+struct GemmScratch {
+  double* part = nullptr;
+  int8_t* omq = nullptr;
+  double* sq = nullptr;
+  int* fl = nullptr;
+  double* scal = nullptr;
+  int* iscal = nullptr;
+};
+size_t gemm_scratch(void* workspace, size_t ws_bytes, int64_t m, int64_t K, int32_t w,
+                    GemmScratch* g) {
+  Arena a{static_cast<char*>(workspace), ws_bytes, 0};
+  const size_t np = std::max(partial_doubles(m, w, choose_split(m, w, K, 2, true)),
+                             std::max(partial_doubles(m, w, choose_split(m, w, K, 2, false)),
+                                      sample_i8_partials(m, w, K)));
+  g->part = a.take<double>(np + 1);
+  g->omq = a.take<int8_t>(static_cast<size_t>(sample_i8_kp(K)) * w);
+  const size_t nsq = sumsq_partials_count(m, K) + 1;
+  g->sq = a.take<double>(nsq);
+  g->fl = a.take<int>(nsq);
+  g->scal = a.take<double>(8);
+  g->iscal = a.take<int>(4);
+  return a.used;
+}
+}  // namespace
+
+extern "C" {
+
 size_t qb_gemm_workspace_bytes(int64_t m, int64_t K, int32_t w) {
   if (m < 1 || K < 0 || w < 1 || w > kMaxPanel) return 0;
-  const int s = choose_split(m, w, K);
-  return (partial_doubles(m, w, s) + 1) * sizeof(double) + 256;
+  GemmScratch g;
+  return gemm_scratch(nullptr, 0, m, K, w, &g);
 }
 
 int qb_sample(const double* X, int64_t m, int64_t K, int64_t ldx, const double* W, int32_t w,
@@ -542,13 +607,21 @@ int qb_sample(const double* X, int64_t m, int64_t K, int64_t ldx, const double* 
   if (!X || !W || !Y || m < 1 || K < 1 || w < 1 || w > kMaxPanel || ldx < m || ldw < K || ldy < m)
     return QB_EINVAL;
   if (ldx >= kMaxLd || ldw >= kMaxLd || ldy >= kMaxLd) return QB_EINVAL;
-  if (precision != QB_SAMPLE_F64 && precision != QB_SAMPLE_F32 && precision != QB_SAMPLE_BF16X3)
+  if (precision != QB_SAMPLE_F64 && precision != QB_SAMPLE_F32 &&
+      precision != QB_SAMPLE_BF16X3 && precision != QB_SAMPLE_INT8X8)
     return QB_EINVAL;
-  if (!workspace || ws_bytes < qb_gemm_workspace_bytes(m, K, w)) return QB_EWORKSPACE;
+  if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return QB_EWORKSPACE;
+  GemmScratch g;
+  if (gemm_scratch(workspace, ws_bytes, m, K, w, &g) > ws_bytes) return QB_EWORKSPACE;
   if (const int dv = device_ready()) return dv;
-  double* part = reinterpret_cast<double*>((reinterpret_cast<uintptr_t>(workspace) + 255) & ~uintptr_t(255));
-  return sample(precision, X, ldx, W, ldw, Y, ldy, m, w, K, part, static_cast<hipStream_t>(stream))
-             ? QB_EHIP : QB_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (precision == QB_SAMPLE_INT8X8) {
+    int cnt = 0;  // ||X||_F^2 fixes the fixed-point grid
+    if (sumsq_partials(X, ldx, m, K, g.sq, &cnt, g.fl, st)) return QB_EHIP;
+    if (sum_partials_ex(g.sq, cnt, g.fl, g.scal, g.iscal, st)) return QB_EHIP;
+  }
+  return sample(precision, X, ldx, W, ldw, Y, ldy, m, w, K, g.part, st, g.scal, g.omq) ? QB_EHIP
+                                                                                     : QB_OK;
 }
 
 int qb_project(const double* Qm, int64_t K, int32_t w, int64_t ldq, const double* X, int64_t N,
@@ -559,10 +632,11 @@ int qb_project(const double* Qm, int64_t K, int32_t w, int64_t ldq, const double
   if (ldq >= kMaxLd || ldx >= kMaxLd || ldc >= kMaxLd) return QB_EINVAL;
   if (precision != QB_SAMPLE_F64 && precision != QB_SAMPLE_F32 && precision != QB_SAMPLE_BF16X3)
     return QB_EINVAL;
-  if (!workspace || ws_bytes < qb_gemm_workspace_bytes(N, K, w)) return QB_EWORKSPACE;
+  if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return QB_EWORKSPACE;
+  GemmScratch g;
+  if (gemm_scratch(workspace, ws_bytes, N, K, w, &g) > ws_bytes) return QB_EWORKSPACE;
   if (const int dv = device_ready()) return dv;
-  double* part = reinterpret_cast<double*>((reinterpret_cast<uintptr_t>(workspace) + 255) & ~uintptr_t(255));
-  return project_t(precision, Qm, ldq, X, ldx, C, ldc, w, N, K, false, part, nullptr, nullptr,
+  return project_t(precision, Qm, ldq, X, ldx, C, ldc, w, N, K, false, g.part, nullptr, nullptr,
                    static_cast<hipStream_t>(stream)) ? QB_EHIP : QB_OK;
 }
 

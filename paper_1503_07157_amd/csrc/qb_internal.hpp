@@ -76,7 +76,7 @@ enum KernelId {
   kKSketch = 0, kKGemmNN, kKGemmTN, kKReduce, kKDowndate, kKChol, kKTrinv, kKNorm, kKCopy,
   kKGemmNNLowp, kKGemmTNLowp, kKGemmNNSmall, kKGemmTNSmall, kKGemmNNTall,
   kKBatchSample, kKBatchGram, kKBatchApply, kKBatchReproj, kKBatchB, kKBatchDowndate,
-  kKCholBatched, kKBatchMisc, kKCount
+  kKCholBatched, kKBatchMisc, kKSampleI8, kKCount
 };
 const char* kernel_name(int id);
 bool prof_enabled();
@@ -100,7 +100,7 @@ int launch_sketch(uint64_t seed, int64_t n, int64_t col0, int w, double* out, in
 // split-K choice for an M x N product with reduction depth K (output tiles of
 // kTileM x kTileN): enough workgroups to fill the chip, at least
 // kSplitMinDepth per workgroup, partial storage bounded by kPartialCapDoubles
-int choose_split(int64_t M, int64_t N, int64_t K, int slots_per_cu = 2);
+int choose_split(int64_t M, int64_t N, int64_t K, int slots_per_cu = 2, bool tall_nn = false);
 // doubles of partial storage for an M x N product split `split` ways
 size_t partial_doubles(int64_t M, int64_t N, int split);
 
@@ -117,6 +117,19 @@ int gemm_nn(const double* X, int64_t ldx, const double* W, int64_t ldw, double* 
 int gemm_tn(const double* Qm, int64_t ldq, const double* X, int64_t ldx, double* C, int64_t ldc,
             int64_t P, int64_t N, int64_t K, bool transpose_out, int split, double* part,
             double* sq_part, int* sq_count, hipStream_t s);
+
+// Exact-range sample Y = A~ Omega~ on the int8 MFMA (k_sample_i8.hip).
+// quantize_sketch: Omega (n x w, ldo) -> int8 sketch q of sample_i8_kp(n) x w
+// bytes (column-major, zero padded).  sample_i8: Y (M x N, N <= 256) from A
+// (M x K, lda) and q; the exponent comes from the device scalar *dnorm2
+// (||A||_F^2) or, when dnorm2 is null, from e_host.  part: split-K partials
+// of sample_i8_partials(M, N, K) doubles.
+int64_t sample_i8_kp(int64_t K);
+int sample_i8_split(int64_t M, int64_t K);
+size_t sample_i8_partials(int64_t M, int64_t N, int64_t K);
+int quantize_sketch(const double* om, int64_t ldo, int64_t n, int w, int8_t* q, hipStream_t s);
+int sample_i8(const double* A, int64_t lda, const int8_t* q, double* Y, int64_t ldy, int64_t M,
+              int N, int64_t K, const double* dnorm2, int e_host, double* part, hipStream_t s);
 
 // mixed-precision sampling variants (precision: 1 = f32, 2 = bf16x3)
 int gemm_nn_lowp(int precision, const double* X, int64_t ldx, const double* W, int64_t ldw,
