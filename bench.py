@@ -19,9 +19,15 @@ The JSON line also carries
   cpu_baseline    the CPU oracle timed on the host on a bounded sample of the
                   same factorisation (its first blocks, same matrix), and the
                   GPU's first blocks compared with it
-  variants        mixed-precision sampling on the same matrix; the
-                  spectral-gap matrix of the same size; the 10000 x 10000
-                  j^-2 workload at P = 0 and 1
+  mixed           the mixed-precision form on the same matrix and
+                  tolerance: the sample as the exact-range int8 product
+                  (QB_SAMPLE_INT8X8), its seconds, error, stop reason and
+                  speed-up over the float64 line
+  variants        mixed-precision sampling on the same matrix (exact int8,
+                  FP32, bf16x3; then P + 1 power iterations in float64,
+                  FP32 and bf16x3 with the last product of each block in
+                  float64); the spectral-gap matrix of the same size; the
+                  10000 x 10000 j^-2 workload at P = 0 and 1
   small_workload  the 2000 x 1000 exp(-j/40) workload: GPU and oracle medians
                   of 3, the oracle also on one thread
 """
@@ -462,20 +468,23 @@ def adjoint_experiment(steps, warmup, no_cpu):
 
 def precision_experiment():
     """The precision sweep: 20000 x 16000 matrices with s_j = 1/j and with a
-    spectral gap (s_j = 1 for j <= 500, 1e-6 after), b = 256, P = 0,
-    eps = 1e-8 ||A||_F, the sampling products and B_i in float64, FP32 and
-    bf16x3.  Reports per variant the seconds, rank, stop reason and the true
-    error ||A - Q B||_F / ||A||_F (computed on the GPU).  The float64 run is
-    the reference the others are read against; the oracle itself is pinned
-    to the float64 path on these matrices through the first block
-    (tests/test_gpu_fullsize.py).  Prints one JSON line."""
+    spectral gap (s_j = 1 for j <= 500, 1e-6 after), b = 256,
+    eps = 1e-8 ||A||_F.  At P = 0: the sampling product in float64, as the
+    exact-range int8 product, in FP32 and in bf16x3, and B_i in FP32 and
+    bf16x3; at P = 1: float64, FP32 and bf16x3 sampling (the last product of
+    each block in float64).  Reports per variant the seconds, rank, stop
+    reason and the true error ||A - Q B||_F / ||A||_F (computed on the GPU).
+    The oracle is pinned to these paths through the first blocks
+    (tests/test_gpu_fullsize.py, tests/test_gpu_exact_sample.py).  Prints
+    one JSON line."""
     import torch
     import paper_1503_07157_amd as qbmi
     import synth
 
     rows = []
-    variants = [("f64", "f64"), ("f32", "f64"), ("bf16x3", "f64"), ("f64", "f32"),
-                ("f64", "bf16x3")]
+    variants = [(0, "f64", "f64"), (0, "int8x8", "f64"), (0, "f32", "f64"), (0, "bf16x3", "f64"),
+                (0, "f64", "f32"), (0, "f64", "bf16x3"), (1, "f64", "f64"), (1, "f32", "f64"),
+                (1, "bf16x3", "f64")]
     for name in ("inv1_20000x16000", "gap_20000x16000"):
         wl = synth.workload(name)
         log(f"[bench] precision: generating {name}")
@@ -483,27 +492,27 @@ def precision_experiment():
         nA = float(torch.linalg.norm(A))
         eps = wl.eps_rel * nA
         ws = None
-        for sample, bgemm in variants:
-            res = qbmi.qb_factor(A, eps, wl.b, 0, wl.seed_omega, sample=sample, bgemm=bgemm,
+        for P, sample, bgemm in variants:
+            res = qbmi.qb_factor(A, eps, wl.b, P, wl.seed_omega, sample=sample, bgemm=bgemm,
                                  workspace=ws)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            res = qbmi.qb_factor(A, eps, wl.b, 0, wl.seed_omega, sample=sample, bgemm=bgemm,
+            res = qbmi.qb_factor(A, eps, wl.b, P, wl.seed_omega, sample=sample, bgemm=bgemm,
                                  workspace=ws)
             torch.cuda.synchronize()
             sec = time.perf_counter() - t0
             err = residual_rel(torch, A, res)
-            fl = nominal_flops(wl.m, wl.n, res.k, 0)
-            rows.append({"workload": name, "sample": sample, "bgemm": bgemm, "k": res.k,
-                         "stop": res.stop_reason, "status": res.status, "seconds": sec,
-                         "gflops": fl / sec / 1e9, "rel_err": err})
-            log(f"[bench] precision {name} sample={sample} B={bgemm}: k={res.k} "
+            fl = nominal_flops(wl.m, wl.n, res.k, P)
+            rows.append({"workload": name, "power_iters": P, "sample": sample, "bgemm": bgemm,
+                         "k": res.k, "stop": res.stop_reason, "status": res.status,
+                         "seconds": sec, "gflops": fl / sec / 1e9, "rel_err": err})
+            log(f"[bench] precision {name} P={P} sample={sample} B={bgemm}: k={res.k} "
                 f"{res.stop_reason} {sec * 1e3:.0f} ms rel_err={err:.2e}")
             del res
             torch.cuda.empty_cache()
         del A
         torch.cuda.empty_cache()
-    print(json.dumps({"experiment": "precision", "eps_rel": 1e-8, "b": 256, "power_iters": 0,
+    print(json.dumps({"experiment": "precision", "eps_rel": 1e-8, "b": 256,
                       "rows": rows, "data": "synthetic"}), flush=True)
 
 

@@ -324,11 +324,13 @@ typedef struct qb_problem {
 size_t qb_factor_batched_workspace_bytes(const qb_problem* probs, int32_t count);
 /* probs: HOST array; every problem's outputs are written there.  Returns
  * QB_OK when the batch ran (see each problem's status), QB_EINVAL when any
- * problem is invalid (nothing runs), QB_EWORKSPACE or QB_EHIP.  The call
- * synchronises the stream once per block iteration (each problem's stop
- * decision is taken on the host) and returns with the stream idle.  It
- * keeps a pinned host staging buffer per calling thread, grown to the
- * largest batch seen, for the descriptors and per-iteration scalars. */
+ * problem is invalid (nothing runs), QB_EWORKSPACE or QB_EHIP.  Each
+ * problem's stop decision is taken on the device; eight block iterations
+ * at a time run as one HIP graph launch on `stream`, after which the call
+ * reads one flag (any problem still active), so it synchronises the stream
+ * once per eight iterations and returns with the stream idle.  It keeps a
+ * pinned host staging buffer per calling thread, grown to the largest
+ * batch seen, for the problem records. */
 int qb_factor_batched(qb_problem* probs, int32_t count, void* workspace, size_t ws_bytes,
                       void* stream);
 

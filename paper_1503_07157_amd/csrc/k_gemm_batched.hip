@@ -31,13 +31,12 @@ using BatchG32 = Shape<32, 32, 2, 2>;
 using BatchN32 = Shape<64, 32, 4, 1>;
 using BatchM32 = Shape<32, 64, 1, 4>;
 
+// One (problem, tile, depth chunk) of a batched product: workgroup-uniform
+// blk; the LDS stages are free again when it returns (the depth loop ends
+// with a barrier, the epilogue's sum synchronises).
 template <class S, int OP>
-__global__ __launch_bounds__(S::NT, S::OCC) void gemm_batched_kernel(
-    const BatchGemm* __restrict__ desc, int count) {
-  __shared__ __attribute__((aligned(16))) double As[2 * S::A_LDS];
-  __shared__ __attribute__((aligned(16))) double Bs[2 * S::B_LDS];
-  __shared__ double red[S::NT / 64];
-  const int64_t blk = blockIdx.x;
+__device__ __forceinline__ void batched_tile(const BatchGemm* __restrict__ desc, int count,
+                                             int64_t blk, double* As, double* Bs, double* red) {
   int lo = 0, hi = count - 1;
   while (lo < hi) {  // last problem with tile0 <= blk
     const int mid = (lo + hi + 1) >> 1;
@@ -116,13 +115,32 @@ __global__ __launch_bounds__(S::NT, S::OCC) void gemm_batched_kernel(
   }
 }
 
+// total: null for one workgroup per (problem, tile, chunk) (grid = the
+// total); else the device count of such units, which a grid of any size
+// walks in strides of the grid (the device-planned batch loop, whose
+// launches keep one grid while the work shrinks)
+template <class S, int OP>
+__global__ __launch_bounds__(S::NT, S::OCC) void gemm_batched_kernel(
+    const BatchGemm* __restrict__ desc, int count, const int64_t* __restrict__ total) {
+  __shared__ __attribute__((aligned(16))) double As[2 * S::A_LDS];
+  __shared__ __attribute__((aligned(16))) double Bs[2 * S::B_LDS];
+  __shared__ double red[S::NT / 64];
+  if (total == nullptr) {
+    batched_tile<S, OP>(desc, count, blockIdx.x, As, Bs, red);
+    return;
+  }
+  const int64_t n = *total;
+  for (int64_t blk = blockIdx.x; blk < n; blk += gridDim.x) {
+    batched_tile<S, OP>(desc, count, blk, As, Bs, red);
+    __syncthreads();
+  }
+}
+
 // C from the depth chunks of the problems with ksplit > 1, in chunk order;
-// kBatchRed elements of C per workgroup
+// kBatchRed elements of C per unit
 template <int OP>
-__global__ __launch_bounds__(256) void gemm_batched_reduce_kernel(
-    const BatchGemm* __restrict__ desc, int count) {
-  __shared__ double red[4];
-  const int64_t blk = blockIdx.x;
+__device__ __forceinline__ void batched_reduce_unit(const BatchGemm* __restrict__ desc, int count,
+                                                    int64_t blk, double* red) {
   int lo = 0, hi = count - 1;
   while (lo < hi) {  // last problem with rblock0 <= blk
     const int mid = (lo + hi + 1) >> 1;
@@ -155,20 +173,45 @@ __global__ __launch_bounds__(256) void gemm_batched_reduce_kernel(
   }
 }
 
+template <int OP>
+__global__ __launch_bounds__(256) void gemm_batched_reduce_kernel(
+    const BatchGemm* __restrict__ desc, int count, const int64_t* __restrict__ total) {
+  __shared__ double red[4];
+  if (total == nullptr) {
+    batched_reduce_unit<OP>(desc, count, blockIdx.x, red);
+    return;
+  }
+  const int64_t n = *total;
+  for (int64_t blk = blockIdx.x; blk < n; blk += gridDim.x) {
+    batched_reduce_unit<OP>(desc, count, blk, red);
+    __syncthreads();
+  }
+}
+
 }  // namespace
 
 namespace {
 template <class S>
-void launch_batched(int op, const BatchGemm* desc, int count, int64_t total_tiles, hipStream_t s) {
-  const dim3 grid(static_cast<unsigned>(total_tiles));
+void launch_batched(int op, const BatchGemm* desc, int count, int64_t grid_size,
+                    const int64_t* total, hipStream_t s) {
+  const dim3 grid(static_cast<unsigned>(grid_size));
   if (op == kBatchNN)
-    hipLaunchKernelGGL((gemm_batched_kernel<S, kBatchNN>), grid, dim3(S::NT), 0, s, desc, count);
+    hipLaunchKernelGGL((gemm_batched_kernel<S, kBatchNN>), grid, dim3(S::NT), 0, s, desc, count,
+                       total);
   else if (op == kBatchTN)
-    hipLaunchKernelGGL((gemm_batched_kernel<S, kBatchTN>), grid, dim3(S::NT), 0, s, desc, count);
+    hipLaunchKernelGGL((gemm_batched_kernel<S, kBatchTN>), grid, dim3(S::NT), 0, s, desc, count,
+                       total);
   else
-    hipLaunchKernelGGL((gemm_batched_kernel<S, kBatchDD>), grid, dim3(S::NT), 0, s, desc, count);
+    hipLaunchKernelGGL((gemm_batched_kernel<S, kBatchDD>), grid, dim3(S::NT), 0, s, desc, count,
+                       total);
 }
 }  // namespace
+
+static_assert(BatchG16::BM == 16 && BatchG16::BN == 16 && BatchG32::BM == 32 &&
+                  BatchG32::BN == 32 && BatchN32::BM == 64 && BatchN32::BN == 32 &&
+                  BatchM32::BM == 32 && BatchM32::BN == 64 && Small::BM == kBatchTile &&
+                  Small::BN == kBatchTile,
+              "batch_tile_dims_hd follows the tile shapes");
 
 void batch_tile_dims(int cls, int* bm, int* bn) {
   switch (cls) {
@@ -181,33 +224,36 @@ void batch_tile_dims(int cls, int* bm, int* bn) {
 }
 
 int gemm_batched(int op, int cls, const BatchGemm* desc, int count, int64_t total_tiles,
-                 int prof_id, double flops, double bytes, hipStream_t s) {
+                 int prof_id, double flops, double bytes, hipStream_t s,
+                 const int64_t* dev_total) {
   if (count <= 0 || total_tiles <= 0) return kOk;
   if (op == kBatchDD && cls == kTileG16) return kEInval;
   if (total_tiles > INT32_MAX) return kEInval;  // one-dimensional grid
   ProfScope ps(prof_id, flops, bytes, s);
   switch (cls) {
-    case kTileG16: launch_batched<BatchG16>(op, desc, count, total_tiles, s); break;
-    case kTileG32: launch_batched<BatchG32>(op, desc, count, total_tiles, s); break;
-    case kTileN32: launch_batched<BatchN32>(op, desc, count, total_tiles, s); break;
-    case kTileM32: launch_batched<BatchM32>(op, desc, count, total_tiles, s); break;
-    default: launch_batched<Small>(op, desc, count, total_tiles, s); break;
+    case kTileG16: launch_batched<BatchG16>(op, desc, count, total_tiles, dev_total, s); break;
+    case kTileG32: launch_batched<BatchG32>(op, desc, count, total_tiles, dev_total, s); break;
+    case kTileN32: launch_batched<BatchN32>(op, desc, count, total_tiles, dev_total, s); break;
+    case kTileM32: launch_batched<BatchM32>(op, desc, count, total_tiles, dev_total, s); break;
+    default: launch_batched<Small>(op, desc, count, total_tiles, dev_total, s); break;
   }
   QB_HIP_TRY(hipGetLastError());
   return kOk;
 }
 
 int gemm_batched_reduce(int op, const BatchGemm* desc, int count, int64_t total_rblocks,
-                        int prof_id, hipStream_t s) {
+                        int prof_id, hipStream_t s, const int64_t* dev_total) {
   if (count <= 0 || total_rblocks <= 0) return kOk;
   if (total_rblocks > INT32_MAX) return kEInval;
   if (op == kBatchDD) return kEInval;
   const dim3 grid(static_cast<unsigned>(total_rblocks));
   ProfScope ps(prof_id, 0.0, 0.0, s);
   if (op == kBatchNN)
-    hipLaunchKernelGGL(gemm_batched_reduce_kernel<kBatchNN>, grid, dim3(256), 0, s, desc, count);
+    hipLaunchKernelGGL(gemm_batched_reduce_kernel<kBatchNN>, grid, dim3(256), 0, s, desc, count,
+                       dev_total);
   else
-    hipLaunchKernelGGL(gemm_batched_reduce_kernel<kBatchTN>, grid, dim3(256), 0, s, desc, count);
+    hipLaunchKernelGGL(gemm_batched_reduce_kernel<kBatchTN>, grid, dim3(256), 0, s, desc, count,
+                       dev_total);
   QB_HIP_TRY(hipGetLastError());
   return kOk;
 }

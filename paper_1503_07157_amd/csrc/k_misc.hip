@@ -111,6 +111,7 @@ __global__ __launch_bounds__(kPartialSumThreads) void sum_partials_kernel(
 // one workgroup per problem of a batch
 __global__ __launch_bounds__(kSumThreads) void sum_batched_kernel(const BatchSum* __restrict__ d) {
   const BatchSum b = d[blockIdx.x];
+  if (b.count <= 0) return;  // a problem that takes no part in this step
   sum_partials_body<kSumThreads>(b.part, b.count, b.flags, b.out, b.iflag);
 }
 

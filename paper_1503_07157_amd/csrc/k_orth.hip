@@ -587,6 +587,7 @@ __global__ __launch_bounds__(512) void chol_inv_lds_kernel(const double* __restr
 template <int WMAX>
 __global__ __launch_bounds__(512) void chol_inv_batched_kernel(const BatchChol* __restrict__ desc) {
   const BatchChol c = desc[blockIdx.x];
+  if (c.w <= 0) return;  // a problem that takes no part in this step
   chol_inv_lds_body<WMAX>(c.G, c.w, c.kept, c.Tinv);
 }
 

@@ -143,9 +143,8 @@ __global__ __launch_bounds__(256) void sketch_kernel(uint32_t k0, uint32_t k1, i
 }
 
 // batch: workgroup -> (problem, pair block, column)
-__global__ __launch_bounds__(256) void sketch_batched_kernel(const BatchSketch* __restrict__ desc,
-                                                             int count) {
-  const int64_t blk = blockIdx.x;
+__device__ __forceinline__ void sketch_batched_unit(const BatchSketch* __restrict__ desc,
+                                                    int count, int64_t blk) {
   int lo = 0, hi = count - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -162,16 +161,30 @@ __global__ __launch_bounds__(256) void sketch_batched_kernel(const BatchSketch* 
               d.out, d.ld, t, lb / nb);
 }
 
+// total: null for one workgroup per unit, else the device unit count walked
+// in strides of the grid
+__global__ __launch_bounds__(256) void sketch_batched_kernel(const BatchSketch* __restrict__ desc,
+                                                             int count,
+                                                             const int64_t* __restrict__ total) {
+  if (total == nullptr) {
+    sketch_batched_unit(desc, count, blockIdx.x);
+    return;
+  }
+  const int64_t n = *total;
+  for (int64_t blk = blockIdx.x; blk < n; blk += gridDim.x) sketch_batched_unit(desc, count, blk);
+}
+
 }  // namespace
 
 int64_t sketch_blocks(int64_t n, int w) { return ((n + 1) / 2 + 255) / 256 * w; }
 
-int sketch_batched(const BatchSketch* desc, int count, int64_t total_blocks, hipStream_t s) {
+int sketch_batched(const BatchSketch* desc, int count, int64_t total_blocks, hipStream_t s,
+                   const int64_t* dev_total) {
   if (count <= 0 || total_blocks <= 0) return kOk;
   if (total_blocks > INT32_MAX) return kEInval;  // one-dimensional grid
   ProfScope ps(kKSketch, 0.0, 0.0, s);
   hipLaunchKernelGGL(sketch_batched_kernel, dim3(static_cast<unsigned>(total_blocks)), dim3(256),
-                     0, s, desc, count);
+                     0, s, desc, count, dev_total);
   QB_HIP_TRY(hipGetLastError());
   return kOk;
 }

@@ -4,15 +4,23 @@
 // Each block iteration runs, for all problems still active:
 //   sketch -> Y = R Omega -> CholQR2 (Gram, Cholesky + inverse, apply) ->
 //   [k > 0: C = Qbar^T Q, Q -= Qbar C, CholQR2] -> B_i = Q_i^T R with
-//   ||B_i||^2 -> R -= Q_i B_i with ||R||^2 -> per-problem compensated sums,
-// then copies every problem's scalars to the host at once and applies the
-// same stopping rule as qb_factor to each.  Problems stop independently;
-// the launches of an iteration cover only the active ones.  Products use
-// MFMA tiles of a class chosen per product role and panel width (a table,
-// see g_tile), one launch per class in use, with a workgroup -> (problem,
-// tile, depth chunk) mapping; the Cholesky runs one workgroup per problem.
-// Inputs are float; every stored value and every product is float64, so
-// each problem follows the float64 oracle.
+//   ||B_i||^2 -> R -= Q_i B_i with ||R||^2 -> per-problem compensated sums
+//   -> the stopping rule of qb_factor (Section 4.2) for each problem.
+// The loop is planned on the device: a plan kernel turns each problem's
+// state (rank k, width w, active) into the descriptors of every step, the
+// products walk the units the plan counted (a fixed grid per launch), and a
+// stop kernel applies the rule and sets the next width.  All launches of
+// an iteration therefore have fixed arguments; eight iterations are
+// captured once per call in a HIP graph, which is replayed until no
+// problem is active (the host reads one flag per replay).  With the
+// profiler on, or QB_BATCHED_EAGER set, the same launches run eagerly, one
+// iteration at a time.  Problems stop independently; a product's units
+// cover only the active problems.  Products use MFMA tiles of a class
+// chosen per product role and panel width (a table, see g_tile), one launch
+// per class the batch can use, with a unit -> (problem, tile, depth chunk)
+// mapping; the Cholesky runs one workgroup per problem.  Inputs are float;
+// every stored value and every product is float64, so each problem follows
+// the float64 oracle.
 #include <algorithm>
 #include <atomic>
 #include <cmath>
@@ -49,21 +57,8 @@ constexpr int64_t kSplitTiles = 64;
 constexpr int64_t kSplitChunk = 256;
 constexpr int64_t kPartDoubles = (kSplitTiles + kSplitTiles - 2) * kBatchTile * kBatchTile;
 
-inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+__host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline int64_t even_up(int64_t v) { return (v + 1) & ~int64_t(1); }
-
-struct DD {
-  double hi, lo;
-};
-inline DD two_sum_h(double a, double b) {
-  const double s = a + b, bb = s - a;
-  return {s, (a - (s - bb)) + (b - bb)};
-}
-inline DD dd_add(DD x, DD y) {
-  DD s = two_sum_h(x.hi, y.hi);
-  s.lo += x.lo + y.lo;
-  return two_sum_h(s.hi, s.lo);
-}
 
 struct Prob {
   // sizes
@@ -75,12 +70,6 @@ struct Prob {
   double* scal;  // [0..1] ||R||^2, [2..3] ||B_i||^2, [4..5] ||A||^2
   int* iflag;
   int64_t nconv;
-  // host state
-  int64_t k = 0;
-  int blocks = 0, reason = QB_STOP_ZERO, w = 0;
-  bool active = false;
-  DD sA{0, 0}, sigB{0, 0};
-  double eps2 = 0, delta = 0, floor2 = 0, lastE = 0, lastD = 0;
 };
 
 bool problem_ok(const qb_problem& p) {
@@ -96,6 +85,42 @@ bool problem_ok(const qb_problem& p) {
 
 // device workspace: per-problem buffers, the scalar and kept tables, and one
 // iteration's descriptors
+constexpr int kSteps = 13;  // product steps of one block iteration
+
+// static per-problem record (uploaded once per call)
+struct DevProb {
+  double *R, *omega, *Y, *Qt, *Qi, *C, *G, *Tinv, *sqB, *sqR, *part;
+  int* kept;
+  double* scal;
+  int* iflag;
+  double *Q, *B;
+  int64_t m, n, kcap, ldr, ldm, ldc, ldq, ldb;
+  uint64_t seed;
+  double eps;
+  int32_t b, pad;
+};
+// per-problem state across iterations
+struct DevState {
+  int64_t k;
+  int32_t w, active, blocks, reason, status, pad;
+  double sA_hi, sA_lo, sigB_hi, sigB_lo, eps2, delta, floor2, lastE, lastD;
+};
+struct TileTable {
+  int32_t cls[QB_ROLES][3];
+};
+
+// device tables of one iteration
+struct Plan {
+  BatchGemm* gemm;      // [kSteps][kTileClasses][count]
+  int64_t* tiles;       // [kSteps][kTileClasses] units of each product launch
+  int64_t* rblocks;     // [kSteps] units of each reduction launch
+  int64_t* sk_blocks;   // [1] sketch units
+  BatchSketch* sketch;  // [count]
+  BatchChol *c1, *c3;   // [count] Cholesky of the first pair of passes / of the re-projected pair
+  BatchSum *sB, *sR;    // [count]
+  int* any_active;      // [1]
+};
+
 struct Layout {
   std::vector<Prob> pr;
   double* scal_all;
@@ -103,6 +128,9 @@ struct Layout {
   int* iflag_all;
   char* desc;       // device descriptor block
   size_t desc_bytes;
+  DevProb* dprob;   // device-planned loop: static records, state, plan tables
+  DevState* dstate;
+  Plan plan;
 };
 
 size_t desc_block_bytes(int count) {
@@ -153,6 +181,19 @@ int carve_batch(Arena& a, const qb_problem* probs, int count, Layout* L) {
   }
   L->desc_bytes = desc_block_bytes(count);
   L->desc = a.take<char>(L->desc_bytes);
+  L->dprob = a.take<DevProb>(static_cast<size_t>(count));
+  L->dstate = a.take<DevState>(static_cast<size_t>(count));
+  Plan& pl = L->plan;
+  pl.gemm = a.take<BatchGemm>(static_cast<size_t>(kSteps) * kTileClasses * count);
+  pl.tiles = a.take<int64_t>(kSteps * kTileClasses);
+  pl.rblocks = a.take<int64_t>(kSteps);
+  pl.sk_blocks = a.take<int64_t>(1);
+  pl.sketch = a.take<BatchSketch>(static_cast<size_t>(count));
+  pl.c1 = a.take<BatchChol>(static_cast<size_t>(count));
+  pl.c3 = a.take<BatchChol>(static_cast<size_t>(count));
+  pl.sB = a.take<BatchSum>(static_cast<size_t>(count));
+  pl.sR = a.take<BatchSum>(static_cast<size_t>(count));
+  pl.any_active = a.take<int>(1);
   return (a.base != nullptr && a.used > a.cap) ? kEWorkspace : kOk;
 }
 
@@ -228,10 +269,12 @@ bool tile_allowed(int role, int wclass, int cls) {
   return true;
 }
 
-// part: the problem's split-K buffer (kPartDoubles), or null for no split
-BatchGemm gemm_desc(int cls, const double* A, int64_t lda, const double* B, int64_t ldb,
-                    double* C, int64_t ldc, int64_t M, int64_t N, int64_t K, double alpha,
-                    double beta, double* sq, double* part) {
+// part: the problem's split-K buffer (kPartDoubles), or null for no split.
+// Host and device (the device-planned loop) build the same descriptors.
+__host__ __device__ BatchGemm gemm_desc(int cls, const double* A, int64_t lda, const double* B,
+                                        int64_t ldb, double* C, int64_t ldc, int64_t M, int64_t N,
+                                        int64_t K, double alpha, double beta, double* sq,
+                                        double* part) {
   BatchGemm g{};
   g.A = A;
   g.B = B;
@@ -244,7 +287,7 @@ BatchGemm gemm_desc(int cls, const double* A, int64_t lda, const double* B, int6
   g.N = static_cast<int32_t>(N);
   g.K = static_cast<int32_t>(K);
   int bm = kBatchTile, bn = kBatchTile;
-  batch_tile_dims(cls, &bm, &bn);
+  batch_tile_dims_hd(cls, &bm, &bn);
   g.cls = cls;
   g.bm = bm;
   g.bn = bn;
@@ -260,7 +303,8 @@ BatchGemm gemm_desc(int cls, const double* A, int64_t lda, const double* B, int6
   g.part = nullptr;
   const int64_t tiles = static_cast<int64_t>(g.tiles_m) * g.tiles_n;
   if (part != nullptr && tiles < kSplitTiles && K >= 2 * kSplitChunk) {
-    int64_t ks = std::min(cdiv(kSplitTiles, tiles), K / kSplitChunk);
+    int64_t ks = cdiv(kSplitTiles, tiles) < K / kSplitChunk ? cdiv(kSplitTiles, tiles)
+                                                             : K / kSplitChunk;
     const int64_t chunk = cdiv(cdiv(K, ks), kTileK) * kTileK;
     ks = cdiv(K, chunk);
     if (ks > 1 && ks * tiles * bm * bn <= kPartDoubles) {
@@ -272,7 +316,7 @@ BatchGemm gemm_desc(int cls, const double* A, int64_t lda, const double* B, int6
   return g;
 }
 
-int64_t reduce_blocks(const BatchGemm& g) {
+__host__ __device__ int64_t reduce_blocks(const BatchGemm& g) {
   return g.ksplit > 1 ? cdiv(static_cast<int64_t>(g.M) * g.N, kBatchRed) : 0;
 }
 
@@ -316,9 +360,290 @@ Step group(const std::vector<BatchGemm>& v, bool reads_c = false) {
 }
 
 // partial sums of squares that a TN product with sq leaves per problem
-int32_t sq_count(const BatchGemm& g) {
+__host__ __device__ int32_t sq_count(const BatchGemm& g) {
   return static_cast<int32_t>(g.ksplit > 1 ? reduce_blocks(g)
                                            : static_cast<int64_t>(g.tiles_m) * g.tiles_n);
+}
+
+
+// ---- device-planned block loop ---------------------------------------------
+// The block loop's decisions (width, re-projection or not, the stopping rule)
+// live on the device: a plan kernel writes every step's descriptors from the
+// problems' state at the start of an iteration, the products walk the units
+// the plan counted, and a stop kernel applies the rule of qb_factor to each
+// problem.  Every launch of an iteration then has the same arguments, so the
+// iterations are captured once in a HIP graph and replayed; the host reads
+// one flag per replay (any problem still active).
+
+
+// the steps of one iteration (product launches), in issue order
+enum { kStY = 0, kStG1, kStA1, kStG2, kStA2, kStRC, kStRQ, kStG3, kStA3, kStG4, kStA4, kStB, kStD };
+__host__ __device__ inline int step_op(int s) {
+  return (s == kStG1 || s == kStG2 || s == kStRC || s == kStG3 || s == kStG4 || s == kStB)
+             ? kBatchTN
+             : (s == kStD ? kBatchDD : kBatchNN);
+}
+__host__ __device__ inline int step_role(int s) {
+  switch (s) {
+    case kStY: return QB_ROLE_SAMPLE;
+    case kStG1: case kStG2: case kStG3: case kStG4: return QB_ROLE_GRAM;
+    case kStA1: case kStA2: case kStA3: case kStA4: return QB_ROLE_APPLY;
+    case kStRC: return QB_ROLE_REPROJ_C;
+    case kStRQ: return QB_ROLE_REPROJ_Q;
+    case kStB: return QB_ROLE_B;
+    default: return QB_ROLE_DOWNDATE;
+  }
+}
+__host__ __device__ inline int width_class_hd(int w) { return w <= 16 ? 0 : w <= 32 ? 1 : 2; }
+
+// The descriptor of step s for problem p at width w and rank k (the same
+// operands and pointers as the host-planned loop); false when p takes no
+// part in the step.
+__host__ __device__ bool step_desc(int s, const DevProb& p, int64_t k, int w, const TileTable& tt,
+                          BatchGemm* g) {
+  const int cls = tt.cls[step_role(s)][width_class_hd(w)];
+  const bool rp = k > 0;  // re-projection steps run once a basis exists
+  double* Qo = p.Q + k * p.ldq;
+  switch (s) {
+    case kStY:
+      *g = gemm_desc(cls, p.R, p.ldr, p.omega, p.n, p.Y, p.ldm, p.m, w, p.n, 1.0, 0.0, nullptr, p.part);
+      return true;
+    case kStG1:
+      *g = gemm_desc(cls, p.Y, p.ldm, p.Y, p.ldm, p.G, w, w, w, p.m, 1.0, 0.0, nullptr, p.part);
+      return true;
+    case kStA1:
+      *g = gemm_desc(cls, p.Y, p.ldm, p.Tinv, w, p.Qt, p.ldm, p.m, w, w, 1.0, 0.0, nullptr, p.part);
+      return true;
+    case kStG2:
+      *g = gemm_desc(cls, p.Qt, p.ldm, p.Qt, p.ldm, p.G, w, w, w, p.m, 1.0, 0.0, nullptr, p.part);
+      return true;
+    case kStA2:
+      *g = gemm_desc(cls, p.Qt, p.ldm, p.Tinv, w, rp ? p.Qi : Qo, rp ? p.ldm : p.ldq, p.m, w, w,
+                     1.0, 0.0, nullptr, p.part);
+      return true;
+    case kStRC:
+      *g = gemm_desc(cls, p.Q, p.ldq, p.Qi, p.ldm, p.C, p.ldc, k, w, p.m, 1.0, 0.0, nullptr, p.part);
+      return rp;
+    case kStRQ:
+      *g = gemm_desc(cls, p.Q, p.ldq, p.C, p.ldc, p.Qi, p.ldm, p.m, w, k, -1.0, 1.0, nullptr, p.part);
+      return rp;
+    case kStG3:
+      *g = gemm_desc(cls, p.Qi, p.ldm, p.Qi, p.ldm, p.G, w, w, w, p.m, 1.0, 0.0, nullptr, p.part);
+      return rp;
+    case kStA3:
+      *g = gemm_desc(cls, p.Qi, p.ldm, p.Tinv, w, p.Qt, p.ldm, p.m, w, w, 1.0, 0.0, nullptr, p.part);
+      return rp;
+    case kStG4:
+      *g = gemm_desc(cls, p.Qt, p.ldm, p.Qt, p.ldm, p.G, w, w, w, p.m, 1.0, 0.0, nullptr, p.part);
+      return rp;
+    case kStA4:
+      *g = gemm_desc(cls, p.Qt, p.ldm, p.Tinv, w, Qo, p.ldq, p.m, w, w, 1.0, 0.0, nullptr, p.part);
+      return rp;
+    case kStB:
+      *g = gemm_desc(cls, Qo, p.ldq, p.R, p.ldr, p.B + k, p.ldb, w, p.n, p.m, 1.0, 0.0, p.sqB,
+                     p.part);
+      return true;
+    default:
+      *g = gemm_desc(cls, Qo, p.ldq, p.B + k, p.ldb, p.R, p.ldr, p.m, p.n, w, 1.0, 0.0, p.sqR,
+                     nullptr);
+      return true;
+  }
+}
+
+
+constexpr int kPlanThreads = 256;
+
+// exclusive scan of v over the workgroup (kPlanThreads); *total gets the sum
+__device__ int64_t block_scan(int64_t v, int64_t* total, int64_t* buf) {
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  int64_t x = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int64_t y = __shfl_up(x, off);
+    if (lane >= off) x += y;
+  }
+  __syncthreads();
+  if (lane == 63) buf[wave] = x;
+  __syncthreads();
+  int64_t before = 0, all = 0;
+#pragma unroll
+  for (int q = 0; q < kPlanThreads / 64; ++q) {
+    if (q < wave) before += buf[q];
+    all += buf[q];
+  }
+  *total = all;
+  return before + x - v;
+}
+
+// workgroup s < kSteps: the descriptors of product step s, class by class,
+// with each problem's first unit (tile0) and first reduction unit (rblock0);
+// workgroup kSteps: sketch, Cholesky and sum records
+__global__ __launch_bounds__(kPlanThreads) void batch_plan_kernel(const DevProb* __restrict__ P,
+                                                                  const DevState* __restrict__ S,
+                                                                  int count, TileTable tt, Plan pl) {
+  __shared__ int64_t buf[kPlanThreads / 64];
+  const int s = blockIdx.x;
+  if (s < kSteps) {
+    int64_t rcarry = 0;
+    for (int c = 0; c < kTileClasses; ++c) {
+      BatchGemm* out = pl.gemm + (static_cast<int64_t>(s) * kTileClasses + c) * count;
+      int64_t carry = 0;
+      for (int i0 = 0; i0 < count; i0 += kPlanThreads) {
+        const int i = i0 + static_cast<int>(threadIdx.x);
+        BatchGemm g{};
+        int64_t units = 0, runits = 0;
+        if (i < count && S[i].active) {
+          const int w = S[i].w;
+          if (step_desc(s, P[i], S[i].k, w, tt, &g) &&
+              tt.cls[step_role(s)][width_class_hd(w)] == c) {
+            units = static_cast<int64_t>(g.tiles_m) * g.tiles_n * g.ksplit;
+            runits = reduce_blocks(g);
+          }
+        }
+        int64_t tot = 0, rtot = 0;
+        const int64_t ex = block_scan(units, &tot, buf);
+        const int64_t rex = block_scan(runits, &rtot, buf);
+        if (i < count) {
+          if (units == 0) {  // no part in this launch: no units, no partial sums
+            g = BatchGemm{};
+            g.ksplit = 1;
+          }
+          g.tile0 = carry + ex;
+          g.rblock0 = rcarry + rex;
+          out[i] = g;
+        }
+        carry += tot;
+        rcarry += rtot;
+      }
+      if (threadIdx.x == 0) pl.tiles[s * kTileClasses + c] = carry;
+    }
+    if (threadIdx.x == 0) pl.rblocks[s] = rcarry;
+    return;
+  }
+  int64_t carry = 0;
+  for (int i0 = 0; i0 < count; i0 += kPlanThreads) {
+    const int i = i0 + static_cast<int>(threadIdx.x);
+    int64_t units = 0;
+    BatchSketch sk{};
+    BatchChol c1{}, c3{};
+    BatchSum sb{}, sr{};
+    if (i < count && S[i].active) {
+      const DevProb& p = P[i];
+      const int w = S[i].w;
+      const int64_t k = S[i].k;
+      units = ((p.n + 1) / 2 + 255) / 256 * w;  // as sketch_blocks(n, w)
+      sk = BatchSketch{p.seed, p.n, k, p.n, p.omega, 0, w};
+      c1 = BatchChol{p.G, p.kept, p.Tinv, w};
+      if (k > 0) c3 = c1;
+      BatchGemm gb, gd;
+      step_desc(kStB, p, k, w, tt, &gb);
+      step_desc(kStD, p, k, w, tt, &gd);
+      sb = BatchSum{p.sqB, nullptr, p.scal + 2, nullptr, sq_count(gb)};
+      sr = BatchSum{p.sqR, nullptr, p.scal + 0, nullptr, sq_count(gd)};
+    }
+    int64_t tot = 0;
+    const int64_t ex = block_scan(units, &tot, buf);
+    if (i < count) {
+      sk.block0 = carry + ex;
+      pl.sketch[i] = sk;
+      pl.c1[i] = c1;
+      pl.c3[i] = c3;
+      pl.sB[i] = sb;
+      pl.sR[i] = sr;
+    }
+    carry += tot;
+  }
+  if (threadIdx.x == 0) {
+    *pl.sk_blocks = carry;
+    *pl.any_active = 0;
+  }
+}
+
+__device__ inline void dd_add_dev(double& hi, double& lo, double bh, double bl) {
+  double s = hi + bh, bb = s - hi;
+  double e = (hi - (s - bb)) + (bh - bb);
+  e += lo + bl;
+  const double s2 = s + e, bb2 = s2 - s;
+  lo = (s - (s2 - bb2)) + (e - bb2);
+  hi = s2;
+}
+
+__device__ inline void next_width(const DevProb& p, DevState& st) {
+  const int64_t left = p.kcap - st.k;
+  st.w = static_cast<int32_t>(left < p.b ? left : p.b);
+  if (st.w <= 0) {
+    st.active = 0;
+    const int64_t r = p.m < p.n ? p.m : p.n;
+    st.reason = p.kcap < r ? QB_STOP_KMAX : QB_STOP_RANK_CAP;
+  }
+}
+
+// ||A||^2 and the non-finite flag of each problem -> the initial state
+__global__ __launch_bounds__(256) void batch_init_kernel(const DevProb* __restrict__ P,
+                                                         DevState* __restrict__ S, int count) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= count) return;
+  const DevProb& p = P[i];
+  DevState st{};
+  st.reason = QB_STOP_ZERO;
+  st.status = QB_OK;
+  if (p.iflag[0]) {
+    st.status = QB_ENONFINITE;
+  } else {
+    st.sA_hi = p.scal[4];
+    st.sA_lo = p.scal[5];
+    const double sAv = st.sA_hi + st.sA_lo;
+    st.lastE = st.lastD = sAv;
+    if (!isfinite(sAv)) {
+      st.status = QB_EINVAL;
+    } else {
+      st.eps2 = p.eps * p.eps;
+      st.delta = kDeltaRelB * sAv;
+      const double f = kFloorRelB * sqrt(sAv);
+      st.floor2 = f * f;
+      st.active = sAv > st.eps2 ? 1 : 0;
+      if (st.active) next_width(p, st);
+    }
+  }
+  S[i] = st;
+}
+
+// the stopping rule of qb_factor after an iteration, per active problem
+__global__ __launch_bounds__(256) void batch_stop_kernel(const DevProb* __restrict__ P,
+                                                         DevState* __restrict__ S, int count,
+                                                         int* __restrict__ any_active) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= count) return;
+  DevState st = S[i];
+  if (!st.active) return;
+  const DevProb& p = P[i];
+  const int wkept = p.kept[0];
+  if (wkept <= 0) {
+    st.active = 0;
+    st.reason = QB_STOP_EXHAUSTED;
+  } else {
+    st.k += wkept;
+    ++st.blocks;
+    dd_add_dev(st.sigB_hi, st.sigB_lo, p.scal[2], p.scal[3]);
+    double eh = st.sA_hi, el = st.sA_lo;
+    dd_add_dev(eh, el, -st.sigB_hi, -st.sigB_lo);
+    st.lastE = eh + el;
+    st.lastD = p.scal[0] + p.scal[1];
+    if (st.lastE <= st.eps2 - st.delta) {
+      st.active = 0;
+      st.reason = QB_STOP_TOL_TRACKED;
+    } else if (!(st.lastE > st.eps2 + st.delta) && st.lastD <= st.eps2) {
+      st.active = 0;
+      st.reason = QB_STOP_TOL_DIRECT;
+    } else if (st.lastD <= st.floor2) {
+      st.active = 0;
+      st.reason = QB_STOP_EXHAUSTED;
+    } else {
+      next_width(p, st);
+    }
+  }
+  S[i] = st;
+  if (st.active) atomicOr(any_active, 1);
 }
 
 
@@ -368,15 +693,10 @@ int qb_factor_batched(qb_problem* probs, int32_t count, void* workspace, size_t 
   // pinned host memory for the descriptors and the per-iteration scalars
   Stage sg;
   sg.cap = L.desc_bytes;
-  const size_t scal_bytes = static_cast<size_t>(count) * kScal * sizeof(double);
-  const size_t kept_bytes = static_cast<size_t>(count) * kKeptStride * sizeof(int);
-  const size_t flag_bytes = static_cast<size_t>(count) * sizeof(int);
-  void* hbuf = pinned_stage(sg.cap + scal_bytes + kept_bytes + flag_bytes);
+  void* hbuf = pinned_stage(sg.cap + 64);
   if (hbuf == nullptr) return QB_EHIP;
   sg.host = static_cast<char*>(hbuf);
-  double* hscal = reinterpret_cast<double*>(sg.host + sg.cap);
-  int* hkept = reinterpret_cast<int*>(sg.host + sg.cap + scal_bytes);
-  int* hflag = reinterpret_cast<int*>(sg.host + sg.cap + scal_bytes + kept_bytes);
+  int* hflag = reinterpret_cast<int*>(sg.host + sg.cap);  // the "still active" flag
   auto upload = [&]() -> int {
     if (sg.used == 0) return kOk;
     return hipMemcpyAsync(L.desc, sg.host, sg.used, hipMemcpyHostToDevice, st) == hipSuccess
@@ -384,14 +704,6 @@ int qb_factor_batched(qb_problem* probs, int32_t count, void* workspace, size_t 
                : kEHip;
   };
   auto dev = [&](size_t off) { return L.desc + off; };
-  auto fetch = [&]() -> int {
-    if (hipMemcpyAsync(hscal, L.scal_all, scal_bytes, hipMemcpyDeviceToHost, st) != hipSuccess ||
-        hipMemcpyAsync(hkept, L.kept_all, kept_bytes, hipMemcpyDeviceToHost, st) != hipSuccess ||
-        hipMemcpyAsync(hflag, L.iflag_all, flag_bytes, hipMemcpyDeviceToHost, st) != hipSuccess ||
-        hipStreamSynchronize(st) != hipSuccess)
-      return kEHip;
-    return kOk;
-  };
 
   auto run = [&]() -> int {
     // ---- R = double(A), ||A||^2, non-finite check ----------------------
@@ -410,252 +722,206 @@ int qb_factor_batched(qb_problem* probs, int32_t count, void* workspace, size_t 
       const size_t ocv = sg.put(cv), osu = sg.put(su);
       if (sg.overflow) return QB_EWORKSPACE;
       if (upload() || convert_batched(reinterpret_cast<BatchConvert*>(dev(ocv)), count, blocks, st) ||
-          sum_batched(reinterpret_cast<BatchSum*>(dev(osu)), count, st) || fetch())
+          sum_batched(reinterpret_cast<BatchSum*>(dev(osu)), count, st))
         return QB_EHIP;
     }
-    for (int i = 0; i < count; ++i) {
-      Prob& p = P[i];
-      qb_problem& q = probs[i];
-      q.k = 0;
-      q.blocks = 0;
-      q.stop_reason = QB_STOP_ZERO;
-      if (hflag[i]) {
-        q.status = QB_ENONFINITE;
-        continue;
+    // ---- static records, initial state ---------------------------------
+    {
+      std::vector<DevProb> dp(count);
+      for (int i = 0; i < count; ++i) {
+        const Prob& p = P[i];
+        const qb_problem& q = probs[i];
+        dp[i] = DevProb{p.R, p.omega, p.Y, p.Qt, p.Qi, p.C, p.G, p.Tinv, p.sqB, p.sqR, p.part,
+                        p.kept, p.scal, p.iflag, q.Q, q.B, p.m, p.n, p.kcap, p.ldr, p.ldm, p.ldc,
+                        q.ldq, q.ldb, q.seed, q.eps, p.b, 0};
       }
-      p.sA = DD{hscal[i * kScal + 4], hscal[i * kScal + 5]};
-      const double sAv = p.sA.hi + p.sA.lo;
-      q.normA2 = sAv;
-      q.resid2 = sAv;
-      if (!std::isfinite(sAv)) {
-        q.status = QB_EINVAL;
-        continue;
-      }
-      p.eps2 = q.eps * q.eps;
-      p.delta = kDeltaRelB * sAv;
-      p.floor2 = (kFloorRelB * std::sqrt(sAv)) * (kFloorRelB * std::sqrt(sAv));
-      p.lastE = p.lastD = sAv;
-      q.status = QB_OK;
-      p.active = sAv > p.eps2;
+      // appended after the conversion's descriptors: their copy to the
+      // device may still be reading the staging buffer
+      const size_t odp = sg.put(dp);
+      if (sg.overflow) return QB_EWORKSPACE;
+      if (hipMemcpyAsync(L.dprob, sg.host + odp, dp.size() * sizeof(DevProb),
+                         hipMemcpyHostToDevice, st) != hipSuccess)
+        return QB_EHIP;
+      hipLaunchKernelGGL(batch_init_kernel, dim3(static_cast<unsigned>(cdiv(count, 256))), dim3(256),
+                         0, st, L.dprob, L.dstate, count);
+      if (hipGetLastError() != hipSuccess) return QB_EHIP;
     }
 
-    // ---- block iterations ----------------------------------------------
-    for (;;) {
-      std::vector<int> act;
-      for (int i = 0; i < count; ++i) {
-        Prob& p = P[i];
-        if (!p.active) continue;
-        p.w = static_cast<int>(std::min<int64_t>(p.b, p.kcap - p.k));
-        if (p.w <= 0) {
-          p.active = false;
-          p.reason = p.kcap < std::min(p.m, p.n) ? QB_STOP_KMAX : QB_STOP_RANK_CAP;
-          continue;
+    // ---- launch plan: the classes each step may use and its grids --------
+    TileTable tt;
+    for (int r = 0; r < QB_ROLES; ++r)
+      for (int c = 0; c < 3; ++c) tt.cls[r][c] = g_tile[r][c].load(std::memory_order_relaxed);
+    int64_t grid[kSteps][kTileClasses] = {};
+    int64_t rgrid[kSteps] = {};
+    int64_t skgrid = 0;
+    for (int i = 0; i < count; ++i) {
+      const Prob& p = P[i];
+      const int64_t w = p.b, k = p.kcap;
+      skgrid += sketch_blocks(p.n, p.b);
+      for (int st_ = 0; st_ < kSteps; ++st_) {
+        int64_t M = 0, N = 0;
+        switch (st_) {
+          case kStY: case kStA1: case kStA2: case kStRQ: case kStA3: case kStA4: M = p.m; N = w; break;
+          case kStRC: M = k; N = w; break;
+          case kStB: M = w; N = p.n; break;
+          case kStD: M = p.m; N = p.n; break;
+          default: M = w; N = w; break;
         }
-        act.push_back(i);
-      }
-      if (act.empty()) break;
-      sg.used = 0;
-      sg.overflow = false;
-      const int na = static_cast<int>(act.size());
-      // sketch
-      std::vector<BatchSketch> sk(na);
-      int64_t skb = 0;
-      for (int a = 0; a < na; ++a) {
-        const Prob& p = P[act[a]];
-        sk[a] = BatchSketch{probs[act[a]].seed, p.n, p.k, p.n, p.omega, skb, p.w};
-        skb += sketch_blocks(p.n, p.w);
-      }
-      // Y = R Omega
-      std::vector<BatchGemm> gY(na);
-      for (int a = 0; a < na; ++a) {
-        const Prob& p = P[act[a]];
-        gY[a] = gemm_desc(tile_of(QB_ROLE_SAMPLE, p.w), p.R, p.ldr, p.omega, p.n, p.Y, p.ldm, p.m, p.w, p.n, 1.0,
-                          0.0, nullptr, p.part);
-      }
-      // CholQR pass helpers: Gram, Cholesky, apply into dst
-      auto gram = [&](const std::vector<int>& ids, double* const* X) {
-        std::vector<BatchGemm> g(ids.size());
-        for (size_t a = 0; a < ids.size(); ++a) {
-          const Prob& p = P[ids[a]];
-          g[a] = gemm_desc(tile_of(QB_ROLE_GRAM, p.w), X[a], p.ldm, X[a], p.ldm, p.G, p.w, p.w, p.w, p.m, 1.0,
-                           0.0, nullptr, p.part);
+        bool seen[kTileClasses] = {};
+        for (int wc = 0; wc <= width_class_hd(p.b); ++wc) {
+          const int c = tt.cls[step_role(st_)][wc];
+          if (seen[c]) continue;
+          seen[c] = true;
+          int bm = 0, bn = 0;
+          batch_tile_dims_hd(c, &bm, &bn);
+          grid[st_][c] += cdiv(M, bm) * cdiv(N, bn) + (st_ == kStD ? 0 : kSplitTiles);
         }
-        return g;
-      };
-      auto chol = [&](const std::vector<int>& ids) {
-        std::vector<BatchChol> c(ids.size());
-        for (size_t a = 0; a < ids.size(); ++a) {
-          const Prob& p = P[ids[a]];
-          c[a] = BatchChol{p.G, p.kept, p.Tinv, p.w};
-        }
-        return c;
-      };
-      auto apply = [&](const std::vector<int>& ids, double* const* X, double* const* D,
-                       const int64_t* ldd) {
-        std::vector<BatchGemm> g(ids.size());
-        for (size_t a = 0; a < ids.size(); ++a) {
-          const Prob& p = P[ids[a]];
-          g[a] = gemm_desc(tile_of(QB_ROLE_APPLY, p.w), X[a], p.ldm, p.Tinv, p.w, D[a], ldd[a], p.m, p.w, p.w,
-                           1.0, 0.0, nullptr, p.part);
-        }
-        return g;
-      };
-      std::vector<int> reproj;
-      for (int a = 0; a < na; ++a)
-        if (P[act[a]].k > 0) reproj.push_back(act[a]);
-      const int nr = static_cast<int>(reproj.size());
-      // pass 1 on Y -> Qt; pass 2 on Qt -> (k == 0 ? Q + k ldq : Qi)
-      std::vector<double*> xY(na), xQt(na), dQt(na), d2(na);
-      std::vector<int64_t> lQt(na), l2(na);
-      for (int a = 0; a < na; ++a) {
-        Prob& p = P[act[a]];
-        qb_problem& q = probs[act[a]];
-        xY[a] = p.Y;
-        xQt[a] = p.Qt;
-        dQt[a] = p.Qt;
-        lQt[a] = p.ldm;
-        d2[a] = p.k > 0 ? p.Qi : q.Q + p.k * q.ldq;
-        l2[a] = p.k > 0 ? p.ldm : q.ldq;
+        if (st_ != kStD) rgrid[st_] += cdiv(M * N, kBatchRed);
       }
-      std::vector<BatchGemm> g1 = gram(act, xY.data()), a1 = apply(act, xY.data(), dQt.data(), lQt.data());
-      std::vector<BatchGemm> g2 = gram(act, xQt.data()), a2 = apply(act, xQt.data(), d2.data(), l2.data());
-      std::vector<BatchChol> c1 = chol(act);
-
-      // re-projection of the problems with k > 0, then CholQR2 into Q + k ldq
-      std::vector<BatchGemm> rC(nr), rQ(nr);
-      std::vector<double*> xQi(nr), dQt2(nr), xQt2(nr), dOut(nr);
-      std::vector<int64_t> lQt2(nr), lOut(nr);
-      for (int a = 0; a < nr; ++a) {
-        Prob& p = P[reproj[a]];
-        qb_problem& q = probs[reproj[a]];
-        rC[a] = gemm_desc(tile_of(QB_ROLE_REPROJ_C, p.w), q.Q, q.ldq, p.Qi, p.ldm, p.C, p.ldc, p.k, p.w, p.m, 1.0,
-                          0.0, nullptr, p.part);
-        rQ[a] = gemm_desc(tile_of(QB_ROLE_REPROJ_Q, p.w), q.Q, q.ldq, p.C, p.ldc, p.Qi, p.ldm, p.m, p.w, p.k, -1.0,
-                          1.0, nullptr, p.part);
-        xQi[a] = p.Qi;
-        dQt2[a] = p.Qt;
-        xQt2[a] = p.Qt;
-        lQt2[a] = p.ldm;
-        dOut[a] = q.Q + p.k * q.ldq;
-        lOut[a] = q.ldq;
-      }
-      std::vector<BatchGemm> g3 = gram(reproj, xQi.data()), a3 = apply(reproj, xQi.data(), dQt2.data(), lQt2.data());
-      std::vector<BatchGemm> g4 = gram(reproj, xQt2.data()), a4 = apply(reproj, xQt2.data(), dOut.data(), lOut.data());
-      std::vector<BatchChol> c3 = chol(reproj);
-
-      // B_i = Q_i^T R with ||B_i||^2, R -= Q_i B_i with ||R||^2, sums
-      std::vector<BatchGemm> gB(na), gD(na);
-      std::vector<BatchSum> sB(na), sR(na);
-      for (int a = 0; a < na; ++a) {
-        Prob& p = P[act[a]];
-        qb_problem& q = probs[act[a]];
-        double* Qo = q.Q + p.k * q.ldq;
-        double* Bo = q.B + p.k;
-        gB[a] = gemm_desc(tile_of(QB_ROLE_B, p.w), Qo, q.ldq, p.R, p.ldr, Bo, q.ldb, p.w, p.n, p.m, 1.0, 0.0,
-                          p.sqB, p.part);
-        gD[a] = gemm_desc(tile_of(QB_ROLE_DOWNDATE, p.w), Qo, q.ldq, Bo, q.ldb, p.R, p.ldr, p.m, p.n, p.w, 1.0, 0.0,
-                          p.sqR, nullptr);
-        sB[a] = BatchSum{p.sqB, nullptr, p.scal + 2, nullptr, sq_count(gB[a])};
-        sR[a] = BatchSum{p.sqR, nullptr, p.scal + 0, nullptr, sq_count(gD[a])};
-      }
-
-
-      Step sY = group(gY), s1 = group(g1), sa1 = group(a1), s2 = group(g2), sa2 = group(a2);
-      Step srC = group(rC), srQ = group(rQ, true), s3 = group(g3), sa3 = group(a3),
-           s4 = group(g4), sa4 = group(a4);
-      Step sBB = group(gB), sDD = group(gD, true);
-      const size_t osk = sg.put(sk);
-      for (Step* x : {&sY, &s1, &sa1, &s2, &sa2}) x->off = sg.put(x->d);
-      const size_t oc1 = sg.put(c1);
-      size_t oc3 = 0;
-      if (nr) {
-        for (Step* x : {&srC, &srQ, &s3, &sa3, &s4, &sa4}) x->off = sg.put(x->d);
-        oc3 = sg.put(c3);
-      }
-      sBB.off = sg.put(sBB.d);
-      sDD.off = sg.put(sDD.d);
-      const size_t osB = sg.put(sB), osR = sg.put(sR);
-      if (sg.overflow) return QB_EWORKSPACE;
-      auto G = [&](size_t off) { return reinterpret_cast<const BatchGemm*>(dev(off)); };
-      auto Ch = [&](size_t off) { return reinterpret_cast<const BatchChol*>(dev(off)); };
-      int e = upload();
-      e = e || sketch_batched(reinterpret_cast<const BatchSketch*>(dev(osk)), na, skb, st);
-      auto mm = [&](int op, const Step& x, int pid) -> int {
+    }
+    constexpr int64_t kGridCap = 2048;  // workgroups of a launch; more units go round strides
+    auto capped = [](int64_t g) { return g < kGridCap ? g : kGridCap; };
+    Plan pl = L.plan;
+    const unsigned pgrid = static_cast<unsigned>(cdiv(count, 256));
+    // eager: per-launch algorithmic work for the profiler from the host copy
+    // of the state (read every iteration); graph: none
+    std::vector<DevState> hs;
+    auto issue = [&](hipStream_t cs, const DevState* hstate) -> int {
+      hipLaunchKernelGGL(batch_plan_kernel, dim3(kSteps + 1), dim3(kPlanThreads), 0, cs, L.dprob,
+                         L.dstate, count, tt, pl);
+      if (hipGetLastError() != hipSuccess) return 1;
+      if (sketch_batched(pl.sketch, count, capped(skgrid), cs, pl.sk_blocks)) return 1;
+      auto mm = [&](int sidx, int pid) -> int {
+        const int op = step_op(sidx);
         for (int c = 0; c < kTileClasses; ++c) {
-          const int cnt = x.begin[c + 1] - x.begin[c];
-          if (cnt == 0) continue;
-          if (gemm_batched(op, c, G(x.off) + x.begin[c], cnt, x.tiles[c], pid, x.flops[c],
-                           x.bytes[c], st))
+          if (grid[sidx][c] == 0) continue;
+          double fl = 0.0, by = 0.0;
+          if (hstate) {
+            for (int i = 0; i < count; ++i) {
+              if (!hstate[i].active) continue;
+              BatchGemm g;
+              const DevProb pr{P[i].R, P[i].omega, P[i].Y, P[i].Qt, P[i].Qi, P[i].C, P[i].G,
+                               P[i].Tinv, P[i].sqB, P[i].sqR, P[i].part, P[i].kept, P[i].scal,
+                               P[i].iflag, probs[i].Q, probs[i].B, P[i].m, P[i].n, P[i].kcap,
+                               P[i].ldr, P[i].ldm, P[i].ldc, probs[i].ldq, probs[i].ldb,
+                               probs[i].seed, probs[i].eps, P[i].b, 0};
+              if (!step_desc(sidx, pr, hstate[i].k, hstate[i].w, tt, &g) || g.cls != c) continue;
+              fl += 2.0 * g.M * g.N * g.K;
+              by += 8.0 * (double(g.M) * g.K + double(g.K) * g.N +
+                           double(g.M) * g.N * ((op == kBatchDD || sidx == kStRQ) ? 2.0 : 1.0));
+            }
+          }
+          const BatchGemm* d = pl.gemm + (static_cast<int64_t>(sidx) * kTileClasses + c) * count;
+          if (gemm_batched(op, c, d, count, capped(grid[sidx][c]), pid, fl, by, cs,
+                           pl.tiles + sidx * kTileClasses + c))
             return 1;
         }
-        return gemm_batched_reduce(op, G(x.off), x.count(), x.rblocks, pid, st) ? 1 : 0;
+        if (rgrid[sidx] == 0) return 0;
+        return gemm_batched_reduce(op, pl.gemm + static_cast<int64_t>(sidx) * kTileClasses * count,
+                                   kTileClasses * count, capped(rgrid[sidx]), pid, cs,
+                                   pl.rblocks + sidx)
+                   ? 1
+                   : 0;
       };
-      e = e || mm(kBatchNN, sY, kKBatchSample);
-      e = e || mm(kBatchTN, s1, kKBatchGram);
-      e = e || chol_inv_batched(Ch(oc1), na, st);
-      e = e || mm(kBatchNN, sa1, kKBatchApply);
-      e = e || mm(kBatchTN, s2, kKBatchGram);
-      e = e || chol_inv_batched(Ch(oc1), na, st);
-      e = e || mm(kBatchNN, sa2, kKBatchApply);
-      if (nr) {
-        e = e || mm(kBatchTN, srC, kKBatchReproj);
-        e = e || mm(kBatchNN, srQ, kKBatchReproj);
-        e = e || mm(kBatchTN, s3, kKBatchGram);
-        e = e || chol_inv_batched(Ch(oc3), nr, st);
-        e = e || mm(kBatchNN, sa3, kKBatchApply);
-        e = e || mm(kBatchTN, s4, kKBatchGram);
-        e = e || chol_inv_batched(Ch(oc3), nr, st);
-        e = e || mm(kBatchNN, sa4, kKBatchApply);
+      int e = 0;
+      e = e || mm(kStY, kKBatchSample);
+      e = e || mm(kStG1, kKBatchGram);
+      e = e || chol_inv_batched(pl.c1, count, cs);
+      e = e || mm(kStA1, kKBatchApply);
+      e = e || mm(kStG2, kKBatchGram);
+      e = e || chol_inv_batched(pl.c1, count, cs);
+      e = e || mm(kStA2, kKBatchApply);
+      e = e || mm(kStRC, kKBatchReproj);
+      e = e || mm(kStRQ, kKBatchReproj);
+      e = e || mm(kStG3, kKBatchGram);
+      e = e || chol_inv_batched(pl.c3, count, cs);
+      e = e || mm(kStA3, kKBatchApply);
+      e = e || mm(kStG4, kKBatchGram);
+      e = e || chol_inv_batched(pl.c3, count, cs);
+      e = e || mm(kStA4, kKBatchApply);
+      e = e || mm(kStB, kKBatchB);
+      e = e || mm(kStD, kKBatchDowndate);
+      e = e || sum_batched(pl.sB, count, cs);
+      e = e || sum_batched(pl.sR, count, cs);
+      if (e) return 1;
+      hipLaunchKernelGGL(batch_stop_kernel, dim3(pgrid), dim3(256), 0, cs, L.dprob, L.dstate,
+                         count, pl.any_active);
+      return hipGetLastError() != hipSuccess ? 1 : 0;
+    };
+    auto more = [&]() -> int {  // 1: a problem is still active, 0: none, -1: error
+      if (hipMemcpyAsync(hflag, pl.any_active, sizeof(int), hipMemcpyDeviceToHost, st) !=
+              hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess)
+        return -1;
+      return hflag[0] != 0 ? 1 : 0;
+    };
+
+    // ---- block iterations ----------------------------------------------
+    const bool eager = prof_enabled() || getenv("QB_BATCHED_EAGER") != nullptr;
+    if (eager) {
+      hs.resize(count);
+      for (;;) {
+        if (hipMemcpyAsync(hs.data(), L.dstate, count * sizeof(DevState), hipMemcpyDeviceToHost,
+                           st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+          return QB_EHIP;
+        if (issue(st, hs.data())) return QB_EHIP;
+        const int mo = more();
+        if (mo < 0) return QB_EHIP;
+        if (mo == 0) break;
       }
-      e = e || mm(kBatchTN, sBB, kKBatchB);
-      e = e || mm(kBatchDD, sDD, kKBatchDowndate);
-      e = e || sum_batched(reinterpret_cast<const BatchSum*>(dev(osB)), na, st);
-      e = e || sum_batched(reinterpret_cast<const BatchSum*>(dev(osR)), na, st);
-      e = e || fetch();
+    } else {
+      // kGraphIters iterations per graph; iterations after every problem
+      // has stopped find nothing to do (empty plans)
+      constexpr int kGraphIters = 8;
+      hipStream_t cs = nullptr;
+      hipGraph_t graph = nullptr;
+      hipGraphExec_t exec = nullptr;
+      int e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess;
+      if (!e) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess;
+      if (!e) {
+        for (int u = 0; u < kGraphIters && !e; ++u) e = issue(cs, nullptr);
+        const bool ended = hipStreamEndCapture(cs, &graph) == hipSuccess;
+        e = e || !ended;
+      }
+      if (!e) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess;
+      while (!e) {
+        if (hipGraphLaunch(exec, st) != hipSuccess) { e = 1; break; }
+        const int mo = more();
+        if (mo < 0) { e = 1; break; }
+        if (mo == 0) break;
+      }
+      if (exec) (void)hipGraphExecDestroy(exec);
+      if (graph) (void)hipGraphDestroy(graph);
+      if (cs) (void)hipStreamDestroy(cs);
       if (e) return QB_EHIP;
-      // the stopping rule of qb_factor, per problem
-      for (int a = 0; a < na; ++a) {
-        const int i = act[a];
-        Prob& p = P[i];
-        const int wkept = hkept[i * kKeptStride];
-        if (wkept <= 0) {
-          p.active = false;
-          p.reason = QB_STOP_EXHAUSTED;
-          continue;
-        }
-        p.k += wkept;
-        ++p.blocks;
-        p.sigB = dd_add(p.sigB, DD{hscal[i * kScal + 2], hscal[i * kScal + 3]});
-        const DD Edd = dd_add(p.sA, DD{-p.sigB.hi, -p.sigB.lo});
-        p.lastE = Edd.hi + Edd.lo;
-        p.lastD = hscal[i * kScal + 0] + hscal[i * kScal + 1];
-        if (p.lastE <= p.eps2 - p.delta) {
-          p.active = false;
-          p.reason = QB_STOP_TOL_TRACKED;
-        } else if (!(p.lastE > p.eps2 + p.delta) && p.lastD <= p.eps2) {
-          p.active = false;
-          p.reason = QB_STOP_TOL_DIRECT;
-        } else if (p.lastD <= p.floor2) {
-          p.active = false;
-          p.reason = QB_STOP_EXHAUSTED;
-        } else if (p.k >= p.kcap) {
-          p.active = false;
-          p.reason = p.kcap < std::min(p.m, p.n) ? QB_STOP_KMAX : QB_STOP_RANK_CAP;
-        }
-      }
     }
+
+    // ---- outputs ---------------------------------------------------------
+    hs.resize(count);
+    if (hipMemcpyAsync(hs.data(), L.dstate, count * sizeof(DevState), hipMemcpyDeviceToHost, st) !=
+            hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return QB_EHIP;
     for (int i = 0; i < count; ++i) {
       qb_problem& q = probs[i];
-      if (q.status != QB_OK) continue;
-      const Prob& p = P[i];
-      q.k = p.k;
-      q.blocks = p.blocks;
-      q.stop_reason = p.reason;
-      q.resid2 = p.lastD;
-      q.status = (p.reason == QB_STOP_ZERO || p.reason == QB_STOP_TOL_TRACKED ||
-                  p.reason == QB_STOP_TOL_DIRECT)
+      const DevState& d = hs[i];
+      q.k = d.k;
+      q.blocks = d.blocks;
+      q.stop_reason = d.reason;
+      q.normA2 = d.sA_hi + d.sA_lo;
+      q.resid2 = d.lastD;
+      if (d.status != QB_OK) {
+        q.status = d.status;
+        q.k = 0;
+        q.blocks = 0;
+        q.stop_reason = QB_STOP_ZERO;
+        continue;
+      }
+      q.status = (d.reason == QB_STOP_ZERO || d.reason == QB_STOP_TOL_TRACKED ||
+                  d.reason == QB_STOP_TOL_DIRECT)
                      ? QB_OK
-                     : (p.reason == QB_STOP_KMAX ? QB_KMAX : QB_RANK_EXHAUSTED);
+                     : (d.reason == QB_STOP_KMAX ? QB_KMAX : QB_RANK_EXHAUSTED);
     }
     return QB_OK;
   };

@@ -188,6 +188,17 @@ constexpr int kBatchTile = 64;      // the default (and downdate) tile of batche
 // of panels at most 32 wide (narrow N / narrow M)
 enum { kTile64 = 0, kTileG16, kTileG32, kTileN32, kTileM32, kTileClasses };
 void batch_tile_dims(int cls, int* bm, int* bn);
+// the same dimensions for device code (checked against the kernels' shapes
+// in k_gemm_batched.hip)
+__host__ __device__ inline void batch_tile_dims_hd(int cls, int* bm, int* bn) {
+  switch (cls) {
+    case kTileG16: *bm = 16; *bn = 16; return;
+    case kTileG32: *bm = 32; *bn = 32; return;
+    case kTileN32: *bm = 64; *bn = 32; return;
+    case kTileM32: *bm = 32; *bn = 64; return;
+    default: *bm = kBatchTile; *bn = kBatchTile; return;
+  }
+}
 constexpr int kBatchRed = 1024;     // elements per workgroup of the split-K reduction
 // prof_id, flops, bytes: the profiler entry and the launch's algorithmic
 // flops (sum of 2 M N K) and bytes (sum of 8 (M K + K N + M N), M N twice
@@ -196,10 +207,14 @@ constexpr int kBatchRed = 1024;     // elements per workgroup of the split-K red
 // ksplit > 1 leave C to gemm_batched_reduce, which sums their chunks in
 // order (alpha sum + beta C for NN, the sum for TN) with per-workgroup sums
 // of squares into sq when sq is set; total_rblocks counts its workgroups.
+// dev_total (optional): a device count of units that the launch's
+// total_tiles (or total_rblocks) workgroups walk in strides of the grid
+// instead of one unit each (the device-planned batch loop).
 int gemm_batched(int op, int cls, const BatchGemm* desc, int count, int64_t total_tiles,
-                 int prof_id, double flops, double bytes, hipStream_t s);
+                 int prof_id, double flops, double bytes, hipStream_t s,
+                 const int64_t* dev_total = nullptr);
 int gemm_batched_reduce(int op, const BatchGemm* desc, int count, int64_t total_rblocks,
-                        int prof_id, hipStream_t s);
+                        int prof_id, hipStream_t s, const int64_t* dev_total = nullptr);
 
 struct BatchChol {  // Cholesky with dropping + inverse of one w x w Gram matrix
   const double* G;
@@ -216,7 +231,8 @@ struct BatchSketch {  // columns [col0, col0 + w) of the n x inf sketch of seed
   int64_t block0;
   int32_t w;
 };
-int sketch_batched(const BatchSketch* desc, int count, int64_t total_blocks, hipStream_t s);
+int sketch_batched(const BatchSketch* desc, int count, int64_t total_blocks, hipStream_t s,
+                   const int64_t* dev_total = nullptr);
 int64_t sketch_blocks(int64_t n, int w);
 
 struct BatchConvert {  // R = double(A) (A float, m x n) with sums of squares and

@@ -151,3 +151,29 @@ def test_other_tile_classes_match_oracle(cuda):
         assert g.k == o.k and g.stop_reason == STOP_NAMES[o.stop_reason]
         Q, B = g.Q.cpu().numpy(), g.B.cpu().numpy()
         assert np.linalg.norm(Q @ B - o.Q @ o.B) <= 1e-10 * math.sqrt(g.normA2)
+
+
+def test_graph_replays_match_eager(cuda, monkeypatch):
+    """The block loop runs as replays of a captured HIP graph (eight
+    iterations per replay, the host reading one flag in between).  The same
+    launches run eagerly, one iteration at a time, when QB_BATCHED_EAGER is
+    set.  Both give bitwise the same factors, also when the batch needs
+    many replays (b = 16 problems with k up to a few hundred) and when the
+    call is repeated after eager work in between."""
+    specs = synth.batch_specs(count=12, seed=4041, m_range=(200, 1200), n_max=600)
+    mats = [dev32(synth.batch_matrix(sp)) for sp in specs]
+    eps = [1e-6 * float(torch.linalg.norm(A, dtype=torch.float64)) for A in mats]
+    bs = [16] * len(specs)
+    seeds = [sp.seed_omega for sp in specs]
+    g1 = qbmi.qb_factor_batched(mats, eps, bs, seeds)
+    monkeypatch.setenv("QB_BATCHED_EAGER", "1")
+    e1 = qbmi.qb_factor_batched(mats, eps, bs, seeds)
+    monkeypatch.delenv("QB_BATCHED_EAGER")
+    torch.cuda.synchronize()
+    g2 = qbmi.qb_factor_batched(mats, eps, bs, seeds)
+    print(f"[case] iterations {max(r.blocks for r in g1)}", flush=True)
+    assert max(r.blocks for r in g1) > 16  # several graph replays
+    for a, b_, c in zip(g1, e1, g2):
+        assert a.k == b_.k == c.k and a.stop_reason == b_.stop_reason == c.stop_reason
+        assert torch.equal(a.Q, b_.Q) and torch.equal(a.B, b_.B)
+        assert torch.equal(a.Q, c.Q) and torch.equal(a.B, c.B)
