@@ -327,10 +327,11 @@ size_t qb_factor_batched_workspace_bytes(const qb_problem* probs, int32_t count)
  * problem is invalid (nothing runs), QB_EWORKSPACE or QB_EHIP.  Each
  * problem's stop decision is taken on the device; eight block iterations
  * at a time run as one HIP graph launch on `stream`, after which the call
- * reads one flag (any problem still active), so it synchronises the stream
- * once per eight iterations and returns with the stream idle.  It keeps a
- * pinned host staging buffer per calling thread, grown to the largest
- * batch seen, for the problem records. */
+ * reads the problems' state (which are still active) and, once they need
+ * much smaller launches, captures the graph again for them.  It thus
+ * synchronises the stream once per eight iterations and returns with the
+ * stream idle.  It keeps a pinned host staging buffer per calling thread,
+ * grown to the largest batch seen, for the problem records. */
 int qb_factor_batched(qb_problem* probs, int32_t count, void* workspace, size_t ws_bytes,
                       void* stream);
 

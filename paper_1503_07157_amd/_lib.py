@@ -12,6 +12,9 @@ import threading
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libqbmi.so")
+# The host-AddressSanitizer build of the same sources (build.py --asan), for
+# the CPU checks of the argument paths; QB_LIBRARY selects it.
+ASAN_LIB_PATH = os.path.join(HERE, "libqbmi_asan.so")
 
 c_i64 = ctypes.c_int64
 c_i32 = ctypes.c_int32
@@ -136,12 +139,15 @@ _lock = threading.Lock()
 _lib = None
 
 
-def load(path: str = LIB_PATH) -> ctypes.CDLL:
-    """Load libqbmi.so and attach signatures; raises if it is not built."""
+def load(path: str | None = None) -> ctypes.CDLL:
+    """Load libqbmi.so (or the library QB_LIBRARY names) and attach
+    signatures; raises if it is not built."""
     global _lib
     with _lock:
         if _lib is not None:
             return _lib
+        if path is None:
+            path = os.environ.get("QB_LIBRARY") or LIB_PATH
         if not os.path.exists(path):
             raise RuntimeError(
                 f"{path} is not built; run `python -m paper_1503_07157_amd.build` "

@@ -517,6 +517,11 @@ int gemm_tn(const double* Qm, int64_t ldq, const double* X, int64_t ldx, double*
   // that return per-tile sums of squares keep the 128 x 128 tiles the
   // partial-sum buffers are sized for.
   const bool small = P * N <= int64_t(256) * 256 && (sq_part == nullptr || nz > 1);
+  // A panel of 129..256 columns (b = 256) takes 256-row tiles, so the long
+  // operand X is read once per column tile instead of once per 128-row tile
+  // row (counters at 20000 x 16000: 2.3x the algorithmic bytes with two
+  // tile rows)
+  const bool tall = !small && P > kTileM && P <= Tall::BM;
   dim3 grid;
   {
     ProfScope ps(small ? kKGemmTNSmall : kKGemmTN, 2.0 * P * N * K, 8.0 * (K * P + K * N + P * N), s);
@@ -524,8 +529,10 @@ int gemm_tn(const double* Qm, int64_t ldq, const double* X, int64_t ldx, double*
     double* sqp = nz > 1 ? static_cast<double*>(nullptr) : sq_part;
     grid = small ? launch_tn<Small>(Qm, ldq, X, ldx, C, ldc, P, N, K, kc, nz, transpose_out, pp,
                                     ldp, sqp, s)
-                 : launch_tn<Big>(Qm, ldq, X, ldx, C, ldc, P, N, K, kc, nz, transpose_out, pp,
-                                  ldp, sqp, s);
+           : tall ? launch_tn<Tall>(Qm, ldq, X, ldx, C, ldc, P, N, K, kc, nz, transpose_out, pp,
+                                    ldp, sqp, s)
+                  : launch_tn<Big>(Qm, ldq, X, ldx, C, ldc, P, N, K, kc, nz, transpose_out, pp,
+                                   ldp, sqp, s);
   }
   QB_HIP_TRY(hipGetLastError());
   if (nz > 1) {

@@ -119,21 +119,38 @@ __device__ __forceinline__ void batched_tile(const BatchGemm* __restrict__ desc,
 // total); else the device count of such units, which a grid of any size
 // walks in strides of the grid (the device-planned batch loop, whose
 // launches keep one grid while the work shrinks)
+// Units of a launch whose count is known only on the device: workgroup g
+// takes unit g first, then further units gridDim.x + (launch counter)++ one
+// at a time, so the long units do not pile up on a few workgroups, and a
+// workgroup with nothing to do (the tail of the batch) exits without
+// touching the counter.  Thread 0 takes the unit, the workgroup reads it
+// from LDS.
+__device__ __forceinline__ int64_t grab_unit(unsigned long long* next, int64_t* slot) {
+  if (threadIdx.x == 0)
+    *slot = static_cast<int64_t>(gridDim.x) + static_cast<int64_t>(atomicAdd(next, 1ull));
+  __syncthreads();
+  const int64_t u = *slot;
+  __syncthreads();
+  return u;
+}
+
 template <class S, int OP>
 __global__ __launch_bounds__(S::NT, S::OCC) void gemm_batched_kernel(
-    const BatchGemm* __restrict__ desc, int count, const int64_t* __restrict__ total) {
+    const BatchGemm* __restrict__ desc, int count, const int64_t* __restrict__ total,
+    unsigned long long* __restrict__ next) {
   __shared__ __attribute__((aligned(16))) double As[2 * S::A_LDS];
   __shared__ __attribute__((aligned(16))) double Bs[2 * S::B_LDS];
   __shared__ double red[S::NT / 64];
+  __shared__ int64_t slot;
   if (total == nullptr) {
     batched_tile<S, OP>(desc, count, blockIdx.x, As, Bs, red);
     return;
   }
+  // units of very different depth: taken one at a time from a counter, so
+  // the long ones do not pile up on a few workgroups
   const int64_t n = *total;
-  for (int64_t blk = blockIdx.x; blk < n; blk += gridDim.x) {
+  for (int64_t blk = blockIdx.x; blk < n; blk = grab_unit(next, &slot))
     batched_tile<S, OP>(desc, count, blk, As, Bs, red);
-    __syncthreads();
-  }
 }
 
 // C from the depth chunks of the problems with ksplit > 1, in chunk order;
@@ -175,17 +192,17 @@ __device__ __forceinline__ void batched_reduce_unit(const BatchGemm* __restrict_
 
 template <int OP>
 __global__ __launch_bounds__(256) void gemm_batched_reduce_kernel(
-    const BatchGemm* __restrict__ desc, int count, const int64_t* __restrict__ total) {
+    const BatchGemm* __restrict__ desc, int count, const int64_t* __restrict__ total,
+    unsigned long long* __restrict__ next) {
   __shared__ double red[4];
+  __shared__ int64_t slot;
   if (total == nullptr) {
     batched_reduce_unit<OP>(desc, count, blockIdx.x, red);
     return;
   }
   const int64_t n = *total;
-  for (int64_t blk = blockIdx.x; blk < n; blk += gridDim.x) {
+  for (int64_t blk = blockIdx.x; blk < n; blk = grab_unit(next, &slot))
     batched_reduce_unit<OP>(desc, count, blk, red);
-    __syncthreads();
-  }
 }
 
 }  // namespace
@@ -193,17 +210,17 @@ __global__ __launch_bounds__(256) void gemm_batched_reduce_kernel(
 namespace {
 template <class S>
 void launch_batched(int op, const BatchGemm* desc, int count, int64_t grid_size,
-                    const int64_t* total, hipStream_t s) {
+                    const int64_t* total, unsigned long long* next, hipStream_t s) {
   const dim3 grid(static_cast<unsigned>(grid_size));
   if (op == kBatchNN)
     hipLaunchKernelGGL((gemm_batched_kernel<S, kBatchNN>), grid, dim3(S::NT), 0, s, desc, count,
-                       total);
+                       total, next);
   else if (op == kBatchTN)
     hipLaunchKernelGGL((gemm_batched_kernel<S, kBatchTN>), grid, dim3(S::NT), 0, s, desc, count,
-                       total);
+                       total, next);
   else
     hipLaunchKernelGGL((gemm_batched_kernel<S, kBatchDD>), grid, dim3(S::NT), 0, s, desc, count,
-                       total);
+                       total, next);
 }
 }  // namespace
 
@@ -225,24 +242,25 @@ void batch_tile_dims(int cls, int* bm, int* bn) {
 
 int gemm_batched(int op, int cls, const BatchGemm* desc, int count, int64_t total_tiles,
                  int prof_id, double flops, double bytes, hipStream_t s,
-                 const int64_t* dev_total) {
+                 const int64_t* dev_total, unsigned long long* dev_next) {
   if (count <= 0 || total_tiles <= 0) return kOk;
   if (op == kBatchDD && cls == kTileG16) return kEInval;
   if (total_tiles > INT32_MAX) return kEInval;  // one-dimensional grid
   ProfScope ps(prof_id, flops, bytes, s);
   switch (cls) {
-    case kTileG16: launch_batched<BatchG16>(op, desc, count, total_tiles, dev_total, s); break;
-    case kTileG32: launch_batched<BatchG32>(op, desc, count, total_tiles, dev_total, s); break;
-    case kTileN32: launch_batched<BatchN32>(op, desc, count, total_tiles, dev_total, s); break;
-    case kTileM32: launch_batched<BatchM32>(op, desc, count, total_tiles, dev_total, s); break;
-    default: launch_batched<Small>(op, desc, count, total_tiles, dev_total, s); break;
+    case kTileG16: launch_batched<BatchG16>(op, desc, count, total_tiles, dev_total, dev_next, s); break;
+    case kTileG32: launch_batched<BatchG32>(op, desc, count, total_tiles, dev_total, dev_next, s); break;
+    case kTileN32: launch_batched<BatchN32>(op, desc, count, total_tiles, dev_total, dev_next, s); break;
+    case kTileM32: launch_batched<BatchM32>(op, desc, count, total_tiles, dev_total, dev_next, s); break;
+    default: launch_batched<Small>(op, desc, count, total_tiles, dev_total, dev_next, s); break;
   }
   QB_HIP_TRY(hipGetLastError());
   return kOk;
 }
 
 int gemm_batched_reduce(int op, const BatchGemm* desc, int count, int64_t total_rblocks,
-                        int prof_id, hipStream_t s, const int64_t* dev_total) {
+                        int prof_id, hipStream_t s, const int64_t* dev_total,
+                        unsigned long long* dev_next) {
   if (count <= 0 || total_rblocks <= 0) return kOk;
   if (total_rblocks > INT32_MAX) return kEInval;
   if (op == kBatchDD) return kEInval;
@@ -250,10 +268,10 @@ int gemm_batched_reduce(int op, const BatchGemm* desc, int count, int64_t total_
   ProfScope ps(prof_id, 0.0, 0.0, s);
   if (op == kBatchNN)
     hipLaunchKernelGGL(gemm_batched_reduce_kernel<kBatchNN>, grid, dim3(256), 0, s, desc, count,
-                       dev_total);
+                       dev_total, dev_next);
   else
     hipLaunchKernelGGL(gemm_batched_reduce_kernel<kBatchTN>, grid, dim3(256), 0, s, desc, count,
-                       dev_total);
+                       dev_total, dev_next);
   QB_HIP_TRY(hipGetLastError());
   return kOk;
 }

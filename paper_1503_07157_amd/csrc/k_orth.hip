@@ -15,12 +15,16 @@
 // reciprocal square root computed while the current column's updates
 // issue; the trailing update G22 -= L21 L21^T runs on
 // v_mfma_f64_16x16x4_f64 over the other waves while wave 0 factors the
-// next panel (look-ahead).  Wider panels (up to 256) keep the lower
-// triangle in registers with a rank-one update per column.
+// next panel (look-ahead).  Wider panels (129..256) are blocked 128 +
+// (w - 128): the LDS factorisation of the leading block, the Schur
+// complement of the trailing block by two small MFMA products, the LDS
+// factorisation of that, and the off-diagonal block of the inverse by two
+// more products (chol_inv_wide), all with the scale and drop threshold of
+// the whole Gram matrix.
 //
 // Inverse: T^{-1} of the kept part, blocked in LDS (16 x 16 diagonal blocks
-// by substitution, joined pairwise with MFMA products) for panels up to 128;
-// one wave per output column by back substitution for wider panels.
+// by substitution, joined pairwise with MFMA products) for blocks up to 128.
+#include <algorithm>
 #include <utility>
 
 #include "qb_internal.hpp"
@@ -30,17 +34,6 @@ namespace {
 
 constexpr double kDropRel = 0x1p-40;
 
-// WMAX: widest panel handled; NW: waves (must divide 64).  A thread holds
-// the lower-triangle entries of its (row slot, column slot) pairs.
-template <int WMAX, int NW_>
-struct CholShape {
-  static constexpr int NW = NW_;          // waves
-  static constexpr int RA = WMAX / 64;    // row slots per lane
-  static constexpr int CB = WMAX / NW_;   // column slots per wave
-  static constexpr int THREADS = 64 * NW_;
-  static constexpr bool valid(int a, int bb) { return 64 * a + 63 >= NW * bb; }
-};
-
 // compile-time loop: f(std::integral_constant<int, I>) for I = 0 .. N-1
 template <class F, int... I>
 __device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
@@ -49,107 +42,6 @@ __device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int
 template <int N, class F>
 __device__ __forceinline__ void static_for(F&& f) {
   static_for_impl(f, std::make_integer_sequence<int, N>{});
-}
-
-// Right-looking Cholesky with dropping on the register-resident lower
-// triangle of G (w x w, column-major, ld w).  emit(c, i, v) receives entry
-// T[c][i] for every i < w once column c is final (zero for i < c and for a
-// dropped column); flag[c] (LDS) is 1 for kept columns.  Leaves the kept
-// count and list in kcnt / klist (LDS) when done.
-template <int WMAX, int NW_, class Emit>
-__device__ __forceinline__ void chol_drop_core(const double* __restrict__ G, int w,
-                                               double (*lbuf)[WMAX], double* dsh, int* flag,
-                                               int* klist, int* kcnt, Emit&& emit) {
-  using S = CholShape<WMAX, NW_>;
-  constexpr int NW = S::NW, RA = S::RA, CB = S::CB;
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-
-  double g[RA][CB];
-  static_for<RA>([&](auto a) {
-    static_for<CB>([&](auto bb) {
-      if constexpr (S::valid(a, bb)) {
-        const int i = lane + 64 * a, j = wave + NW * bb;
-        g[a][bb] = (i < w && j < w && i >= j) ? G[i + static_cast<int64_t>(j) * w] : 0.0;
-        if (i == j && i < w) dsh[i] = g[a][bb];
-      }
-    });
-  });
-  lds_barrier();
-  double gmax = 0.0;
-  for (int c = 0; c < w; ++c) gmax = fmax(gmax, dsh[c]);
-  const double thresh = kDropRel * gmax;
-
-  static_for<CB>([&](auto cb) {
-    constexpr int ac = (NW * cb) / 64;  // row slot holding the diagonal of this column slot
-    for (int W = 0; W < NW; ++W) {
-      const int c = W + NW * cb;
-      if (c >= w) break;
-      double* buf = lbuf[c & 1];
-      if (wave == W) {
-        double gd = 0.0;
-        if constexpr (S::valid(ac, cb)) gd = g[ac][cb];
-        const double d = __shfl(gd, c & 63);
-        const bool keep = (d > thresh) && (gmax > 0.0);
-        const double sdiag = keep ? sqrt(d) : 0.0;
-        const double inv = keep ? 1.0 / sdiag : 0.0;
-        static_for<RA>([&](auto a) {
-          const int i = lane + 64 * a;
-          double v = 0.0;
-          if constexpr (S::valid(a, cb)) v = (i > c) ? g[a][cb] * inv : 0.0;
-          if (i == c) v = sdiag;
-          buf[i] = v;
-          if (i < w) emit(c, i, (i >= c) ? v : 0.0);
-        });
-        if (lane == 0) flag[c] = keep ? 1 : 0;
-      }
-      lds_barrier();
-      // rank-one update of the trailing entries held here; the LDS reads are
-      // issued in groups without branches so their latencies overlap
-      double rv[RA];
-      static_for<RA>([&](auto a) { rv[a] = buf[lane + 64 * a]; });
-      constexpr int GS = (CB >= 32) ? 4 : 8;  // reads in flight per group
-      static_for<CB / GS>([&](auto grp) {
-        double cv[GS];
-        static_for<GS>([&](auto q) { cv[q] = buf[wave + NW * (GS * grp + q)]; });
-        static_for<GS>([&](auto q) {
-          constexpr int bb = GS * grp + q;
-          const int j = wave + NW * bb;
-          static_for<RA>([&](auto a) {
-            if constexpr (S::valid(a, bb)) {
-              const int i = lane + 64 * a;
-              const double upd = (j > c && i >= j) ? rv[a] * cv[q] : 0.0;
-              g[a][bb] -= upd;
-            }
-          });
-        });
-      });
-    }
-  });
-  lds_barrier();
-  if (threadIdx.x == 0) {
-    int cnt = 0;
-    for (int c = 0; c < w; ++c)
-      if (flag[c]) klist[cnt++] = c;
-    *kcnt = cnt;
-  }
-  lds_barrier();
-}
-
-// Cholesky with dropping writing T (w x w, column-major) and the kept list
-// to global memory; used with trinv_kernel for panels wider than 128.
-template <int WMAX, int NW_>
-__global__ __launch_bounds__(64 * NW_) void chol_drop_kernel(
-    const double* __restrict__ G, int w, double* __restrict__ T, int* __restrict__ kept) {
-  __shared__ double lbuf[2][WMAX];
-  __shared__ double dsh[WMAX];
-  __shared__ int flag[WMAX];
-  __shared__ int klist[WMAX];
-  __shared__ int kcnt;
-  chol_drop_core<WMAX, NW_>(G, w, lbuf, dsh, flag, klist, &kcnt,
-                            [&](int c, int i, double v) { T[c + static_cast<int64_t>(i) * w] = v; });
-  for (int i = threadIdx.x; i < kcnt; i += blockDim.x) kept[1 + i] = klist[i];
-  if (threadIdx.x == 0) kept[0] = kcnt;
 }
 
 // value of v in lane l (l uniform)
@@ -331,12 +223,19 @@ __device__ __forceinline__ void tri_index(int job, int& bi, int& bj) {
 // of two scaling is exact and leaves every pivot test unchanged, and it
 // keeps every kept pivot inside the range of the hardware reciprocal square
 // root estimate.
+// ldg: leading dimension of G.  Gd (wd x wd, ld wd): the matrix whose
+// largest diagonal entry fixes the power-of-two scale and the drop
+// threshold; G itself for a whole Gram matrix, the whole Gram matrix when G
+// is one of its diagonal blocks or a Schur complement (so every block is
+// scaled and tested as the unblocked factorisation would be).
 template <int WMAX, int NW>
-__device__ __forceinline__ void chol_blocked(const double* __restrict__ G, int w, double* Ts,
+__device__ __forceinline__ void chol_blocked(const double* __restrict__ G, int w, int ldg,
+                                             const double* __restrict__ Gd, int wd, double* Ts,
                                              int* flag, double* rdiag, int* klist, int* kcnt,
                                              int* ulist, int* ucnt, int& sexp) {
   constexpr int TS = WMAX + 1;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double gscaled = 0.0;
   // lower triangle of G into Ts, everything else zero; every load of a
   // thread is issued before the first store.  Each wave also reads the
   // diagonal to find the scale.
@@ -347,10 +246,10 @@ __device__ __forceinline__ void chol_blocked(const double* __restrict__ G, int w
     for (int q = 0; q < PER; ++q) {
       const int idx = threadIdx.x + 64 * NW * q;
       const int i = idx % WMAX, j = idx / WMAX;
-      v[q] = (i < w && j < w && i >= j) ? G[i + static_cast<int64_t>(j) * w] : 0.0;
+      v[q] = (i < w && j < w && i >= j) ? G[i + static_cast<int64_t>(j) * ldg] : 0.0;
     }
     double gd = 0.0;
-    for (int c = lane; c < w; c += 64) gd = fmax(gd, G[c + static_cast<int64_t>(c) * w]);
+    for (int c = lane; c < wd; c += 64) gd = fmax(gd, Gd[c + static_cast<int64_t>(c) * wd]);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) gd = fmax(gd, __shfl_xor(gd, off));
     int ex = 0;
@@ -361,14 +260,10 @@ __device__ __forceinline__ void chol_blocked(const double* __restrict__ G, int w
       const int idx = threadIdx.x + 64 * NW * q;
       Ts[(idx / WMAX) * TS + idx % WMAX] = ldexp(v[q], 2 * sexp);
     }
+    gscaled = ldexp(gd, 2 * sexp);  // exact: the largest scaled diagonal entry
   }
   lds_barrier();
-  double gmax = 0.0;
-  if (wave == 0) {
-    for (int c = lane; c < w; c += 64) gmax = fmax(gmax, Ts[c * TS + c]);
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) gmax = fmax(gmax, __shfl_xor(gmax, off));
-  }
+  const double gmax = gscaled;
   const double thresh = kDropRel * gmax;
   auto panel = [&](int p) {
     if (WMAX > 64 && p + 64 < WMAX)
@@ -475,9 +370,10 @@ __device__ __forceinline__ void lds_block16(double* M, int ra, int ka, int kb, i
 }
 
 template <int WMAX>
-__device__ __forceinline__ void chol_inv_lds_body(const double* __restrict__ G, int w,
+__device__ __forceinline__ void chol_inv_lds_body(const double* __restrict__ G, int w, int ldg,
+                                                  const double* __restrict__ Gd, int wd,
                                                   int* __restrict__ kept,
-                                                  double* __restrict__ Tinv) {
+                                                  double* __restrict__ Tinv, int ldt) {
   using L = LdsInvShape<WMAX>;
   constexpr int TS = L::TS, NW = L::NW;
   __shared__ double Ts[WMAX * TS];
@@ -489,7 +385,7 @@ __device__ __forceinline__ void chol_inv_lds_body(const double* __restrict__ G, 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 
   int sexp;
-  chol_blocked<WMAX, NW>(G, w, Ts, flag, rdiag, klist, &kcnt, ulist, &ucnt, sexp);
+  chol_blocked<WMAX, NW>(G, w, ldg, Gd, wd, Ts, flag, rdiag, klist, &kcnt, ulist, &ucnt, sexp);
   // T' = T with every dropped or padding index u turned into a unit row and
   // column (its inverse restricted to the kept indices is T_kept^{-1})
   const int nu = ucnt;
@@ -564,7 +460,7 @@ __device__ __forceinline__ void chol_inv_lds_body(const double* __restrict__ G, 
   // scale of G), zero for a >= count
   const int wk = kcnt;
   for (int a = wave; a < w; a += NW) {
-    double* col = Tinv + static_cast<int64_t>(a) * w;
+    double* col = Tinv + static_cast<int64_t>(a) * ldt;
     if (a < wk) {
       const int kc = klist[a];
       for (int r = lane; r < w; r += 64) col[r] = ldexp(Ts[r * TS + kc], sexp);
@@ -580,7 +476,16 @@ template <int WMAX>
 __global__ __launch_bounds__(512) void chol_inv_lds_kernel(const double* __restrict__ G, int w,
                                                            int* __restrict__ kept,
                                                            double* __restrict__ Tinv) {
-  chol_inv_lds_body<WMAX>(G, w, kept, Tinv);
+  chol_inv_lds_body<WMAX>(G, w, w, G, w, kept, Tinv, w);
+}
+
+// one diagonal block (or Schur complement) of a wider Gram matrix Gd
+template <int WMAX>
+__global__ __launch_bounds__(512) void chol_inv_block_kernel(const double* __restrict__ G, int w,
+                                                             int ldg, const double* __restrict__ Gd,
+                                                             int wd, int* __restrict__ kept,
+                                                             double* __restrict__ Tinv, int ldt) {
+  chol_inv_lds_body<WMAX>(G, w, ldg, Gd, wd, kept, Tinv, ldt);
 }
 
 // one workgroup per problem of a batch
@@ -588,65 +493,7 @@ template <int WMAX>
 __global__ __launch_bounds__(512) void chol_inv_batched_kernel(const BatchChol* __restrict__ desc) {
   const BatchChol c = desc[blockIdx.x];
   if (c.w <= 0) return;  // a problem that takes no part in this step
-  chol_inv_lds_body<WMAX>(c.G, c.w, c.kept, c.Tinv);
-}
-
-// Column `a` of the inverse of the kept part Tc = T[kept][:, kept]; written
-// into Tinv (w x w) at rows kept[i], zero elsewhere and for a >= count.
-template <int WMAX>
-__global__ __launch_bounds__(64) void trinv_kernel(const double* __restrict__ T, int w,
-                                                   const int* __restrict__ kept,
-                                                   double* __restrict__ Tinv) {
-  constexpr int RA = WMAX / 64;
-  __shared__ int kidx[WMAX];
-  const int a = blockIdx.x;
-  const int lane = threadIdx.x;
-  const int wk = kept[0];
-  double* out = Tinv + static_cast<int64_t>(a) * w;
-  for (int i = lane; i < w; i += 64) out[i] = 0.0;
-  if (a >= wk) return;
-  for (int i = lane; i < wk; i += 64) kidx[i] = kept[1 + i];
-  __syncthreads();
-  double s[RA];
-  int64_t rowoff[RA];
-#pragma unroll
-  for (int q = 0; q < RA; ++q) {
-    const int i = lane + 64 * q;
-    s[q] = (i == a) ? 1.0 : 0.0;
-    rowoff[q] = (i < wk) ? kidx[i] : 0;
-  }
-  int kl = kidx[a];
-  double tcol[RA];
-#pragma unroll
-  for (int q = 0; q < RA; ++q) tcol[q] = T[rowoff[q] + static_cast<int64_t>(kl) * w];
-  for (int l = a; l >= 0; --l) {
-    // prefetch the next column while this one is applied
-    double tnext[RA];
-    const int kn = (l > 0) ? kidx[l - 1] : kl;
-#pragma unroll
-    for (int q = 0; q < RA; ++q) tnext[q] = T[rowoff[q] + static_cast<int64_t>(kn) * w];
-    double own = 0.0, tll = 0.0;
-#pragma unroll
-    for (int q = 0; q < RA; ++q)
-      if (q == (l >> 6)) { own = s[q]; tll = tcol[q]; }
-    const double sl = __shfl(own, l & 63);
-    const double dl = __shfl(tll, l & 63);
-    const double xl = sl / dl;
-#pragma unroll
-    for (int q = 0; q < RA; ++q) {
-      const int i = lane + 64 * q;
-      if (i < l) s[q] -= tcol[q] * xl;
-      if (i == l) s[q] = xl;
-    }
-#pragma unroll
-    for (int q = 0; q < RA; ++q) tcol[q] = tnext[q];
-    kl = kn;
-  }
-#pragma unroll
-  for (int q = 0; q < RA; ++q) {
-    const int i = lane + 64 * q;
-    if (i <= a) out[rowoff[q]] = s[q];
-  }
+  chol_inv_lds_body<WMAX>(c.G, c.w, c.w, c.G, c.w, c.kept, c.Tinv, c.w);
 }
 
 template <int WMAX>
@@ -658,20 +505,92 @@ int launch_chol_inv_lds(const double* G, int w, int* kept, double* Tinv, hipStre
   return kOk;
 }
 
-template <int WMAX, int NW>
-int launch_chol_inv(const double* G, int w, double* T, int* kept, double* Tinv, hipStream_t s) {
-  const double w3 = double(w) * w * w / 3.0, w2b = 16.0 * w * w;
+// S = G22 - M (w2 x w2): the Schur complement of the leading 128 x 128
+// block, G22 the trailing block of G (ld ldg), M = T12^T T12 (ld w2)
+__global__ __launch_bounds__(256) void schur_kernel(const double* __restrict__ G, int ldg, int h,
+                                                    int w2, const double* __restrict__ M,
+                                                    double* __restrict__ S) {
+  const int idx = blockIdx.x * 256 + threadIdx.x;
+  if (idx >= w2 * w2) return;
+  const int i = idx % w2, j = idx / w2;
+  S[idx] = G[(h + i) + static_cast<int64_t>(h + j) * ldg] - M[idx];
+}
+
+// Assemble T^{-1} (w x w, kept columns first) from the two blocks:
+// columns [0, k1): the first block's inverse in rows [0, h), zero below;
+// columns [k1, k1 + k2): U (rows [0, h)) over the second block's inverse
+// (rows [h, w)); zero after.  Merges the kept lists (second block offset by
+// h).  One workgroup per output column c (w of them); the first also
+// writes the kept list.
+__global__ __launch_bounds__(256) void chol_join_kernel(int w, int h, const int* __restrict__ kept1,
+                                                        const int* __restrict__ kept2,
+                                                        const double* __restrict__ U,
+                                                        const double* __restrict__ T22inv,
+                                                        double* __restrict__ Tinv,
+                                                        int* __restrict__ kept) {
+  const int k1 = kept1[0], k2 = kept2[0], w2 = w - h;
+  const int c = blockIdx.x;
+  double* col = Tinv + static_cast<int64_t>(c) * w;
+  if (c < k1) {
+    for (int r = h + threadIdx.x; r < w; r += 256) col[r] = 0.0;
+  } else {
+    const int a = c - k1;
+    for (int r = threadIdx.x; r < w; r += 256)
+      col[r] = a >= k2 ? 0.0 : (r < h ? U[r + a * h] : T22inv[(r - h) + a * w2]);
+  }
+  if (c == 0) {
+    for (int i = threadIdx.x; i < k1 + k2; i += 256)
+      kept[1 + i] = i < k1 ? kept1[1 + i] : h + kept2[1 + (i - k1)];
+    if (threadIdx.x == 0) kept[0] = k1 + k2;
+  }
+}
+
+// Panels of 129..256 columns, blocked 128 + (w - 128) (G = T^T T, T upper):
+//   T11 from the LDS kernel on G11 (T11^{-1} into Tinv's leading block),
+//   T12 = T11^{-T} G12,  S = G22 - T12^T T12,  T22 from the LDS kernel on S,
+//   upper-right block of T^{-1}:  U = -T11^{-1} (T12 T22^{-1}),
+// with the power-of-two scale and the drop threshold of the whole G in both
+// factorisations: the pivots of S are those the unblocked factorisation
+// meets for columns 128.., so the same columns are kept.  scratch: 6 h^2
+// doubles and 2 (h + 1) ints after them.
+int chol_inv_wide(const double* G, int w, double* scratch, int* kept, double* Tinv,
+                  hipStream_t s) {
+  constexpr int h = 128;
+  const int w2 = w - h;
+  double* T12 = scratch;            // h x w2, ld h
+  double* M = T12 + h * h;          // w2 x w2
+  double* S = M + h * h;            // w2 x w2
+  double* T22inv = S + h * h;       // w2 x w2
+  double* W = T22inv + h * h;       // h x w2
+  double* U = W + h * h;            // h x w2
+  int* kept1 = reinterpret_cast<int*>(U + h * h);
+  int* kept2 = kept1 + h + 1;
   {
-    ProfScope ps(kKChol, w3, w2b, s);
-    hipLaunchKernelGGL((chol_drop_kernel<WMAX, NW>), dim3(1), dim3(CholShape<WMAX, NW>::THREADS),
-                       0, s, G, w, T, kept);
+    ProfScope ps(kKChol, 2.0 * double(w) * w * w / 3.0, 16.0 * w * w, s);
+    hipLaunchKernelGGL(chol_inv_block_kernel<128>, dim3(1), dim3(LdsInvShape<128>::THREADS), 0, s,
+                       G, h, w, G, w, kept1, Tinv, w);
   }
   QB_HIP_TRY(hipGetLastError());
+  int rc = gemm_tn(Tinv, w, G + static_cast<int64_t>(h) * w, w, T12, h, h, w2, h, false, 1,
+                   nullptr, nullptr, nullptr, s);
+  if (rc) return rc;
+  rc = gemm_tn(T12, h, T12, h, M, w2, w2, w2, h, false, 1, nullptr, nullptr, nullptr, s);
+  if (rc) return rc;
+  hipLaunchKernelGGL(schur_kernel, dim3(static_cast<unsigned>((w2 * w2 + 255) / 256)), dim3(256),
+                     0, s, G, w, h, w2, M, S);
+  QB_HIP_TRY(hipGetLastError());
   {
-    ProfScope ps(kKTrinv, w3, w2b, s);
-    hipLaunchKernelGGL(trinv_kernel<WMAX>, dim3(static_cast<unsigned>(w)), dim3(64), 0, s, T, w,
-                       kept, Tinv);
+    ProfScope ps(kKChol, 0.0, 0.0, s);
+    hipLaunchKernelGGL(chol_inv_block_kernel<128>, dim3(1), dim3(LdsInvShape<128>::THREADS), 0, s,
+                       S, w2, w2, G, w, kept2, T22inv, w2);
   }
+  QB_HIP_TRY(hipGetLastError());
+  rc = gemm_nn(T12, h, T22inv, w2, W, h, h, w2, w2, 1.0, 0.0, 1, nullptr, s);
+  if (rc) return rc;
+  rc = gemm_nn(Tinv, w, W, h, U, h, h, w2, h, -1.0, 0.0, 1, nullptr, s);
+  if (rc) return rc;
+  hipLaunchKernelGGL(chol_join_kernel, dim3(static_cast<unsigned>(w)), dim3(256), 0, s, w, h,
+                     kept1, kept2, U, T22inv, Tinv, kept);
   QB_HIP_TRY(hipGetLastError());
   return kOk;
 }
@@ -679,7 +598,7 @@ int launch_chol_inv(const double* G, int w, double* T, int* kept, double* Tinv, 
 int chol_inv(const double* G, int w, double* T, int* kept, double* Tinv, hipStream_t s) {
   if (w <= 64) return launch_chol_inv_lds<64>(G, w, kept, Tinv, s);
   if (w <= 128) return launch_chol_inv_lds<128>(G, w, kept, Tinv, s);
-  if (w <= 256) return launch_chol_inv<256, 16>(G, w, T, kept, Tinv, s);
+  if (w <= 256) return chol_inv_wide(G, w, T, kept, Tinv, s);
   return kEInval;
 }
 
@@ -715,7 +634,10 @@ size_t orth_work_bytes(int64_t m, int w) {
 int orth_carve(Arena& a, int64_t m, int w, OrthWork* ow) {
   ow->ldt = (m + 1) & ~int64_t(1);
   ow->gram = a.take<double>(static_cast<size_t>(w) * w);
-  ow->tfull = a.take<double>(static_cast<size_t>(w) * w);
+  // scratch of chol_inv_wide (panels wider than 128)
+  ow->tfull = a.take<double>(w > 128 ? std::max(static_cast<size_t>(w) * w,
+                                                static_cast<size_t>(6 * 128 * 128 + 2 * 129))
+                                     : static_cast<size_t>(w) * w);
   ow->tinv = a.take<double>(static_cast<size_t>(w) * w);
   ow->qtmp = a.take<double>(static_cast<size_t>(ow->ldt) * w);
   ow->kept = a.take<int>(static_cast<size_t>(w) + 1);

@@ -81,39 +81,50 @@ __global__ __launch_bounds__(256) void quantize_sketch_kernel(const double* __re
   *reinterpret_cast<uint32_t*>(q + k0 + j * kp) = word;
 }
 
+// four 7-bit fields of v (bits 0..27) into the four bytes
+__device__ __forceinline__ uint32_t spread_lo(uint32_t v) {
+  uint32_t r = v & 0x7fu;
+  r = ((v << 1) & 0x7f00u) | r;
+  r = ((v << 2) & 0x7f0000u) | r;
+  return ((v << 3) & 0x7f000000u) | r;
+}
+// three 7-bit fields of v and its signed top field (bits 21..28, the sign
+// extension of v >> 21) into the four bytes
+__device__ __forceinline__ uint32_t spread_hi(uint32_t v) {
+  uint32_t r = v & 0x7fu;
+  r = ((v << 1) & 0x7f00u) | r;
+  r = ((v << 2) & 0x7f0000u) | r;
+  return ((v << 3) & 0xff000000u) | r;
+}
+// 4 x 4 byte transpose: d[s] byte c = w[c] byte s (v_perm_b32 picks bytes
+// 0..3 of its second operand with selectors 0..3, of its first with 4..7)
+__device__ __forceinline__ void transpose4(const uint32_t (&w)[4], uint32_t* d) {
+  const uint32_t x0 = __builtin_amdgcn_perm(w[1], w[0], 0x06020400u);
+  const uint32_t x1 = __builtin_amdgcn_perm(w[1], w[0], 0x07030501u);
+  const uint32_t y0 = __builtin_amdgcn_perm(w[3], w[2], 0x06020400u);
+  const uint32_t y1 = __builtin_amdgcn_perm(w[3], w[2], 0x07030501u);
+  d[0] = __builtin_amdgcn_perm(y0, x0, 0x05040100u);
+  d[2] = __builtin_amdgcn_perm(y0, x0, 0x07060302u);
+  d[1] = __builtin_amdgcn_perm(y1, x1, 0x05040100u);
+  d[3] = __builtin_amdgcn_perm(y1, x1, 0x07060302u);
+}
+
 // digits of four entries of one row at consecutive depths, packed one
-// dword per digit (byte c = entry c)
+// dword per digit (byte c = entry c): v = rint(x 2^(55-E)) = h 2^28 + l
+// with 0 <= l < 2^28; digits 0..3 are the 7-bit fields of l, digits 4..6
+// those of h, digit 7 the signed h >> 21
 __device__ __forceinline__ void digits4(const double (&x)[4], double scale, uint32_t (&out)[kDigits]) {
-  uint32_t lo[4];
-  int hi[4];
+  uint32_t wl[4], wh[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     const double t = rint(x[c] * scale);          // |t| < 2^54, exact scaling
     const double h = floor(t * 0x1p-28);          // exact
     const double l = fma(-h, 0x1p28, t);          // exact, in [0, 2^28)
-    hi[c] = static_cast<int>(h);
-    lo[c] = static_cast<uint32_t>(static_cast<int>(l));
+    wh[c] = spread_hi(static_cast<uint32_t>(static_cast<int>(h)));
+    wl[c] = spread_lo(static_cast<uint32_t>(static_cast<int>(l)));
   }
-#pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    uint32_t w = 0;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) w |= ((lo[c] >> (7 * s)) & 127u) << (8 * c);
-    out[s] = w;
-  }
-#pragma unroll
-  for (int s = 0; s < 3; ++s) {
-    uint32_t w = 0;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) w |= ((static_cast<uint32_t>(hi[c]) >> (7 * s)) & 127u) << (8 * c);
-    out[4 + s] = w;
-  }
-  {
-    uint32_t w = 0;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) w |= (static_cast<uint32_t>(hi[c] >> 21) & 255u) << (8 * c);
-    out[7] = w;
-  }
+  transpose4(wl, out);
+  transpose4(wh, out + 4);
 }
 
 // Y (M x N, N <= BN) for rows [32 bx, +32) and depth chunk z.  dnorm2: the

@@ -249,6 +249,7 @@ int qb_adjoint(const double* A, int64_t m, int64_t n, int64_t lda, int32_t b, in
                int32_t power_iters, uint64_t seed, const double* Q, int64_t ldq, const double* B,
                int64_t ldb, const double* dQ, int64_t lddq, const double* dB, int64_t lddb,
                double* dA, int64_t ldda, void* workspace, size_t ws_bytes, void* stream) {
+  Range rcall("qb_adjoint");
   Dims d;
   if (!A || !Q || !B || !dA) return QB_EINVAL;
   if (!adj_dims(m, n, lda, b, blocks, power_iters, ldq, ldb, &d)) return QB_EINVAL;

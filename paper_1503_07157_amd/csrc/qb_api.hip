@@ -19,6 +19,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstring>
+#include <optional>
 
 #include "../../include/qb.h"
 #include "qb_internal.hpp"
@@ -257,6 +258,7 @@ int factor_impl(const double* A, int64_t m, int64_t n, int64_t lda, double eps, 
                 int32_t power_iters, uint64_t seed, double* Q, int64_t ldq, double* B,
                 int64_t ldb, int64_t kmax, int64_t* k_out, qb_info* info, void* workspace,
                 size_t ws_bytes, void* stream, uint32_t flags, bool pinned) {
+  Range rcall("qb_factor");
   if (k_out) *k_out = 0;
   if (!k_out || !A || !Q || !B) return QB_EINVAL;
   if (!valid_sizes(m, n, b) || power_iters < 0 || !(eps >= 0.0) || !std::isfinite(eps))
@@ -364,6 +366,7 @@ int factor_impl(const double* A, int64_t m, int64_t n, int64_t lda, double eps, 
   for (;;) {
     const int w = static_cast<int>(std::min<int64_t>(bw, kcap - k));
     if (w <= 0) { reason = (kcap < r) ? QB_STOP_KMAX : QB_STOP_RANK_CAP; break; }
+    Range rblock("qb_block");
     // (2)-(3) sample the residual and orthonormalise
     if (spec_k != k || spec_w != w) {
       if (launch_sketch(seed, n, k, w, wk.omega, n, st)) return QB_EHIP;
@@ -373,6 +376,8 @@ int factor_impl(const double* A, int64_t m, int64_t n, int64_t lda, double eps, 
         return QB_EHIP;
     }
     spec_k = -1;
+    std::optional<Range> rsub;
+    rsub.emplace("qb_block_range_finder");
     if (power_orth) {
       if (orth_cholqr2(wk.Y, ldm, wk.Qi, ldm, m, w, wk.ow, st)) return QB_EHIP;
       // (4)-(7) power iterations on the residual
@@ -398,6 +403,8 @@ int factor_impl(const double* A, int64_t m, int64_t n, int64_t lda, double eps, 
       }
       if (orth_cholqr2(wk.Y, ldm, wk.Qi, ldm, m, w, wk.ow, st)) return QB_EHIP;
     }
+    rsub.reset();
+    rsub.emplace("qb_block_reproject_B_downdate");
     double* Qout = Q + k * ldq;
     // (3') re-projection against the basis so far, then orth
     if (k > 0) {

@@ -115,6 +115,7 @@ struct Plan {
   int64_t* tiles;       // [kSteps][kTileClasses] units of each product launch
   int64_t* rblocks;     // [kSteps] units of each reduction launch
   int64_t* sk_blocks;   // [1] sketch units
+  unsigned long long* next;  // [kSteps][kTileClasses] then [kSteps]: unit counters of the launches
   BatchSketch* sketch;  // [count]
   BatchChol *c1, *c3;   // [count] Cholesky of the first pair of passes / of the re-projected pair
   BatchSum *sB, *sR;    // [count]
@@ -188,6 +189,7 @@ int carve_batch(Arena& a, const qb_problem* probs, int count, Layout* L) {
   pl.tiles = a.take<int64_t>(kSteps * kTileClasses);
   pl.rblocks = a.take<int64_t>(kSteps);
   pl.sk_blocks = a.take<int64_t>(1);
+  pl.next = a.take<unsigned long long>(kSteps * kTileClasses + kSteps);
   pl.sketch = a.take<BatchSketch>(static_cast<size_t>(count));
   pl.c1 = a.take<BatchChol>(static_cast<size_t>(count));
   pl.c3 = a.take<BatchChol>(static_cast<size_t>(count));
@@ -484,6 +486,8 @@ __global__ __launch_bounds__(kPlanThreads) void batch_plan_kernel(const DevProb*
   __shared__ int64_t buf[kPlanThreads / 64];
   const int s = blockIdx.x;
   if (s < kSteps) {
+    if (threadIdx.x < kTileClasses) pl.next[s * kTileClasses + threadIdx.x] = 0;
+    if (threadIdx.x == kTileClasses) pl.next[kSteps * kTileClasses + s] = 0;
     int64_t rcarry = 0;
     for (int c = 0; c < kTileClasses; ++c) {
       BatchGemm* out = pl.gemm + (static_cast<int64_t>(s) * kTileClasses + c) * count;
@@ -678,6 +682,7 @@ size_t qb_factor_batched_workspace_bytes(const qb_problem* probs, int32_t count)
 
 int qb_factor_batched(qb_problem* probs, int32_t count, void* workspace, size_t ws_bytes,
                       void* stream) {
+  Range rcall("qb_factor_batched");
   if (!probs || count < 1) return QB_EINVAL;
   for (int i = 0; i < count; ++i)
     if (!problem_ok(probs[i])) return QB_EINVAL;
@@ -751,36 +756,57 @@ int qb_factor_batched(qb_problem* probs, int32_t count, void* workspace, size_t 
     TileTable tt;
     for (int r = 0; r < QB_ROLES; ++r)
       for (int c = 0; c < 3; ++c) tt.cls[r][c] = g_tile[r][c].load(std::memory_order_relaxed);
+    // Grid of each launch: the units the problems that may still be active
+    // could need at their widest (w = b, k = kcap), capped below.  Recomputed
+    // (and the graph captured again) when the problems left need much less.
     int64_t grid[kSteps][kTileClasses] = {};
     int64_t rgrid[kSteps] = {};
     int64_t skgrid = 0;
-    for (int i = 0; i < count; ++i) {
-      const Prob& p = P[i];
-      const int64_t w = p.b, k = p.kcap;
-      skgrid += sketch_blocks(p.n, p.b);
-      for (int st_ = 0; st_ < kSteps; ++st_) {
-        int64_t M = 0, N = 0;
-        switch (st_) {
-          case kStY: case kStA1: case kStA2: case kStRQ: case kStA3: case kStA4: M = p.m; N = w; break;
-          case kStRC: M = k; N = w; break;
-          case kStB: M = w; N = p.n; break;
-          case kStD: M = p.m; N = p.n; break;
-          default: M = w; N = w; break;
-        }
-        bool seen[kTileClasses] = {};
-        for (int wc = 0; wc <= width_class_hd(p.b); ++wc) {
-          const int c = tt.cls[step_role(st_)][wc];
-          if (seen[c]) continue;
-          seen[c] = true;
-          int bm = 0, bn = 0;
-          batch_tile_dims_hd(c, &bm, &bn);
-          grid[st_][c] += cdiv(M, bm) * cdiv(N, bn) + (st_ == kStD ? 0 : kSplitTiles);
-        }
-        if (st_ != kStD) rgrid[st_] += cdiv(M * N, kBatchRed);
-      }
-    }
-    constexpr int64_t kGridCap = 2048;  // workgroups of a launch; more units go round strides
+    std::vector<char> alive(count, 1);
+    // workgroups of a launch (they take further units from the launch's
+    // counter until none is left)
+    constexpr int64_t kGridCap = 2048;
     auto capped = [](int64_t g) { return g < kGridCap ? g : kGridCap; };
+    auto compute_grids = [&]() -> int64_t {
+      for (auto& row : grid)
+        for (int64_t& g : row) g = 0;
+      for (int64_t& g : rgrid) g = 0;
+      skgrid = 0;
+      for (int i = 0; i < count; ++i) {
+        if (!alive[i]) continue;
+        const Prob& p = P[i];
+        const int64_t w = p.b, k = p.kcap;
+        skgrid += sketch_blocks(p.n, p.b);
+        for (int st_ = 0; st_ < kSteps; ++st_) {
+          int64_t M = 0, N = 0;
+          switch (st_) {
+            case kStY: case kStA1: case kStA2: case kStRQ: case kStA3: case kStA4: M = p.m; N = w; break;
+            case kStRC: M = k; N = w; break;
+            case kStB: M = w; N = p.n; break;
+            case kStD: M = p.m; N = p.n; break;
+            default: M = w; N = w; break;
+          }
+          bool seen[kTileClasses] = {};
+          for (int wc = 0; wc <= width_class_hd(p.b); ++wc) {
+            const int c = tt.cls[step_role(st_)][wc];
+            if (seen[c]) continue;
+            seen[c] = true;
+            int bm = 0, bn = 0;
+            batch_tile_dims_hd(c, &bm, &bn);
+            grid[st_][c] += cdiv(M, bm) * cdiv(N, bn) + (st_ == kStD ? 0 : kSplitTiles);
+          }
+          if (st_ != kStD) rgrid[st_] += cdiv(M * N, kBatchRed);
+        }
+      }
+      // workgroups launched per iteration with these grids
+      int64_t tot = capped(skgrid);
+      for (int st_ = 0; st_ < kSteps; ++st_) {
+        tot += capped(rgrid[st_]);
+        for (int c = 0; c < kTileClasses; ++c) tot += capped(grid[st_][c]);
+      }
+      return tot;
+    };
+    int64_t grid_total = compute_grids();
     Plan pl = L.plan;
     const unsigned pgrid = static_cast<unsigned>(cdiv(count, 256));
     // eager: per-launch algorithmic work for the profiler from the host copy
@@ -813,13 +839,13 @@ int qb_factor_batched(qb_problem* probs, int32_t count, void* workspace, size_t 
           }
           const BatchGemm* d = pl.gemm + (static_cast<int64_t>(sidx) * kTileClasses + c) * count;
           if (gemm_batched(op, c, d, count, capped(grid[sidx][c]), pid, fl, by, cs,
-                           pl.tiles + sidx * kTileClasses + c))
+                           pl.tiles + sidx * kTileClasses + c, pl.next + sidx * kTileClasses + c))
             return 1;
         }
         if (rgrid[sidx] == 0) return 0;
         return gemm_batched_reduce(op, pl.gemm + static_cast<int64_t>(sidx) * kTileClasses * count,
                                    kTileClasses * count, capped(rgrid[sidx]), pid, cs,
-                                   pl.rblocks + sidx)
+                                   pl.rblocks + sidx, pl.next + kSteps * kTileClasses + sidx)
                    ? 1
                    : 0;
       };
@@ -872,24 +898,57 @@ int qb_factor_batched(qb_problem* probs, int32_t count, void* workspace, size_t 
       }
     } else {
       // kGraphIters iterations per graph; iterations after every problem
-      // has stopped find nothing to do (empty plans)
+      // has stopped find nothing to do (empty plans).  After each replay the
+      // host reads the problems' state; once the problems left need less
+      // than half the captured grids, the graph is captured again with
+      // grids for those problems only (the batch narrows fast: a few long
+      // problems run the last half of the iterations alone).
       constexpr int kGraphIters = 8;
       hipStream_t cs = nullptr;
       hipGraph_t graph = nullptr;
       hipGraphExec_t exec = nullptr;
       int e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess;
-      if (!e) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess;
-      if (!e) {
-        for (int u = 0; u < kGraphIters && !e; ++u) e = issue(cs, nullptr);
+      auto capture = [&]() -> int {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+        if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return 1;
+        int ce = 0;
+        for (int u = 0; u < kGraphIters && !ce; ++u) ce = issue(cs, nullptr);
         const bool ended = hipStreamEndCapture(cs, &graph) == hipSuccess;
-        e = e || !ended;
-      }
-      if (!e) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess;
+        if (ce || !ended) return 1;
+        return hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess;
+      };
+      if (!e) e = capture();
+      hs.resize(count);
       while (!e) {
-        if (hipGraphLaunch(exec, st) != hipSuccess) { e = 1; break; }
-        const int mo = more();
-        if (mo < 0) { e = 1; break; }
-        if (mo == 0) break;
+        Range rrep("qb_batched_graph_replay");
+        if (hipGraphLaunch(exec, st) != hipSuccess ||
+            hipMemcpyAsync(hs.data(), L.dstate, count * sizeof(DevState), hipMemcpyDeviceToHost,
+                           st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess) {
+          e = 1;
+          break;
+        }
+        bool any = false;
+        for (int i = 0; i < count; ++i) {
+          alive[i] = hs[i].active ? 1 : 0;
+          any = any || hs[i].active;
+        }
+        if (!any) break;
+        int64_t old_grid[kSteps][kTileClasses], old_rgrid[kSteps], old_sk = skgrid;
+        std::memcpy(old_grid, grid, sizeof(grid));
+        std::memcpy(old_rgrid, rgrid, sizeof(rgrid));
+        const int64_t need = compute_grids();
+        if (2 * need < grid_total) {
+          grid_total = need;
+          e = capture();
+        } else {  // keep the captured graph and its grids
+          std::memcpy(grid, old_grid, sizeof(grid));
+          std::memcpy(rgrid, old_rgrid, sizeof(rgrid));
+          skgrid = old_sk;
+        }
       }
       if (exec) (void)hipGraphExecDestroy(exec);
       if (graph) (void)hipGraphDestroy(graph);

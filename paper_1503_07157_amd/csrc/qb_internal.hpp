@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 #include <cstddef>
 #include <cstdint>
 
@@ -51,6 +52,15 @@ constexpr int64_t kMaxDowndateCols = int64_t(65535) * 64;
 // QB_ENODEVICE unless the current HIP device is a gfx950; the answer is
 // cached per device, so only the first call on a device queries it.
 int device_ready();
+
+// roctx range for the duration of a scope (shown by rocprofv3 --marker-trace;
+// a few nanoseconds when no tool listens)
+struct Range {
+  explicit Range(const char* name) { roctxRangePushA(name); }
+  ~Range() { roctxRangePop(); }
+  Range(const Range&) = delete;
+  Range& operator=(const Range&) = delete;
+};
 
 // Workspace arena: bump allocator over a caller buffer, 256-byte aligned.
 struct Arena {
@@ -208,13 +218,16 @@ constexpr int kBatchRed = 1024;     // elements per workgroup of the split-K red
 // order (alpha sum + beta C for NN, the sum for TN) with per-workgroup sums
 // of squares into sq when sq is set; total_rblocks counts its workgroups.
 // dev_total (optional): a device count of units that the launch's
-// total_tiles (or total_rblocks) workgroups walk in strides of the grid
-// instead of one unit each (the device-planned batch loop).
+// total_tiles (or total_rblocks) workgroups share instead of one unit each
+// (the device-planned batch loop).
+// dev_next: the launch's unit counter (zeroed before the launch); the
+// workgroups take units from it one at a time.
 int gemm_batched(int op, int cls, const BatchGemm* desc, int count, int64_t total_tiles,
                  int prof_id, double flops, double bytes, hipStream_t s,
-                 const int64_t* dev_total = nullptr);
+                 const int64_t* dev_total = nullptr, unsigned long long* dev_next = nullptr);
 int gemm_batched_reduce(int op, const BatchGemm* desc, int count, int64_t total_rblocks,
-                        int prof_id, hipStream_t s, const int64_t* dev_total = nullptr);
+                        int prof_id, hipStream_t s, const int64_t* dev_total = nullptr,
+                        unsigned long long* dev_next = nullptr);
 
 struct BatchChol {  // Cholesky with dropping + inverse of one w x w Gram matrix
   const double* G;

@@ -9,6 +9,8 @@ tensors of shape (m, n) with strides (1, ld), ld >= m (use
 from __future__ import annotations
 
 import ctypes
+import json
+import os
 from dataclasses import dataclass, field
 
 import torch
@@ -78,6 +80,14 @@ class QBResult:
     R: torch.Tensor | None = None
 
 
+def _trace_record(rec: dict) -> None:
+    """QB_TRACE=1: one JSON line per qb_factor call (sizes, rank, stop
+    reason and the per-block kept widths, tracked E_i and direct D_i) appended
+    to QB_TRACE_FILE (default qb_trace.jsonl)."""
+    with open(os.environ.get("QB_TRACE_FILE", "qb_trace.jsonl"), "a") as f:
+        f.write(json.dumps(rec) + "\n")
+
+
 def workspace_bytes(m, n, b, kmax=-1, sample="f64", overwrite=False) -> int:
     flags = QB_SAMPLE[sample] | (QB_OVERWRITE_A if overwrite else 0)
     return int(_lib.load().qb_workspace_bytes(m, n, b, kmax, flags))
@@ -143,6 +153,13 @@ def qb_factor(A: torch.Tensor, eps: float, b: int, power_iters: int = 0, seed: i
         _check(code, "qb_factor")
     kk = int(k.value)
     L = info.trace_len
+    if os.environ.get("QB_TRACE") == "1":
+        _trace_record({"m": m, "n": n, "b": int(b), "power_iters": int(power_iters),
+                       "seed": int(seed), "sample": sample, "bgemm": bgemm, "eps": float(eps),
+                       "k": kk, "blocks": int(info.blocks), "status": int(code),
+                       "stop": QB_STOP.get(info.stop_reason, str(info.stop_reason)),
+                       "normA2": info.normA2, "widths": list(tw[:L]), "E": list(tE[:L]),
+                       "D": list(tD[:L])})
     return QBResult(Q=Q[:, :kk], B=B[:kk, :], k=kk, status=code,
                     stop_reason=QB_STOP.get(info.stop_reason, str(info.stop_reason)),
                     normA2=info.normA2, indicator=info.indicator, resid2=info.resid2,

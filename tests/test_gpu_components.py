@@ -125,7 +125,7 @@ def test_orth_matches_oracle(cuda, m, w, cond):
     assert np.linalg.norm(Qg - Qo) < 1e-13 * cond * w
 
 
-@pytest.mark.parametrize("m,w", [(2000, 128), (700, 64), (3000, 100)])
+@pytest.mark.parametrize("m,w", [(2000, 128), (700, 64), (3000, 100), (3000, 256), (1500, 129)])
 def test_orth_power_of_two_scale_invariance(cuda, m, w):
     """orth(2^s X) equals orth(X) bit for bit: the Gram scales by exactly
     2^2s, the Cholesky works on G brought to a fixed power-of-two range, and
@@ -156,3 +156,28 @@ def test_orth_drops_dependent_and_zero_columns(cuda):
     Z = np.zeros((50, 4), order="F")
     Qz, kz = qbmi.orth(dev(Z))
     assert kz == 0 and np.all(host(Qz) == 0.0)
+
+
+@pytest.mark.parametrize("w", [129, 200, 256])
+def test_wide_orth_drops_across_the_two_blocks(cuda, w):
+    """Panels wider than 128 are factorised as a 128-column block and its
+    Schur complement, with the scale and drop threshold of the whole Gram
+    matrix: dependent and zero columns are dropped in either block, also
+    when the dependence reaches back into the first block, and the kept
+    columns and Q are the oracle's (unblocked CholQR2)."""
+    r = _rng(w)
+    X = r.standard_normal((900, w))
+    X[:, 5] = X[:, 1] - 2.0 * X[:, 3]                 # inside the first block
+    X[:, 128] = 0.5 * X[:, 10] + X[:, 100]            # second block on the first
+    X[:, w - 1] = 0.0                                 # zero column at the end
+    if w > 140:
+        X[:, 140] = X[:, 130] - X[:, 20]              # mixes both blocks
+    X = np.asfortranarray(X)
+    Qg, kept = qbmi.orth(dev(X))
+    Qo, ko = cholqr2(X)
+    print(f"[case] w={w}: kept {kept} oracle {len(ko)}", flush=True)
+    assert kept == len(ko)
+    Qg = host(Qg)
+    assert np.linalg.norm(Qg[:, :kept] - Qo) < 1e-11
+    assert np.all(Qg[:, kept:] == 0.0)
+    assert np.linalg.norm(Qg[:, :kept].T @ Qg[:, :kept] - np.eye(kept)) < 20 * U * w
