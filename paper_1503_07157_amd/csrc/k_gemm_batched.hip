@@ -123,15 +123,22 @@ __device__ __forceinline__ void batched_tile(const BatchGemm* __restrict__ desc,
 // takes unit g first, then further units gridDim.x + (launch counter)++ one
 // at a time, so the long units do not pile up on a few workgroups, and a
 // workgroup with nothing to do (the tail of the batch) exits without
-// touching the counter.  Thread 0 takes the unit, the workgroup reads it
-// from LDS.
-__device__ __forceinline__ int64_t grab_unit(unsigned long long* next, int64_t* slot) {
-  if (threadIdx.x == 0)
-    *slot = static_cast<int64_t>(gridDim.x) + static_cast<int64_t>(atomicAdd(next, 1ull));
-  __syncthreads();
-  const int64_t u = *slot;
-  __syncthreads();
-  return u;
+// touching the counter.  Thread 0 takes the next unit when it starts the
+// current one, so the atomic's latency hides behind the unit's work; the
+// workgroup reads it from LDS afterwards.
+template <class Body>
+__device__ __forceinline__ void walk_units(unsigned long long* next, int64_t n, int64_t* slot,
+                                           Body&& body) {
+  int64_t blk = blockIdx.x;
+  while (blk < n) {
+    unsigned long long nx = 0;
+    if (threadIdx.x == 0) nx = atomicAdd(next, 1ull);
+    body(blk);
+    if (threadIdx.x == 0) *slot = static_cast<int64_t>(gridDim.x) + static_cast<int64_t>(nx);
+    __syncthreads();
+    blk = *slot;
+    __syncthreads();
+  }
 }
 
 template <class S, int OP>
@@ -148,9 +155,8 @@ __global__ __launch_bounds__(S::NT, S::OCC) void gemm_batched_kernel(
   }
   // units of very different depth: taken one at a time from a counter, so
   // the long ones do not pile up on a few workgroups
-  const int64_t n = *total;
-  for (int64_t blk = blockIdx.x; blk < n; blk = grab_unit(next, &slot))
-    batched_tile<S, OP>(desc, count, blk, As, Bs, red);
+  walk_units(next, *total, &slot,
+             [&](int64_t blk) { batched_tile<S, OP>(desc, count, blk, As, Bs, red); });
 }
 
 // C from the depth chunks of the problems with ksplit > 1, in chunk order;
@@ -200,9 +206,8 @@ __global__ __launch_bounds__(256) void gemm_batched_reduce_kernel(
     batched_reduce_unit<OP>(desc, count, blockIdx.x, red);
     return;
   }
-  const int64_t n = *total;
-  for (int64_t blk = blockIdx.x; blk < n; blk = grab_unit(next, &slot))
-    batched_reduce_unit<OP>(desc, count, blk, red);
+  walk_units(next, *total, &slot,
+             [&](int64_t blk) { batched_reduce_unit<OP>(desc, count, blk, red); });
 }
 
 }  // namespace

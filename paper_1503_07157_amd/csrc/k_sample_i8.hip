@@ -133,7 +133,8 @@ template <int BN>
 __global__ __launch_bounds__(2 * BN, 1) void sample_i8_kernel(
     const double* __restrict__ A, int64_t lda, const int8_t* __restrict__ q, int64_t kp,
     double* __restrict__ Y, int64_t ldy, int64_t M, int N, int64_t K, int64_t kchunk,
-    const double* __restrict__ dnorm2, int e_host, double* __restrict__ part, int64_t ldp) {
+    const double* __restrict__ dnorm2, int e_host, double* __restrict__ part, int64_t ldp,
+    int tiles_chunks) {
   constexpr int NT = 2 * BN;
   constexpr int UPT = (kRows * kStep / 4) / NT;   // 4-entry units per thread per step
   constexpr int BPT = (BN * kStep / 16) / NT;     // 16-byte sketch pieces per thread per step
@@ -145,8 +146,22 @@ __global__ __launch_bounds__(2 * BN, 1) void sample_i8_kernel(
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
   const int wm = (wave & 1) * 16, wn = (wave >> 1) * 64;
-  const int64_t m0 = static_cast<int64_t>(blockIdx.x) * kRows;
-  const int64_t kbeg = static_cast<int64_t>(blockIdx.y) * kchunk;
+  // XCD-aware order: workgroup L runs on XCD L mod 8; XCD x takes a
+  // contiguous run of (chunk, row tile) pairs, so the workgroups resident on
+  // one XCD read neighbouring 256-byte row segments of the same columns of
+  // A (whole DRAM pages between them) instead of segments 8 tiles apart.
+  int64_t tile, chunk;
+  {
+    constexpr int kXcd = 8;
+    const int64_t tiles_m = gridDim.x / tiles_chunks;
+    const int64_t L = blockIdx.x, total = gridDim.x;
+    const int64_t q = total / kXcd, r = total % kXcd, x = L % kXcd, j = L / kXcd;
+    const int64_t logical = x * q + (x < r ? x : r) + j;
+    chunk = logical / tiles_m;
+    tile = logical - chunk * tiles_m;
+  }
+  const int64_t m0 = tile * kRows;
+  const int64_t kbeg = chunk * kchunk;
   const int64_t kend = kbeg + kchunk < K ? kbeg + kchunk : K;
   const int E = dnorm2 ? split_exponent_dev(dnorm2[0]) : e_host;
   const double scale = ldexp(1.0, kFracBits - E);
@@ -244,7 +259,7 @@ __global__ __launch_bounds__(2 * BN, 1) void sample_i8_kernel(
 
   // combine the digit sums: y = sum_s 128^s acc_s, then scale by 2^(E-59)
   const double oscale = ldexp(1.0, E - kFracBits - 4);
-  double* out = part ? part + static_cast<int64_t>(blockIdx.y) * ldp * N : Y;
+  double* out = part ? part + chunk * ldp * N : Y;
   const int64_t ldo = part ? ldp : ldy;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
@@ -314,21 +329,23 @@ int sample_i8(const double* A, int64_t lda, const int8_t* q, double* Y, int64_t 
   const int64_t kc = sample_i8_kp(cdiv(K, nz));
   const int nzr = static_cast<int>(cdiv(K, kc));
   if (kc > kMaxChunk) return kEInval;
+  if (cdiv(M, kRows) * nzr >= (int64_t(1) << 31)) return kEInval;  // one-dimensional grid
   if (nzr > 1 && part == nullptr) return kEInval;
   const int64_t ldp = (M + 1) & ~int64_t(1);
   double* pp = nzr > 1 ? part : nullptr;
-  const dim3 grid(static_cast<unsigned>(cdiv(M, kRows)), static_cast<unsigned>(nzr));
+  // one-dimensional grid: (row tile, depth chunk) pairs, chunk-major
+  const dim3 grid(static_cast<unsigned>(cdiv(M, kRows) * nzr));
   {
     ProfScope ps(kKSampleI8, 2.0 * M * N * K, 8.0 * M * K + 1.0 * K * N + 8.0 * M * N, s);
     if (N <= 64)
       hipLaunchKernelGGL(sample_i8_kernel<64>, grid, dim3(128), 0, s, A, lda, q, kp, Y, ldy, M, N,
-                         K, kc, dnorm2, e_host, pp, ldp);
+                         K, kc, dnorm2, e_host, pp, ldp, nzr);
     else if (N <= 128)
       hipLaunchKernelGGL(sample_i8_kernel<128>, grid, dim3(256), 0, s, A, lda, q, kp, Y, ldy, M,
-                         N, K, kc, dnorm2, e_host, pp, ldp);
+                         N, K, kc, dnorm2, e_host, pp, ldp, nzr);
     else
       hipLaunchKernelGGL(sample_i8_kernel<256>, grid, dim3(512), 0, s, A, lda, q, kp, Y, ldy, M,
-                         N, K, kc, dnorm2, e_host, pp, ldp);
+                         N, K, kc, dnorm2, e_host, pp, ldp, nzr);
   }
   QB_HIP_TRY(hipGetLastError());
   if (nzr > 1) {

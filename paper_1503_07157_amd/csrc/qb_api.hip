@@ -81,6 +81,10 @@ size_t max_partials(int64_t m, int64_t n, int b, int64_t kcap, bool exact) {
       const size_t v = partial_doubles(rows, cols, s);
       if (v > best) best = v;
     }
+    for (int slots : {1, 2}) {  // the low-precision sampling products
+      const size_t v = partial_doubles(rows, cols, choose_split_fill(rows, cols, K, slots));
+      if (v > best) best = v;
+    }
   };
   upd(m, b, n);                // Y = A Omega, Y = A Z
   upd(b, n, m);                // B_i = Q^T A, (A^T Q)^T
@@ -173,9 +177,11 @@ int sample(uint32_t prec, const double* X, int64_t ldx, const double* W, int64_t
     if (quantize_sketch(W, ldw, K, static_cast<int>(N), omq, s)) return kEHip;
     return sample_i8(X, ldx, omq, Y, ldy, M, static_cast<int>(N), K, xnorm2, 0, part, s);
   }
+  if (prec == QB_SAMPLE_F64)
+    return gemm_nn(X, ldx, W, ldw, Y, ldy, M, N, K, 1.0, 0.0, choose_split(M, N, K, 2, true), part,
+                   s);
   // the bf16x3 form of this product runs one workgroup per CU
-  const int split = choose_split(M, N, K, prec == QB_SAMPLE_BF16X3 ? 1 : 2, prec == QB_SAMPLE_F64);
-  if (prec == QB_SAMPLE_F64) return gemm_nn(X, ldx, W, ldw, Y, ldy, M, N, K, 1.0, 0.0, split, part, s);
+  const int split = choose_split_fill(M, N, K, prec == QB_SAMPLE_BF16X3 ? 1 : 2);
   return gemm_nn_lowp(prec == QB_SAMPLE_F32 ? 1 : 2, X, ldx, W, ldw, Y, ldy, M, N, K, split,
                       part, s);
 }
@@ -586,9 +592,11 @@ struct GemmScratch {
 size_t gemm_scratch(void* workspace, size_t ws_bytes, int64_t m, int64_t K, int32_t w,
                     GemmScratch* g) {
   Arena a{static_cast<char*>(workspace), ws_bytes, 0};
-  const size_t np = std::max(partial_doubles(m, w, choose_split(m, w, K, 2, true)),
-                             std::max(partial_doubles(m, w, choose_split(m, w, K, 2, false)),
-                                      sample_i8_partials(m, w, K)));
+  size_t np = std::max(partial_doubles(m, w, choose_split(m, w, K, 2, true)),
+                       std::max(partial_doubles(m, w, choose_split(m, w, K, 2, false)),
+                                sample_i8_partials(m, w, K)));
+  for (int slots : {1, 2})
+    np = std::max(np, partial_doubles(m, w, choose_split_fill(m, w, K, slots)));
   g->part = a.take<double>(np + 1);
   g->omq = a.take<int8_t>(static_cast<size_t>(sample_i8_kp(K)) * w);
   const size_t nsq = sumsq_partials_count(m, K) + 1;

@@ -763,6 +763,27 @@ int qb_factor_batched(qb_problem* probs, int32_t count, void* workspace, size_t 
     int64_t rgrid[kSteps] = {};
     int64_t skgrid = 0;
     std::vector<char> alive(count, 1);
+    // whether step st_ of problem p can ever split its depth (so needs the
+    // reduction launch): gemm_desc splits only outputs of fewer than
+    // kSplitTiles tiles with a depth of at least 2 kSplitChunk; the tile
+    // count is smallest at w = 1 and k = 1, the depth fixed or growing
+    auto may_split = [&](int st_, const Prob& p, const TileTable& t) {
+      for (int wc = 0; wc <= width_class_hd(p.b); ++wc) {
+        int bm = 0, bn = 0;
+        batch_tile_dims_hd(t.cls[step_role(st_)][wc], &bm, &bn);
+        int64_t M = 1, N = 1, K = 0;
+        switch (st_) {
+          case kStY: M = p.m; K = p.n; break;
+          case kStA1: case kStA2: case kStA3: case kStA4: M = p.m; K = p.b; break;
+          case kStRC: K = p.m; break;
+          case kStRQ: M = p.m; K = p.kcap; break;
+          case kStB: N = p.n; K = p.m; break;
+          default: K = p.m; break;  // the Gram matrices
+        }
+        if (cdiv(M, bm) * cdiv(N, bn) < kSplitTiles && K >= 2 * kSplitChunk) return true;
+      }
+      return false;
+    };
     // workgroups of a launch (they take further units from the launch's
     // counter until none is left)
     constexpr int64_t kGridCap = 2048;
@@ -795,7 +816,9 @@ int qb_factor_batched(qb_problem* probs, int32_t count, void* workspace, size_t 
             batch_tile_dims_hd(c, &bm, &bn);
             grid[st_][c] += cdiv(M, bm) * cdiv(N, bn) + (st_ == kStD ? 0 : kSplitTiles);
           }
-          if (st_ != kStD) rgrid[st_] += cdiv(M * N, kBatchRed);
+          // a reduction only where some width or rank could split the
+          // product's depth: fewest tiles at w = 1 (k = 1 for Qbar^T Q_i)
+          if (st_ != kStD && may_split(st_, p, tt)) rgrid[st_] += cdiv(M * N, kBatchRed);
         }
       }
       // workgroups launched per iteration with these grids
