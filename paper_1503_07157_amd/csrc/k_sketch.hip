@@ -161,15 +161,10 @@ __device__ __forceinline__ void sketch_batched_unit(const BatchSketch* __restric
               d.out, d.ld, t, lb / nb);
 }
 
-// total: null for one workgroup per unit, else the device unit count walked
-// in strides of the grid
+// total: the device unit count, walked in strides of the grid
 __global__ __launch_bounds__(256) void sketch_batched_kernel(const BatchSketch* __restrict__ desc,
                                                              int count,
                                                              const int64_t* __restrict__ total) {
-  if (total == nullptr) {
-    sketch_batched_unit(desc, count, blockIdx.x);
-    return;
-  }
   const int64_t n = *total;
   for (int64_t blk = blockIdx.x; blk < n; blk += gridDim.x) sketch_batched_unit(desc, count, blk);
 }
@@ -181,7 +176,7 @@ int64_t sketch_blocks(int64_t n, int w) { return ((n + 1) / 2 + 255) / 256 * w; 
 int sketch_batched(const BatchSketch* desc, int count, int64_t total_blocks, hipStream_t s,
                    const int64_t* dev_total) {
   if (count <= 0 || total_blocks <= 0) return kOk;
-  if (total_blocks > INT32_MAX) return kEInval;  // one-dimensional grid
+  if (total_blocks > INT32_MAX || dev_total == nullptr) return kEInval;  // one-dimensional grid
   ProfScope ps(kKSketch, 0.0, 0.0, s);
   hipLaunchKernelGGL(sketch_batched_kernel, dim3(static_cast<unsigned>(total_blocks)), dim3(256),
                      0, s, desc, count, dev_total);

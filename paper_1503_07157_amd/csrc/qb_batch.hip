@@ -24,7 +24,9 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <utility>
 #include <vector>
 
 #include "../../include/qb.h"
@@ -112,6 +114,7 @@ struct TileTable {
 // device tables of one iteration
 struct Plan {
   BatchGemm* gemm;      // [kSteps][kTileClasses][count]
+  BatchGemm* rgemm;     // [kSteps][count] each problem's own entry, for the reduction
   int64_t* tiles;       // [kSteps][kTileClasses] units of each product launch
   int64_t* rblocks;     // [kSteps] units of each reduction launch
   int64_t* sk_blocks;   // [1] sketch units
@@ -186,6 +189,7 @@ int carve_batch(Arena& a, const qb_problem* probs, int count, Layout* L) {
   L->dstate = a.take<DevState>(static_cast<size_t>(count));
   Plan& pl = L->plan;
   pl.gemm = a.take<BatchGemm>(static_cast<size_t>(kSteps) * kTileClasses * count);
+  pl.rgemm = a.take<BatchGemm>(static_cast<size_t>(kSteps) * count);
   pl.tiles = a.take<int64_t>(kSteps * kTileClasses);
   pl.rblocks = a.take<int64_t>(kSteps);
   pl.sk_blocks = a.take<int64_t>(1);
@@ -477,51 +481,63 @@ __device__ int64_t block_scan(int64_t v, int64_t* total, int64_t* buf) {
   return before + x - v;
 }
 
-// workgroup s < kSteps: the descriptors of product step s, class by class,
-// with each problem's first unit (tile0) and first reduction unit (rblock0);
-// workgroup kSteps: sketch, Cholesky and sum records
+// workgroup s kTileClasses + c (s < kSteps): the descriptors of product
+// step s in tile class c, with each problem's first unit (tile0), and the
+// step's reduction descriptors (each problem's own entry, first reduction
+// unit rblock0 in problem order; written by the workgroup of that problem's
+// class, or of class 0 for a problem with none); workgroup kSteps
+// kTileClasses: sketch, Cholesky and sum records
 __global__ __launch_bounds__(kPlanThreads) void batch_plan_kernel(const DevProb* __restrict__ P,
                                                                   const DevState* __restrict__ S,
                                                                   int count, TileTable tt, Plan pl) {
   __shared__ int64_t buf[kPlanThreads / 64];
-  const int s = blockIdx.x;
-  if (s < kSteps) {
-    if (threadIdx.x < kTileClasses) pl.next[s * kTileClasses + threadIdx.x] = 0;
-    if (threadIdx.x == kTileClasses) pl.next[kSteps * kTileClasses + s] = 0;
-    int64_t rcarry = 0;
-    for (int c = 0; c < kTileClasses; ++c) {
-      BatchGemm* out = pl.gemm + (static_cast<int64_t>(s) * kTileClasses + c) * count;
-      int64_t carry = 0;
-      for (int i0 = 0; i0 < count; i0 += kPlanThreads) {
-        const int i = i0 + static_cast<int>(threadIdx.x);
-        BatchGemm g{};
-        int64_t units = 0, runits = 0;
-        if (i < count && S[i].active) {
-          const int w = S[i].w;
-          if (step_desc(s, P[i], S[i].k, w, tt, &g) &&
-              tt.cls[step_role(s)][width_class_hd(w)] == c) {
-            units = static_cast<int64_t>(g.tiles_m) * g.tiles_n * g.ksplit;
-            runits = reduce_blocks(g);
-          }
+  const int wg = blockIdx.x;
+  if (wg < kSteps * kTileClasses) {
+    const int s = wg / kTileClasses, c = wg % kTileClasses;
+    if (threadIdx.x == 0) pl.next[wg] = 0;
+    if (c == 0 && threadIdx.x == 1) pl.next[kSteps * kTileClasses + s] = 0;
+    BatchGemm* out = pl.gemm + static_cast<int64_t>(wg) * count;
+    BatchGemm* rout = pl.rgemm + static_cast<int64_t>(s) * count;
+    int64_t carry = 0, rcarry = 0;
+    for (int i0 = 0; i0 < count; i0 += kPlanThreads) {
+      const int i = i0 + static_cast<int>(threadIdx.x);
+      BatchGemm g{};
+      int64_t units = 0, runits = 0;
+      int cls = -1;
+      if (i < count && S[i].active) {
+        const int w = S[i].w;
+        if (step_desc(s, P[i], S[i].k, w, tt, &g)) {
+          cls = tt.cls[step_role(s)][width_class_hd(w)];
+          runits = reduce_blocks(g);
+          if (cls == c) units = static_cast<int64_t>(g.tiles_m) * g.tiles_n * g.ksplit;
         }
-        int64_t tot = 0, rtot = 0;
-        const int64_t ex = block_scan(units, &tot, buf);
-        const int64_t rex = block_scan(runits, &rtot, buf);
-        if (i < count) {
-          if (units == 0) {  // no part in this launch: no units, no partial sums
-            g = BatchGemm{};
-            g.ksplit = 1;
-          }
+      }
+      int64_t tot = 0, rtot = 0;
+      const int64_t ex = block_scan(units, &tot, buf);
+      const int64_t rex = block_scan(runits, &rtot, buf);
+      if (i < count) {
+        if (cls != c) {  // no part in this launch: no units, no partial sums
+          out[i] = BatchGemm{};
+          out[i].ksplit = 1;
+          out[i].tile0 = carry + ex;
+        } else {
           g.tile0 = carry + ex;
-          g.rblock0 = rcarry + rex;
           out[i] = g;
         }
-        carry += tot;
-        rcarry += rtot;
+        if (cls == c || (cls < 0 && c == 0)) {
+          BatchGemm r = cls < 0 ? BatchGemm{} : g;
+          if (cls < 0) r.ksplit = 1;
+          r.rblock0 = rcarry + rex;
+          rout[i] = r;
+        }
       }
-      if (threadIdx.x == 0) pl.tiles[s * kTileClasses + c] = carry;
+      carry += tot;
+      rcarry += rtot;
     }
-    if (threadIdx.x == 0) pl.rblocks[s] = rcarry;
+    if (threadIdx.x == 0) {
+      pl.tiles[wg] = carry;
+      if (c == 0) pl.rblocks[s] = rcarry;
+    }
     return;
   }
   int64_t carry = 0;
@@ -696,12 +712,17 @@ int qb_factor_batched(qb_problem* probs, int32_t count, void* workspace, size_t 
   std::vector<Prob>& P = L.pr;
 
   // pinned host memory for the descriptors and the per-iteration scalars
+  // (then the "still active" flag and two copies of the problems' state)
   Stage sg;
   sg.cap = L.desc_bytes;
-  void* hbuf = pinned_stage(sg.cap + 64);
+  const size_t st_off = (sg.cap + 64 + 255) & ~size_t(255);
+  const size_t st_bytes = static_cast<size_t>(count) * sizeof(DevState);
+  void* hbuf = pinned_stage(st_off + 2 * st_bytes);
   if (hbuf == nullptr) return QB_EHIP;
   sg.host = static_cast<char*>(hbuf);
   int* hflag = reinterpret_cast<int*>(sg.host + sg.cap);  // the "still active" flag
+  DevState* hstate2[2] = {reinterpret_cast<DevState*>(sg.host + st_off),
+                          reinterpret_cast<DevState*>(sg.host + st_off + st_bytes)};
   auto upload = [&]() -> int {
     if (sg.used == 0) return kOk;
     return hipMemcpyAsync(L.desc, sg.host, sg.used, hipMemcpyHostToDevice, st) == hipSuccess
@@ -757,8 +778,9 @@ int qb_factor_batched(qb_problem* probs, int32_t count, void* workspace, size_t 
     for (int r = 0; r < QB_ROLES; ++r)
       for (int c = 0; c < 3; ++c) tt.cls[r][c] = g_tile[r][c].load(std::memory_order_relaxed);
     // Grid of each launch: the units the problems that may still be active
-    // could need at their widest (w = b, k = kcap), capped below.  Recomputed
-    // (and the graph captured again) when the problems left need much less.
+    // could need at their widest (w = b, k = kcap), an upper bound on what
+    // the device plans.  Recomputed (and the graph captured again) when the
+    // problems left need less than half.
     int64_t grid[kSteps][kTileClasses] = {};
     int64_t rgrid[kSteps] = {};
     int64_t skgrid = 0;
@@ -784,10 +806,6 @@ int qb_factor_batched(qb_problem* probs, int32_t count, void* workspace, size_t 
       }
       return false;
     };
-    // workgroups of a launch (they take further units from the launch's
-    // counter until none is left)
-    constexpr int64_t kGridCap = 2048;
-    auto capped = [](int64_t g) { return g < kGridCap ? g : kGridCap; };
     auto compute_grids = [&]() -> int64_t {
       for (auto& row : grid)
         for (int64_t& g : row) g = 0;
@@ -822,10 +840,10 @@ int qb_factor_batched(qb_problem* probs, int32_t count, void* workspace, size_t 
         }
       }
       // workgroups launched per iteration with these grids
-      int64_t tot = capped(skgrid);
+      int64_t tot = skgrid;
       for (int st_ = 0; st_ < kSteps; ++st_) {
-        tot += capped(rgrid[st_]);
-        for (int c = 0; c < kTileClasses; ++c) tot += capped(grid[st_][c]);
+        tot += rgrid[st_];
+        for (int c = 0; c < kTileClasses; ++c) tot += grid[st_][c];
       }
       return tot;
     };
@@ -836,10 +854,10 @@ int qb_factor_batched(qb_problem* probs, int32_t count, void* workspace, size_t 
     // of the state (read every iteration); graph: none
     std::vector<DevState> hs;
     auto issue = [&](hipStream_t cs, const DevState* hstate) -> int {
-      hipLaunchKernelGGL(batch_plan_kernel, dim3(kSteps + 1), dim3(kPlanThreads), 0, cs, L.dprob,
-                         L.dstate, count, tt, pl);
+      hipLaunchKernelGGL(batch_plan_kernel, dim3(kSteps * kTileClasses + 1), dim3(kPlanThreads), 0,
+                         cs, L.dprob, L.dstate, count, tt, pl);
       if (hipGetLastError() != hipSuccess) return 1;
-      if (sketch_batched(pl.sketch, count, capped(skgrid), cs, pl.sk_blocks)) return 1;
+      if (sketch_batched(pl.sketch, count, skgrid, cs, pl.sk_blocks)) return 1;
       auto mm = [&](int sidx, int pid) -> int {
         const int op = step_op(sidx);
         for (int c = 0; c < kTileClasses; ++c) {
@@ -861,13 +879,13 @@ int qb_factor_batched(qb_problem* probs, int32_t count, void* workspace, size_t 
             }
           }
           const BatchGemm* d = pl.gemm + (static_cast<int64_t>(sidx) * kTileClasses + c) * count;
-          if (gemm_batched(op, c, d, count, capped(grid[sidx][c]), pid, fl, by, cs,
+          if (gemm_batched(op, c, d, count, grid[sidx][c], pid, fl, by, cs,
                            pl.tiles + sidx * kTileClasses + c, pl.next + sidx * kTileClasses + c))
             return 1;
         }
         if (rgrid[sidx] == 0) return 0;
-        return gemm_batched_reduce(op, pl.gemm + static_cast<int64_t>(sidx) * kTileClasses * count,
-                                   kTileClasses * count, capped(rgrid[sidx]), pid, cs,
+        return gemm_batched_reduce(op, pl.rgemm + static_cast<int64_t>(sidx) * count, count,
+                                   rgrid[sidx], pid, cs,
                                    pl.rblocks + sidx, pl.next + kSteps * kTileClasses + sidx)
                    ? 1
                    : 0;
@@ -915,25 +933,52 @@ int qb_factor_batched(qb_problem* probs, int32_t count, void* workspace, size_t 
             hipStreamSynchronize(st) != hipSuccess)
           return QB_EHIP;
         if (issue(st, hs.data())) return QB_EHIP;
+        // the one-workgroup-per-unit launches rely on the host grids
+        // bounding the units the device planned: checked here, per
+        // iteration (the graph path runs the same plan and bounds)
+        int64_t ut[kSteps * kTileClasses], ur[kSteps], us = 0;
+        if (hipMemcpyAsync(ut, pl.tiles, sizeof(ut), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipMemcpyAsync(ur, pl.rblocks, sizeof(ur), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipMemcpyAsync(&us, pl.sk_blocks, sizeof(us), hipMemcpyDeviceToHost, st) !=
+                hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+          return QB_EHIP;
+        bool fits = us <= skgrid;
+        for (int st_ = 0; st_ < kSteps; ++st_) {
+          fits = fits && ur[st_] <= rgrid[st_];
+          for (int c = 0; c < kTileClasses; ++c)
+            fits = fits && ut[st_ * kTileClasses + c] <= grid[st_][c];
+        }
+        if (!fits) {
+          std::fprintf(stderr, "qb_factor_batched: planned units exceed the launch grids\n");
+          return QB_EHIP;
+        }
         const int mo = more();
         if (mo < 0) return QB_EHIP;
         if (mo == 0) break;
       }
     } else {
       // kGraphIters iterations per graph; iterations after every problem
-      // has stopped find nothing to do (empty plans).  After each replay the
-      // host reads the problems' state; once the problems left need less
-      // than half the captured grids, the graph is captured again with
-      // grids for those problems only (the batch narrows fast: a few long
-      // problems run the last half of the iterations alone).
+      // has stopped find nothing to do (empty plans).  Each replay is
+      // enqueued before the host waits for the state after the previous
+      // one, so the host's reading never leaves the GPU idle; the replay
+      // enqueued after the last problem stopped runs empty.  Once the
+      // problems left need less than half the captured grids, the graph is
+      // captured again with grids for those problems only (the batch narrows
+      // fast: a few long problems run the last half of the iterations
+      // alone); the replaced graphs may still be running, so they are
+      // destroyed at the end.
       constexpr int kGraphIters = 8;
       hipStream_t cs = nullptr;
       hipGraph_t graph = nullptr;
       hipGraphExec_t exec = nullptr;
+      std::vector<std::pair<hipGraph_t, hipGraphExec_t>> retired;
+      hipEvent_t ev[2] = {nullptr, nullptr};
       int e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess;
+      for (hipEvent_t& x : ev)
+        e = e || hipEventCreateWithFlags(&x, hipEventDisableTiming) != hipSuccess;
       auto capture = [&]() -> int {
-        if (exec) (void)hipGraphExecDestroy(exec);
-        if (graph) (void)hipGraphDestroy(graph);
+        if (exec || graph) retired.emplace_back(graph, exec);
         exec = nullptr;
         graph = nullptr;
         if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return 1;
@@ -943,21 +988,27 @@ int qb_factor_batched(qb_problem* probs, int32_t count, void* workspace, size_t 
         if (ce || !ended) return 1;
         return hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess;
       };
+      // one replay and the copy of the state after it into hstate2[b]
+      auto replay = [&](int b) -> int {
+        return hipGraphLaunch(exec, st) != hipSuccess ||
+               hipMemcpyAsync(hstate2[b], L.dstate, st_bytes, hipMemcpyDeviceToHost, st) !=
+                   hipSuccess ||
+               hipEventRecord(ev[b], st) != hipSuccess;
+      };
       if (!e) e = capture();
-      hs.resize(count);
+      if (!e) e = replay(0);
+      int cur = 0;
       while (!e) {
         Range rrep("qb_batched_graph_replay");
-        if (hipGraphLaunch(exec, st) != hipSuccess ||
-            hipMemcpyAsync(hs.data(), L.dstate, count * sizeof(DevState), hipMemcpyDeviceToHost,
-                           st) != hipSuccess ||
-            hipStreamSynchronize(st) != hipSuccess) {
+        if (replay(cur ^ 1) || hipEventSynchronize(ev[cur]) != hipSuccess) {
           e = 1;
           break;
         }
+        const DevState* hsr = hstate2[cur];
         bool any = false;
         for (int i = 0; i < count; ++i) {
-          alive[i] = hs[i].active ? 1 : 0;
-          any = any || hs[i].active;
+          alive[i] = hsr[i].active ? 1 : 0;
+          any = any || hsr[i].active;
         }
         if (!any) break;
         int64_t old_grid[kSteps][kTileClasses], old_rgrid[kSteps], old_sk = skgrid;
@@ -972,9 +1023,18 @@ int qb_factor_batched(qb_problem* probs, int32_t count, void* workspace, size_t 
           std::memcpy(rgrid, old_rgrid, sizeof(rgrid));
           skgrid = old_sk;
         }
+        cur ^= 1;
+      }
+      // every replay has finished before anything is destroyed
+      if (hipStreamSynchronize(st) != hipSuccess) e = 1;
+      for (auto& ge : retired) {
+        if (ge.second) (void)hipGraphExecDestroy(ge.second);
+        if (ge.first) (void)hipGraphDestroy(ge.first);
       }
       if (exec) (void)hipGraphExecDestroy(exec);
       if (graph) (void)hipGraphDestroy(graph);
+      for (hipEvent_t x : ev)
+        if (x) (void)hipEventDestroy(x);
       if (cs) (void)hipStreamDestroy(cs);
       if (e) return QB_EHIP;
     }

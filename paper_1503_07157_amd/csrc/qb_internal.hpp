@@ -215,21 +215,22 @@ constexpr int kBatchRed = 1024;     // elements per workgroup of the split-K red
 // prof_id, flops, bytes: the profiler entry and the launch's algorithmic
 // flops (sum of 2 M N K) and bytes (sum of 8 (M K + K N + M N), M N twice
 // when C is also read).
-// total_tiles counts every (tile, depth chunk) workgroup.  Problems with
+// Units are (problem, tile, depth chunk) triples.  Problems with
 // ksplit > 1 leave C to gemm_batched_reduce, which sums their chunks in
 // order (alpha sum + beta C for NN, the sum for TN) with per-workgroup sums
 // of squares into sq when sq is set; total_rblocks counts its workgroups.
-// dev_total (optional): a device count of units that the launch's
-// total_tiles (or total_rblocks) workgroups share instead of one unit each
-// (the device-planned batch loop).
-// dev_next: the launch's unit counter (zeroed before the launch); the
-// workgroups take units from it one at a time.
+// dev_total: the device count of the launch's units, planned on the device;
+// total_tiles (total_rblocks) is an upper bound on it from the host (the
+// captured launch keeps its grid while the work shrinks).  Bounds up to 2^22
+// launch one workgroup per unit, the ones past the device count exiting at
+// once; larger bounds launch a fixed grid that takes units from dev_next,
+// the launch's unit counter (zeroed before the launch).  Both are required.
 int gemm_batched(int op, int cls, const BatchGemm* desc, int count, int64_t total_tiles,
                  int prof_id, double flops, double bytes, hipStream_t s,
-                 const int64_t* dev_total = nullptr, unsigned long long* dev_next = nullptr);
+                 const int64_t* dev_total, unsigned long long* dev_next);
 int gemm_batched_reduce(int op, const BatchGemm* desc, int count, int64_t total_rblocks,
-                        int prof_id, hipStream_t s, const int64_t* dev_total = nullptr,
-                        unsigned long long* dev_next = nullptr);
+                        int prof_id, hipStream_t s, const int64_t* dev_total,
+                        unsigned long long* dev_next);
 
 struct BatchChol {  // Cholesky with dropping + inverse of one w x w Gram matrix
   const double* G;
@@ -246,8 +247,9 @@ struct BatchSketch {  // columns [col0, col0 + w) of the n x inf sketch of seed
   int64_t block0;
   int32_t w;
 };
+// dev_total: the device count of units, walked in strides of the grid
 int sketch_batched(const BatchSketch* desc, int count, int64_t total_blocks, hipStream_t s,
-                   const int64_t* dev_total = nullptr);
+                   const int64_t* dev_total);
 int64_t sketch_blocks(int64_t n, int w);
 
 struct BatchConvert {  // R = double(A) (A float, m x n) with sums of squares and

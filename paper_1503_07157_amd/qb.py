@@ -300,38 +300,55 @@ def pivoted_qr(Q: torch.Tensor, B: torch.Tensor):
 def qb_factor_batched(As, eps, bs, seeds, kmax=None):
     """Batched QB of the float32 column-major device matrices As (list):
     eps, bs, seeds per problem (lists).  Returns a list of QBResult (no
-    trace), each with its own status."""
+    trace), each with its own status.  The outputs of all problems share two
+    device buffers (problem i's Q is m x kcap with ld m, its B kcap x n with
+    ld kcap, each at an offset 16-byte aligned); each result holds views of
+    its own part."""
     lib = _lib.load()
     count = len(As)
+    if count == 0:
+        return []
+    dev = As[0].device
     probs = (QBProblem * count)()
-    keep = []
+    shapes = []
+    offq = offb = 0
     for i, A in enumerate(As):
         if A.dtype != torch.float32:
             raise ValueError("qb_factor_batched takes float32 matrices")
+        if A.device != dev:
+            raise ValueError("qb_factor_batched takes matrices on one device")
         lda = _ld(A, "A", torch.float32)
         m, n = A.shape
         r = min(m, n)
-        kc = r if kmax is None else int(kmax[i])
-        Q = torch.empty((max(kc, 1), m), dtype=torch.float64, device=A.device).t()
-        B = torch.empty((n, max(kc, 1)), dtype=torch.float64, device=A.device).t()
-        keep.append((Q, B))
+        kc = r if kmax is None or int(kmax[i]) < 0 else int(kmax[i])
+        kq = max(kc, 1)
+        shapes.append((m, n, kq, offq, offb))
+        offq += (kq * m + 1) & ~1
+        offb += (kq * n + 1) & ~1
         p = probs[i]
         p.A, p.m, p.n, p.lda = A.data_ptr(), m, n, lda
         p.eps, p.seed, p.kmax = float(eps[i]), int(seeds[i]) & 0xFFFFFFFFFFFFFFFF, kc
-        p.Q, p.ldq, p.B, p.ldb = Q.data_ptr(), _ld(Q, "Q"), B.data_ptr(), _ld(B, "B")
+        p.ldq, p.ldb = max(m, 1), kq
         p.b = int(bs[i])
+    qbuf = torch.empty(max(offq, 1), dtype=torch.float64, device=dev)
+    bbuf = torch.empty(max(offb, 1), dtype=torch.float64, device=dev)
+    q0, b0 = qbuf.data_ptr(), bbuf.data_ptr()
+    for i, (m, n, kq, oq, ob) in enumerate(shapes):
+        probs[i].Q = q0 + 8 * oq
+        probs[i].B = b0 + 8 * ob
     need = int(lib.qb_factor_batched_workspace_bytes(probs, count))
     if need == 0:
         raise QBError(_lib.QB_EINVAL, "qb_factor_batched_workspace_bytes")
-    ws = _workspace(need, As[0].device)
-    _check(lib.qb_factor_batched(probs, count, _aligned_ptr(ws), need, _stream(As[0].device)),
+    ws = _workspace(need, dev)
+    _check(lib.qb_factor_batched(probs, count, _aligned_ptr(ws), need, _stream(dev)),
            "qb_factor_batched")
     out = []
-    for i in range(count):
+    for i, (m, n, kq, oq, ob) in enumerate(shapes):
         p = probs[i]
-        Q, B = keep[i]
         kk = int(p.k) if p.status >= 0 else 0
-        out.append(QBResult(Q=Q[:, :kk], B=B[:kk, :], k=kk, status=int(p.status),
+        Q = torch.as_strided(qbuf, (m, kk), (1, m), oq)
+        B = torch.as_strided(bbuf, (kk, n), (1, kq), ob)
+        out.append(QBResult(Q=Q, B=B, k=kk, status=int(p.status),
                             stop_reason=QB_STOP.get(p.stop_reason, str(p.stop_reason)),
                             normA2=p.normA2, indicator=float("nan"), resid2=p.resid2,
                             blocks=int(p.blocks), widths=[], E=[], D=[], R=None))
