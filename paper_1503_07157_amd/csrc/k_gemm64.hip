@@ -304,9 +304,37 @@ void launch_reduce(const double* part, int nz, int64_t ldp, double* out, int64_t
                      alpha, beta, tr ? 1 : 0, sq_part, sk, bm, bn);
 }
 
-// R -= Q B; per-workgroup sum of squares of the updated tile.
-// grid: (M tiles, N tiles)
-template <class S>
+// Tile order of the downdate: the eight XCDs (workgroup L runs on XCD
+// L % 8, each with its own 4 MB L2) take contiguous ranges of one sequence,
+// which runs over groups of G row tiles (kDdRows rows of R), each group
+// swept across all column tiles.  An XCD then holds its group's Q row
+// blocks (2 MB at depth 256) in L2 while the B column blocks stream past.
+// With the plain (row tile, column tile) grid every XCD walked every eighth
+// row tile of each column, touched 5 MB of Q row blocks per column at
+// b = 256 and fetched them again for the next: 3.0x the algorithmic bytes
+// per launch at 20000 x 16000 (FETCH_SIZE/WRITE_SIZE), 1.65x in this order.
+constexpr int64_t kDdRows = 1024;
+__device__ __forceinline__ bool dd_tile(int64_t L, int64_t tm, int64_t tn, int64_t G, int64_t* row,
+                                        int64_t* col) {
+  const int64_t total = tm * tn;
+  const int64_t per = (total + 7) >> 3;
+  const int64_t j = L >> 3;
+  const int64_t u = (L & 7) * per + j;
+  if (j >= per || u >= total) return false;
+  const int64_t span = G * tn;
+  const int64_t grp = u / span, w = u - grp * span;
+  const int64_t rows = tm - grp * G < G ? tm - grp * G : G;
+  *col = w / rows;
+  *row = grp * G + (w - *col * rows);
+  return true;
+}
+
+// R -= Q B; per-workgroup sum of squares of the updated tile, at index
+// row tile + column tile * (row tiles).  grid: 8 ceil(tiles / 8), one
+// dimension (dd_tile).  AHEAD: the R tile is read before the depth loop
+// (its latency overlaps the MFMA work; registers for the whole tile, so
+// 64 x 64 tiles only); else it is read in the epilogue.
+template <class S, bool AHEAD>
 __global__ __launch_bounds__(S::NT, S::OCC) void downdate_kernel(double* __restrict__ R, int64_t ldr,
                                                          const double* __restrict__ Qm,
                                                          int64_t ldq,
@@ -318,26 +346,34 @@ __global__ __launch_bounds__(S::NT, S::OCC) void downdate_kernel(double* __restr
   __shared__ __attribute__((aligned(16))) double As[2 * S::A_LDS];
   __shared__ __attribute__((aligned(16))) double Bs[2 * S::B_LDS];
   __shared__ double red[S::NT / 64];
-  const int64_t m0 = static_cast<int64_t>(blockIdx.x) * S::BM;
-  const int64_t n0 = static_cast<int64_t>(blockIdx.y) * S::BN;
-  // the R tile is read before the depth loop, so its latency overlaps the
-  // MFMA work
-  d4 rv[S::IB][S::JB];
+  const int64_t tm = (M + S::BM - 1) / S::BM, tn = (N + S::BN - 1) / S::BN;
+  int64_t tr = 0, tc = 0;
+  if (!dd_tile(blockIdx.x, tm, tn, kDdRows / S::BM, &tr, &tc)) return;
+  const int64_t m0 = tr * S::BM;
+  const int64_t n0 = tc * S::BN;
+  d4 rv[AHEAD ? S::IB : 1][S::JB];
+  if constexpr (AHEAD) {
 #pragma unroll
-  for (int i = 0; i < S::IB; ++i)
+    for (int i = 0; i < S::IB; ++i)
 #pragma unroll
-    for (int j = 0; j < S::JB; ++j)
-      rv[i][j] = load4(R, ldr, m0 + acc_row0<S>(i), n0 + acc_col<S>(j), M, N, vec_r);
+      for (int j = 0; j < S::JB; ++j)
+        rv[i][j] = load4(R, ldr, m0 + acc_row0<S>(i), n0 + acc_col<S>(j), M, N, vec_r);
+  }
   d4 acc[S::IB][S::JB];
   mma_loop<S, false>(Qm, ldq, B, ldb, m0, n0, M, N, 0, K, vec_ab != 0, As, Bs, acc);
   double sq = 0.0;
 #pragma unroll
   for (int i = 0; i < S::IB; ++i) {
     const int64_t row0 = m0 + acc_row0<S>(i);
+    if constexpr (!AHEAD) {
+#pragma unroll
+      for (int j = 0; j < S::JB; ++j)
+        rv[0][j] = load4(R, ldr, row0, n0 + acc_col<S>(j), M, N, vec_r);
+    }
 #pragma unroll
     for (int j = 0; j < S::JB; ++j) {
       const int64_t col = n0 + acc_col<S>(j);
-      const d4 v = rv[i][j] - acc[i][j];
+      const d4 v = rv[AHEAD ? i : 0][j] - acc[i][j];
       store4(R, ldr, row0, col, M, N, vec_r, v);
 #pragma unroll
       for (int r = 0; r < 4; ++r)
@@ -345,7 +381,7 @@ __global__ __launch_bounds__(S::NT, S::OCC) void downdate_kernel(double* __restr
     }
   }
   const double tot = block_sum(sq, red);
-  if (threadIdx.x == 0) sq_part[blockIdx.x + static_cast<int64_t>(blockIdx.y) * gridDim.x] = tot;
+  if (threadIdx.x == 0) sq_part[tr + tc * tm] = tot;
 }
 
 int64_t part_ld(int64_t M) { return (M + 1) & ~int64_t(1); }
@@ -573,7 +609,7 @@ int gemm_tn(const double* Qm, int64_t ldq, const double* X, int64_t ldx, double*
   return kOk;
 }
 
-size_t downdate_partials(int64_t M, int64_t N) {
+size_t downdate_partials(int64_t M, int64_t N) {  // the most tiles: 64 x 64
   return static_cast<size_t>(cdiv(M, Small::BM)) * static_cast<size_t>(cdiv(N, Small::BN));
 }
 
@@ -581,20 +617,31 @@ int downdate(double* R, int64_t ldr, const double* Qm, int64_t ldq, const double
              int64_t M, int64_t N, int64_t K, double* sq_part, int* sq_count, hipStream_t s) {
   if (M <= 0 || N <= 0) { if (sq_count) *sq_count = 0; return kOk; }
   if (!ld_fits(ldq) || !ld_fits(ldb)) return kEInval;
-  // 64 x 64 tiles, each reading its R tile ahead of the depth loop
-  // (measured per 10^4 x 10^4 factorisation: 51.7 -> 49.1 ms against
-  // 128 x 128 tiles with R read in the epilogue; larger tiles reading
-  // ahead were slower)
-  if (cdiv(M, Small::BM) > INT32_MAX || cdiv(N, Small::BN) > 65535) return kEInval;
-  const dim3 grid(static_cast<unsigned>(cdiv(M, Small::BM)),
-                  static_cast<unsigned>(cdiv(N, Small::BN)));
+  // Shallow updates (K < 192): 64 x 64 tiles, each reading its R tile ahead
+  // of the depth loop (measured per 10^4 x 10^4 factorisation at b = 128:
+  // 51.7 -> 49.1 ms against 128 x 128 tiles with R read in the epilogue).
+  // Deep ones with tiles for every CU: 128 x 128 tiles, two workgroups per
+  // CU, R read in the epilogue (one workgroup's epilogue overlaps the other's
+  // depth loop): 204 -> 198 ms of downdates per 20000 x 16000 factorisation
+  // at b = 256, where 256 x 128 tiles (one workgroup per CU, nothing to
+  // hide the epilogue behind) took 217 ms.
+  const bool deep = K >= 192 && cdiv(M, Big::BM) * cdiv(N, Big::BN) >= 4 * kNumCU;
+  const int64_t tiles = deep ? cdiv(M, Big::BM) * cdiv(N, Big::BN)
+                             : cdiv(M, Small::BM) * cdiv(N, Small::BN);
+  if (tiles > INT32_MAX - 8) return kEInval;
+  const dim3 grid(static_cast<unsigned>(8 * cdiv(tiles, 8)));  // dd_tile
   {
     ProfScope ps(kKDowndate, 2.0 * M * N * K, 8.0 * (2 * M * N + M * K + K * N), s);
-    hipLaunchKernelGGL(downdate_kernel<Small>, grid, dim3(Small::NT), 0, s, R, ldr, Qm, ldq, B,
-                       ldb, M, N, K, sq_part, vec_ok(R, ldr), vec_ok(Qm, ldq) & vec_ok(B, ldb));
+    const int vr = vec_ok(R, ldr), vab = vec_ok(Qm, ldq) & vec_ok(B, ldb);
+    if (deep)
+      hipLaunchKernelGGL((downdate_kernel<Big, false>), grid, dim3(Big::NT), 0, s, R, ldr, Qm,
+                         ldq, B, ldb, M, N, K, sq_part, vr, vab);
+    else
+      hipLaunchKernelGGL((downdate_kernel<Small, true>), grid, dim3(Small::NT), 0, s, R, ldr, Qm,
+                         ldq, B, ldb, M, N, K, sq_part, vr, vab);
   }
   QB_HIP_TRY(hipGetLastError());
-  if (sq_count) *sq_count = static_cast<int>(grid.x * grid.y);
+  if (sq_count) *sq_count = static_cast<int>(tiles);
   return kOk;
 }
 
