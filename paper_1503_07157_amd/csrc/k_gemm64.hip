@@ -493,9 +493,9 @@ int choose_split(int64_t M, int64_t N, int64_t K, int slots_per_cu, bool tall_nn
 // workgroups fill their last round of slots best (ties to the smaller).
 // 314 tiles on 512 slots (Y = R Omega at 20000 x 256): 1 and 2 fill 61 %,
 // 3 fills 92 %.
-int choose_split_fill(int64_t M, int64_t N, int64_t K, int slots_per_cu) {
+int choose_split_fill(int64_t M, int64_t N, int64_t K, int slots_per_cu, int bm, int bn) {
   const int64_t slots = int64_t(kNumCU) * slots_per_cu;
-  const int64_t tiles = cdiv(M, kTileM) * cdiv(N, kTileN);
+  const int64_t tiles = cdiv(M, bm) * cdiv(N, bn);
   int64_t lim = K / kSplitMinDepth;
   const int64_t by_mem = kPartialCapDoubles / ((M * N > 0) ? M * N : 1);
   if (lim > by_mem) lim = by_mem;

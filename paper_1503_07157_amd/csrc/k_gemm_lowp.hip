@@ -18,6 +18,17 @@
 //   f32 16x16x4    A lane l: A[l % 16][l / 16];   B lane l: B[l / 16][l % 16]
 //   bf16 16x16x32  A lane l: A[l % 16][8 (l / 16) + i], i < 8;
 //                  B lane l: B[8 (l / 16) + i][l % 16]
+//
+// Tiles: eight waves of 64 x 64 each, the panel side of the tile covering
+// the whole panel so that X (the residual) is read once: Y = X W takes
+// 128 x 256 tiles for panels W of 129..256 columns and 256 x 128 for
+// narrower ones; C = Q^T X takes 256 x 128 for panels Q of 129..256 columns
+// and 128 x 256 for narrower ones.  With 128 x 128 tiles a 256-wide panel read
+// the residual twice (counters at 20000 x 16000: 2.15x the algorithmic
+// bytes).  Operands move as 16-byte pairs of doubles, are rounded while
+// they are written to LDS, and two LDS stages let the next depth slice be
+// loaded and stored while the current one is multiplied (one barrier per
+// slice).
 #include "qb_internal.hpp"
 
 namespace qb {
@@ -25,186 +36,243 @@ namespace {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
-
-constexpr int BM = 128, BN = 128, NT = 256;
+typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+typedef float fl2 __attribute__((ext_vector_type(2)));
 
 template <int PREC>
-struct Cfg;
+struct Elem;
 template <>
-struct Cfg<1> {  // f32
-  static constexpr int BK = 16;
-  static constexpr int SK = BK + 1;  // floats per LDS row (k contiguous)
+struct Elem<1> {  // f32: 16 depth indices per slice, 18 floats per LDS row
+  static constexpr int BK = 16, SK = 18;
 };
 template <>
-struct Cfg<2> {  // bf16x3
-  static constexpr int BK = 32;
-  static constexpr int SK = 40;      // bf16 per LDS row: 80-byte stride
+struct Elem<2> {  // bf16x3: 32 depth indices per slice, 40 bf16 (80 bytes) per LDS row
+  static constexpr int BK = 32, SK = 40;
 };
 
-// global operand (m, k) element address helper
-template <bool KCONTIG>
-__device__ __forceinline__ double load_op(const double* __restrict__ X, int64_t ld, int64_t r,
-                                          int64_t kk, bool ok) {
-  if (!ok) return 0.0;
-  return KCONTIG ? X[kk + r * ld] : X[r + kk * ld];
+template <int PREC, int BM_, int BN_, int WGM_, int WGN_>
+struct LShape {
+  static constexpr int BM = BM_, BN = BN_, WGM = WGM_, WGN = WGN_;
+  static constexpr int NT = 64 * WGM * WGN;
+  static constexpr int WM = BM / WGM, WN = BN / WGN, IB = WM / 16, JB = WN / 16;
+  static constexpr int BK = Elem<PREC>::BK, SK = Elem<PREC>::SK;
+  // double pairs per thread per slice, of A (BM x BK) and of B (BN x BK)
+  static constexpr int PA = BM * BK / (2 * NT), PB = BN * BK / (2 * NT);
+  // LDS bytes of one stage: f32 A, B; bf16x3 A hi, A lo, B hi, B lo
+  static constexpr int STAGE = PREC == 1 ? (BM + BN) * SK * 4 : 2 * (BM + BN) * SK * 2;
+  static_assert(PA >= 1 && PB >= 1 && PA * 2 * NT == BM * BK && PB * 2 * NT == BN * BK,
+                "whole pairs per thread");
+  static_assert(WM == 64 && WN == 64, "64 x 64 per wave");
+};
+template <int PREC>
+using NNS = LShape<PREC, 128, 256, 2, 4>;
+template <int PREC>
+using TNS = LShape<PREC, 256, 128, 4, 2>;
+
+__device__ __forceinline__ double2 ld_pair(const double* p, bool ok0, bool ok1, bool vec) {
+  if (vec && ok0 && ok1) return *reinterpret_cast<const double2*>(p);
+  double2 v = make_double2(0.0, 0.0);
+  if (ok0) v.x = p[0];
+  if (ok1) v.y = p[1];
+  return v;
 }
 
-// C tile (BM x BN) accumulated over k in [kbeg, kend); A is M x K (m- or
-// k-contiguous in global memory), B is K x N with k contiguous.
-template <int PREC, bool A_KCONTIG>
+__device__ __forceinline__ void split_bf16(double x, __bf16& hi, __bf16& lo) {
+  hi = static_cast<__bf16>(static_cast<float>(x));
+  lo = static_cast<__bf16>(static_cast<float>(x - static_cast<double>(static_cast<float>(hi))));
+}
+
+// Accumulate the BM x BN tile over k in [kbeg, kend).  A is M x K, element
+// (m, k) at A[m + k lda] (m-contiguous) or A[k + m lda] (A_KCONTIG); B is
+// K x N, element (k, n) at B[k + n ldb].  vec: both operands allow 16-byte
+// pair loads (16-byte aligned base, even ld).
+template <int PREC, class S, bool A_KCONTIG>
 __device__ __forceinline__ void lowp_loop(const double* __restrict__ A, int64_t lda,
                                           const double* __restrict__ Bm, int64_t ldb, int64_t m0,
                                           int64_t n0, int64_t M, int64_t N, int64_t kbeg,
-                                          int64_t kend, char* smem, f4 acc[4][4]) {
-  constexpr int BK = Cfg<PREC>::BK, SK = Cfg<PREC>::SK;
-  constexpr int PER = (BM * BK) / NT;  // elements of each operand per thread per fill
+                                          int64_t kend, bool vec, char* smem,
+                                          f4 (&acc)[S::IB][S::JB]) {
+  constexpr int BK = S::BK, SK = S::SK, NT = S::NT;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int wm = (wave & 1) * 64, wn = (wave >> 1) * 64;
+  const int wm = (wave % S::WGM) * S::WM, wn = (wave / S::WGM) * S::WN;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < S::IB; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = (f4){0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < S::JB; ++j) acc[i][j] = (f4){0.f, 0.f, 0.f, 0.f};
   if (kbeg >= kend) return;
 
-  double ra[PER], rb[PER];
+  double2 ra[S::PA], rb[S::PB];
   auto gload = [&](int64_t kc) {
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
+    for (int q = 0; q < S::PA; ++q) {
       const int e = t + NT * q;
-      int mi, ki;
-      if (A_KCONTIG) { ki = e % BK; mi = e / BK; } else { mi = e % BM; ki = e / BM; }
-      const int64_t gm = m0 + mi, gk = kc + ki;
-      ra[q] = load_op<A_KCONTIG>(A, lda, gm, gk, gm < M && gk < kend);
-      const int kb = e % BK, nb = e / BK;
-      const int64_t gn = n0 + nb, gkb = kc + kb;
-      rb[q] = load_op<true>(Bm, ldb, gn, gkb, gn < N && gkb < kend);
+      if (A_KCONTIG) {  // pair (row r, depth 2 kp .. 2 kp + 1)
+        const int kp = e % (BK / 2), r = e / (BK / 2);
+        const int64_t gm = m0 + r, gk = kc + 2 * kp;
+        ra[q] = ld_pair(A + gk + gm * lda, gm < M && gk < kend, gm < M && gk + 1 < kend, vec);
+      } else {          // pair (rows 2 rp .. 2 rp + 1, depth kk)
+        const int rp = e % (S::BM / 2), kk = e / (S::BM / 2);
+        const int64_t gm = m0 + 2 * rp, gk = kc + kk;
+        ra[q] = ld_pair(A + gm + gk * lda, gm < M && gk < kend, gm + 1 < M && gk < kend, vec);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < S::PB; ++q) {
+      const int e = t + NT * q;
+      const int kp = e % (BK / 2), c = e / (BK / 2);
+      const int64_t gn = n0 + c, gk = kc + 2 * kp;
+      rb[q] = ld_pair(Bm + gk + gn * ldb, gn < N && gk < kend, gn < N && gk + 1 < kend, vec);
     }
   };
 
   if constexpr (PREC == 1) {
-    float* As = reinterpret_cast<float*>(smem);
-    float* Bs = As + BM * SK;
-    auto sstore = [&]() {
+    auto sstore = [&](int stage) {
+      float* As = reinterpret_cast<float*>(smem + stage * S::STAGE);
+      float* Bs = As + S::BM * SK;
 #pragma unroll
-      for (int q = 0; q < PER; ++q) {
+      for (int q = 0; q < S::PA; ++q) {
         const int e = t + NT * q;
-        int mi, ki;
-        if (A_KCONTIG) { ki = e % BK; mi = e / BK; } else { mi = e % BM; ki = e / BM; }
-        As[mi * SK + ki] = static_cast<float>(ra[q]);
-        Bs[(e / BK) * SK + (e % BK)] = static_cast<float>(rb[q]);
+        if (A_KCONTIG) {
+          const int kp = e % (BK / 2), r = e / (BK / 2);
+          *reinterpret_cast<fl2*>(As + r * SK + 2 * kp) =
+              (fl2){static_cast<float>(ra[q].x), static_cast<float>(ra[q].y)};
+        } else {
+          const int rp = e % (S::BM / 2), kk = e / (S::BM / 2);
+          As[(2 * rp) * SK + kk] = static_cast<float>(ra[q].x);
+          As[(2 * rp + 1) * SK + kk] = static_cast<float>(ra[q].y);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < S::PB; ++q) {
+        const int e = t + NT * q;
+        const int kp = e % (BK / 2), c = e / (BK / 2);
+        *reinterpret_cast<fl2*>(Bs + c * SK + 2 * kp) =
+            (fl2){static_cast<float>(rb[q].x), static_cast<float>(rb[q].y)};
       }
     };
-    gload(kbeg);
-    sstore();
-    __syncthreads();
-    for (int64_t kc = kbeg; kc < kend; kc += BK) {
-      const bool more = kc + BK < kend;
-      if (more) gload(kc + BK);
+    auto compute = [&](int stage) {
+      const float* As = reinterpret_cast<const float*>(smem + stage * S::STAGE);
+      const float* Bs = As + S::BM * SK;
 #pragma unroll
       for (int k4 = 0; k4 < BK / 4; ++k4) {
         const int kq = 4 * k4 + (lane >> 4);
-        float a[4], b[4];
+        float a[S::IB], b[S::JB];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) a[i] = As[(wm + 16 * i + (lane & 15)) * SK + kq];
+        for (int i = 0; i < S::IB; ++i) a[i] = As[(wm + 16 * i + (lane & 15)) * SK + kq];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) b[j] = Bs[(wn + 16 * j + (lane & 15)) * SK + kq];
+        for (int j = 0; j < S::JB; ++j) b[j] = Bs[(wn + 16 * j + (lane & 15)) * SK + kq];
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < S::IB; ++i)
 #pragma unroll
-          for (int j = 0; j < 4; ++j)
+          for (int j = 0; j < S::JB; ++j)
             acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
-      }
-      __syncthreads();
-      if (more) {
-        sstore();
-        __syncthreads();
-      }
-    }
-  } else {
-    __bf16* Ah = reinterpret_cast<__bf16*>(smem);
-    __bf16* Al = Ah + BM * SK;
-    __bf16* Bh = Al + BM * SK;
-    __bf16* Bl = Bh + BN * SK;
-    auto sstore = [&]() {
-#pragma unroll
-      for (int q = 0; q < PER; ++q) {
-        const int e = t + NT * q;
-        int mi, ki;
-        if (A_KCONTIG) { ki = e % BK; mi = e / BK; } else { mi = e % BM; ki = e / BM; }
-        const __bf16 ah = static_cast<__bf16>(static_cast<float>(ra[q]));
-        const __bf16 al = static_cast<__bf16>(static_cast<float>(ra[q] - static_cast<double>(static_cast<float>(ah))));
-        Ah[mi * SK + ki] = ah;
-        Al[mi * SK + ki] = al;
-        const __bf16 bh = static_cast<__bf16>(static_cast<float>(rb[q]));
-        const __bf16 bl = static_cast<__bf16>(static_cast<float>(rb[q] - static_cast<double>(static_cast<float>(bh))));
-        const int o = (e / BK) * SK + (e % BK);
-        Bh[o] = bh;
-        Bl[o] = bl;
       }
     };
     gload(kbeg);
-    sstore();
+    sstore(0);
     __syncthreads();
+    int stage = 0;
     for (int64_t kc = kbeg; kc < kend; kc += BK) {
       const bool more = kc + BK < kend;
       if (more) gload(kc + BK);
-      const int k8 = 8 * (lane >> 4);
-      bf8 bh[4], bl[4];
+      compute(stage);
+      if (more) sstore(stage ^ 1);
+      __syncthreads();
+      stage ^= 1;
+    }
+  } else {
+    auto sstore = [&](int stage) {
+      __bf16* Ah = reinterpret_cast<__bf16*>(smem + stage * S::STAGE);
+      __bf16* Al = Ah + S::BM * SK;
+      __bf16* Bh = Al + S::BM * SK;
+      __bf16* Bl = Bh + S::BN * SK;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
+      for (int q = 0; q < S::PA; ++q) {
+        const int e = t + NT * q;
+        __bf16 h0, l0, h1, l1;
+        split_bf16(ra[q].x, h0, l0);
+        split_bf16(ra[q].y, h1, l1);
+        if (A_KCONTIG) {
+          const int kp = e % (BK / 2), r = e / (BK / 2);
+          *reinterpret_cast<bf2*>(Ah + r * SK + 2 * kp) = (bf2){h0, h1};
+          *reinterpret_cast<bf2*>(Al + r * SK + 2 * kp) = (bf2){l0, l1};
+        } else {
+          const int rp = e % (S::BM / 2), kk = e / (S::BM / 2);
+          Ah[(2 * rp) * SK + kk] = h0;
+          Al[(2 * rp) * SK + kk] = l0;
+          Ah[(2 * rp + 1) * SK + kk] = h1;
+          Al[(2 * rp + 1) * SK + kk] = l1;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < S::PB; ++q) {
+        const int e = t + NT * q;
+        const int kp = e % (BK / 2), c = e / (BK / 2);
+        __bf16 h0, l0, h1, l1;
+        split_bf16(rb[q].x, h0, l0);
+        split_bf16(rb[q].y, h1, l1);
+        *reinterpret_cast<bf2*>(Bh + c * SK + 2 * kp) = (bf2){h0, h1};
+        *reinterpret_cast<bf2*>(Bl + c * SK + 2 * kp) = (bf2){l0, l1};
+      }
+    };
+    auto compute = [&](int stage) {
+      const __bf16* Ah = reinterpret_cast<const __bf16*>(smem + stage * S::STAGE);
+      const __bf16* Al = Ah + S::BM * SK;
+      const __bf16* Bh = Al + S::BM * SK;
+      const __bf16* Bl = Bh + S::BN * SK;
+      const int k8 = 8 * (lane >> 4);
+      bf8 bh[S::JB], bl[S::JB];
+#pragma unroll
+      for (int j = 0; j < S::JB; ++j) {
         const int col = wn + 16 * j + (lane & 15);
         bh[j] = *reinterpret_cast<const bf8*>(Bh + col * SK + k8);
         bl[j] = *reinterpret_cast<const bf8*>(Bl + col * SK + k8);
       }
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
+      for (int i = 0; i < S::IB; ++i) {
         const int row = wm + 16 * i + (lane & 15);
         const bf8 ah = *reinterpret_cast<const bf8*>(Ah + row * SK + k8);
         const bf8 al = *reinterpret_cast<const bf8*>(Al + row * SK + k8);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < S::JB; ++j) {
           // small terms first so they are not absorbed by the large one
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[j], acc[i][j], 0, 0, 0);
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[j], acc[i][j], 0, 0, 0);
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[j], acc[i][j], 0, 0, 0);
         }
       }
+    };
+    gload(kbeg);
+    sstore(0);
+    __syncthreads();
+    int stage = 0;
+    for (int64_t kc = kbeg; kc < kend; kc += BK) {
+      const bool more = kc + BK < kend;
+      if (more) gload(kc + BK);
+      compute(stage);
+      if (more) sstore(stage ^ 1);
       __syncthreads();
-      if (more) {
-        sstore();
-        __syncthreads();
-      }
+      stage ^= 1;
     }
   }
 }
 
-template <int PREC>
-constexpr int smem_bytes() {
-  return PREC == 1 ? (BM + BN) * Cfg<1>::SK * 4 : 2 * (BM + BN) * Cfg<2>::SK * 2;
-}
-
-__device__ __forceinline__ int acc_row(int i, int r) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  return (wave & 1) * 64 + 16 * i + 4 * (lane >> 4) + r;
-}
-__device__ __forceinline__ int acc_col(int j) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  return (wave >> 1) * 64 + 16 * j + (lane & 15);
-}
-
-// out tile -> partial buffer part[z] (rows x cols, ld = rows) or, when
-// part is null, directly to out (ld, optional transposed store)
-__device__ __forceinline__ void store_tile(const f4 acc[4][4], int64_t m0, int64_t n0, int64_t M,
-                                           int64_t N, double* __restrict__ part,
+// out tile -> partial buffer part[z] (M x N, ld = M) or, when part is null,
+// directly to out (ld, optional transposed store)
+template <class S>
+__device__ __forceinline__ void store_tile(const f4 (&acc)[S::IB][S::JB], int64_t m0, int64_t n0,
+                                           int64_t M, int64_t N, double* __restrict__ part,
                                            double* __restrict__ out, int64_t ldo, int transpose) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = (wave % S::WGM) * S::WM, wn = (wave / S::WGM) * S::WN;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < S::IB; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int64_t col = n0 + acc_col(j);
+    for (int j = 0; j < S::JB; ++j) {
+      const int64_t col = n0 + wn + 16 * j + (lane & 15);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t row = m0 + acc_row(i, r);
+        const int64_t row = m0 + wm + 16 * i + 4 * (lane >> 4) + r;
         if (row < M && col < N) {
           const double v = static_cast<double>(acc[i][j][r]);
           if (part != nullptr) part[static_cast<int64_t>(blockIdx.z) * M * N + row + col * M] = v;
@@ -215,40 +283,37 @@ __device__ __forceinline__ void store_tile(const f4 acc[4][4], int64_t m0, int64
     }
 }
 
-// Y = X W (X m-contiguous).  grid (M tiles, N tiles, split).  The bf16x3
-// form holds 32 prefetched doubles per thread and runs one workgroup per CU.
-template <int PREC>
-__global__ __launch_bounds__(NT, PREC == 2 ? 1 : 2) void lowp_nn_kernel(const double* __restrict__ X, int64_t ldx,
-                                                        const double* __restrict__ W, int64_t ldw,
-                                                        double* __restrict__ Y, int64_t ldy,
-                                                        int64_t M, int64_t N, int64_t K,
-                                                        int64_t kchunk, double* __restrict__ part) {
-  __shared__ __attribute__((aligned(16))) char smem[smem_bytes<PREC>()];
-  const int64_t m0 = static_cast<int64_t>(blockIdx.x) * BM;
-  const int64_t n0 = static_cast<int64_t>(blockIdx.y) * BN;
+// Y = X W (X m-contiguous).  grid (M tiles, N tiles, split).
+template <int PREC, class S>
+__global__ __launch_bounds__(S::NT, 1) void lowp_nn_kernel(
+    const double* __restrict__ X, int64_t ldx, const double* __restrict__ W, int64_t ldw,
+    double* __restrict__ Y, int64_t ldy, int64_t M, int64_t N, int64_t K, int64_t kchunk,
+    int vec, double* __restrict__ part) {
+  __shared__ __attribute__((aligned(16))) char smem[2 * S::STAGE];
+  const int64_t m0 = static_cast<int64_t>(blockIdx.x) * S::BM;
+  const int64_t n0 = static_cast<int64_t>(blockIdx.y) * S::BN;
   const int64_t kbeg = static_cast<int64_t>(blockIdx.z) * kchunk;
   const int64_t kend = (kbeg + kchunk < K) ? kbeg + kchunk : K;
-  f4 acc[4][4];
-  lowp_loop<PREC, false>(X, ldx, W, ldw, m0, n0, M, N, kbeg, kend, smem, acc);
-  store_tile(acc, m0, n0, M, N, part, Y, ldy, 0);
+  f4 acc[S::IB][S::JB];
+  lowp_loop<PREC, S, false>(X, ldx, W, ldw, m0, n0, M, N, kbeg, kend, vec != 0, smem, acc);
+  store_tile<S>(acc, m0, n0, M, N, part, Y, ldy, 0);
 }
 
-// C = Q^T X (Q: K x P, so the A operand is k-contiguous).  grid (N tiles, P tiles, split)
-template <int PREC>
-__global__ __launch_bounds__(NT, 2) void lowp_tn_kernel(const double* __restrict__ Qm, int64_t ldq,
-                                                        const double* __restrict__ X, int64_t ldx,
-                                                        double* __restrict__ C, int64_t ldc,
-                                                        int64_t P, int64_t N, int64_t K,
-                                                        int64_t kchunk, int transpose,
-                                                        double* __restrict__ part) {
-  __shared__ __attribute__((aligned(16))) char smem[smem_bytes<PREC>()];
-  const int64_t n0 = static_cast<int64_t>(blockIdx.x) * BN;
-  const int64_t m0 = static_cast<int64_t>(blockIdx.y) * BM;
+// C = Q^T X (Q: K x P, so the A operand is k-contiguous).  grid (N tiles,
+// P tiles, split)
+template <int PREC, class S>
+__global__ __launch_bounds__(S::NT, 1) void lowp_tn_kernel(
+    const double* __restrict__ Qm, int64_t ldq, const double* __restrict__ X, int64_t ldx,
+    double* __restrict__ C, int64_t ldc, int64_t P, int64_t N, int64_t K, int64_t kchunk,
+    int transpose, int vec, double* __restrict__ part) {
+  __shared__ __attribute__((aligned(16))) char smem[2 * S::STAGE];
+  const int64_t n0 = static_cast<int64_t>(blockIdx.x) * S::BN;
+  const int64_t m0 = static_cast<int64_t>(blockIdx.y) * S::BM;
   const int64_t kbeg = static_cast<int64_t>(blockIdx.z) * kchunk;
   const int64_t kend = (kbeg + kchunk < K) ? kbeg + kchunk : K;
-  f4 acc[4][4];
-  lowp_loop<PREC, true>(Qm, ldq, X, ldx, m0, n0, P, N, kbeg, kend, smem, acc);
-  store_tile(acc, m0, n0, P, N, part, C, ldc, transpose);
+  f4 acc[S::IB][S::JB];
+  lowp_loop<PREC, S, true>(Qm, ldq, X, ldx, m0, n0, P, N, kbeg, kend, vec != 0, smem, acc);
+  store_tile<S>(acc, m0, n0, P, N, part, C, ldc, transpose);
 }
 
 // out = sum_s part[s] (fixed order), optional transposed store
@@ -272,20 +337,25 @@ int64_t chunk_for(int64_t K, int split, int bk) {
   return cdiv(c, bk) * bk;
 }
 
-template <int PREC>
+int pair_ok(const double* p, int64_t ld) {
+  return ((reinterpret_cast<uintptr_t>(p) & 15) == 0 && (ld & 1) == 0) ? 1 : 0;
+}
+
+template <int PREC, class S>
 int nn_impl(const double* X, int64_t ldx, const double* W, int64_t ldw, double* Y, int64_t ldy,
             int64_t M, int64_t N, int64_t K, int split, double* part, hipStream_t s) {
   if (M <= 0 || N <= 0) return kOk;
   if (K <= 0) return zero_matrix(Y, ldy, M, N, s);
   if (split > 1 && part == nullptr) return kEInval;
-  const int64_t kc = split > 1 ? chunk_for(K, split, Cfg<PREC>::BK) : K;
+  const int64_t kc = split > 1 ? chunk_for(K, split, S::BK) : K;
   const int nz = split > 1 ? static_cast<int>(cdiv(K, kc)) : 1;
-  dim3 grid(static_cast<unsigned>(cdiv(M, BM)), static_cast<unsigned>(cdiv(N, BN)),
+  dim3 grid(static_cast<unsigned>(cdiv(M, S::BM)), static_cast<unsigned>(cdiv(N, S::BN)),
             static_cast<unsigned>(nz));
   {
     ProfScope ps(kKGemmNNLowp, 2.0 * M * N * K * (PREC == 2 ? 3 : 1), 8.0 * (M * K + K * N + M * N), s);
-    hipLaunchKernelGGL(lowp_nn_kernel<PREC>, grid, dim3(NT), 0, s, X, ldx, W, ldw, Y, ldy, M, N,
-                       K, kc, nz > 1 ? part : static_cast<double*>(nullptr));
+    hipLaunchKernelGGL((lowp_nn_kernel<PREC, S>), grid, dim3(S::NT), 0, s, X, ldx, W, ldw, Y, ldy, M,
+                       N, K, kc, pair_ok(X, ldx) & pair_ok(W, ldw),
+                       nz > 1 ? part : static_cast<double*>(nullptr));
   }
   QB_HIP_TRY(hipGetLastError());
   if (nz > 1) {
@@ -298,20 +368,21 @@ int nn_impl(const double* X, int64_t ldx, const double* W, int64_t ldw, double* 
   return kOk;
 }
 
-template <int PREC>
+template <int PREC, class S>
 int tn_impl(const double* Qm, int64_t ldq, const double* X, int64_t ldx, double* C, int64_t ldc,
             int64_t P, int64_t N, int64_t K, bool tr, int split, double* part, hipStream_t s) {
   if (P <= 0 || N <= 0) return kOk;
   if (K <= 0) return tr ? zero_matrix(C, ldc, N, P, s) : zero_matrix(C, ldc, P, N, s);
   if (split > 1 && part == nullptr) return kEInval;
-  const int64_t kc = split > 1 ? chunk_for(K, split, Cfg<PREC>::BK) : K;
+  const int64_t kc = split > 1 ? chunk_for(K, split, S::BK) : K;
   const int nz = split > 1 ? static_cast<int>(cdiv(K, kc)) : 1;
-  dim3 grid(static_cast<unsigned>(cdiv(N, BN)), static_cast<unsigned>(cdiv(P, BM)),
+  dim3 grid(static_cast<unsigned>(cdiv(N, S::BN)), static_cast<unsigned>(cdiv(P, S::BM)),
             static_cast<unsigned>(nz));
   {
     ProfScope ps(kKGemmTNLowp, 2.0 * P * N * K * (PREC == 2 ? 3 : 1), 8.0 * (K * P + K * N + P * N), s);
-    hipLaunchKernelGGL(lowp_tn_kernel<PREC>, grid, dim3(NT), 0, s, Qm, ldq, X, ldx, C, ldc, P, N,
-                       K, kc, tr ? 1 : 0, nz > 1 ? part : static_cast<double*>(nullptr));
+    hipLaunchKernelGGL((lowp_tn_kernel<PREC, S>), grid, dim3(S::NT), 0, s, Qm, ldq, X, ldx, C, ldc, P,
+                       N, K, kc, tr ? 1 : 0, pair_ok(Qm, ldq) & pair_ok(X, ldx),
+                       nz > 1 ? part : static_cast<double*>(nullptr));
   }
   QB_HIP_TRY(hipGetLastError());
   if (nz > 1) {
@@ -326,21 +397,42 @@ int tn_impl(const double* Qm, int64_t ldq, const double* X, int64_t ldx, double*
 
 }  // namespace
 
+int lowp_split(int precision, bool nn, int64_t M, int64_t N, int64_t K) {
+  // one eight-wave workgroup per CU in both precisions (bf16x3: two 61 KB
+  // LDS stages; f32: about 145 VGPRs, so two waves per SIMD)
+  (void)precision;
+  const bool wide_tile = nn ? N > TNS<1>::BN : M <= NNS<1>::BM;  // 128 x 256
+  if (wide_tile) return choose_split_fill(M, N, K, 1, NNS<1>::BM, NNS<1>::BN);
+  return choose_split_fill(M, N, K, 1, TNS<1>::BM, TNS<1>::BN);
+}
+
 int gemm_nn_lowp(int precision, const double* X, int64_t ldx, const double* W, int64_t ldw,
                  double* Y, int64_t ldy, int64_t M, int64_t N, int64_t K, int split,
                  double* part, hipStream_t s) {
-  if (precision == 1) return nn_impl<1>(X, ldx, W, ldw, Y, ldy, M, N, K, split, part, s);
-  if (precision == 2) return nn_impl<2>(X, ldx, W, ldw, Y, ldy, M, N, K, split, part, s);
+  // panels up to 128 wide take 256 x 128 tiles (a 128 x 256 tile would
+  // multiply half a tile of zeros)
+  const bool narrow = N <= TNS<1>::BN;
+  if (precision == 1)
+    return narrow ? nn_impl<1, TNS<1>>(X, ldx, W, ldw, Y, ldy, M, N, K, split, part, s)
+                  : nn_impl<1, NNS<1>>(X, ldx, W, ldw, Y, ldy, M, N, K, split, part, s);
+  if (precision == 2)
+    return narrow ? nn_impl<2, TNS<2>>(X, ldx, W, ldw, Y, ldy, M, N, K, split, part, s)
+                  : nn_impl<2, NNS<2>>(X, ldx, W, ldw, Y, ldy, M, N, K, split, part, s);
   return kEInval;
 }
 
 int gemm_tn_lowp(int precision, const double* Qm, int64_t ldq, const double* X, int64_t ldx,
                  double* C, int64_t ldc, int64_t P, int64_t N, int64_t K, bool transpose_out,
                  int split, double* part, hipStream_t s) {
+  // panels Q up to 128 wide take 128 x 256 tiles (a 256-row tile would
+  // multiply half a tile of zeros)
+  const bool narrow = P <= NNS<1>::BM;
   if (precision == 1)
-    return tn_impl<1>(Qm, ldq, X, ldx, C, ldc, P, N, K, transpose_out, split, part, s);
+    return narrow ? tn_impl<1, NNS<1>>(Qm, ldq, X, ldx, C, ldc, P, N, K, transpose_out, split, part, s)
+                  : tn_impl<1, TNS<1>>(Qm, ldq, X, ldx, C, ldc, P, N, K, transpose_out, split, part, s);
   if (precision == 2)
-    return tn_impl<2>(Qm, ldq, X, ldx, C, ldc, P, N, K, transpose_out, split, part, s);
+    return narrow ? tn_impl<2, NNS<2>>(Qm, ldq, X, ldx, C, ldc, P, N, K, transpose_out, split, part, s)
+                  : tn_impl<2, TNS<2>>(Qm, ldq, X, ldx, C, ldc, P, N, K, transpose_out, split, part, s);
   return kEInval;
 }
 

@@ -81,10 +81,11 @@ size_t max_partials(int64_t m, int64_t n, int b, int64_t kcap, bool exact) {
       const size_t v = partial_doubles(rows, cols, s);
       if (v > best) best = v;
     }
-    for (int slots : {1, 2}) {  // the low-precision sampling products
-      const size_t v = partial_doubles(rows, cols, choose_split_fill(rows, cols, K, slots));
-      if (v > best) best = v;
-    }
+    for (int lp : {1, 2})  // the low-precision sampling products
+      for (bool nn : {false, true}) {
+        const size_t v = partial_doubles(rows, cols, lowp_split(lp, nn, rows, cols, K));
+        if (v > best) best = v;
+      }
   };
   upd(m, b, n);                // Y = A Omega, Y = A Z
   upd(b, n, m);                // B_i = Q^T A, (A^T Q)^T
@@ -180,19 +181,17 @@ int sample(uint32_t prec, const double* X, int64_t ldx, const double* W, int64_t
   if (prec == QB_SAMPLE_F64)
     return gemm_nn(X, ldx, W, ldw, Y, ldy, M, N, K, 1.0, 0.0, choose_split(M, N, K, 2, true), part,
                    s);
-  // the bf16x3 form of this product runs one workgroup per CU
-  const int split = choose_split_fill(M, N, K, prec == QB_SAMPLE_BF16X3 ? 1 : 2);
-  return gemm_nn_lowp(prec == QB_SAMPLE_F32 ? 1 : 2, X, ldx, W, ldw, Y, ldy, M, N, K, split,
-                      part, s);
+  const int lp = prec == QB_SAMPLE_F32 ? 1 : 2;
+  return gemm_nn_lowp(lp, X, ldx, W, ldw, Y, ldy, M, N, K, lowp_split(lp, true, M, N, K), part, s);
 }
 
 int project_t(uint32_t prec, const double* Qm, int64_t ldq, const double* X, int64_t ldx,
               double* C, int64_t ldc, int64_t P, int64_t N, int64_t K, bool tr, double* part,
               double* sq, int* sqc, hipStream_t s) {
-  const int split = choose_split(P, N, K);
   if (prec == QB_SAMPLE_F64)
-    return gemm_tn(Qm, ldq, X, ldx, C, ldc, P, N, K, tr, split, part, sq, sqc, s);
-  return gemm_tn_lowp(prec == QB_SAMPLE_F32 ? 1 : 2, Qm, ldq, X, ldx, C, ldc, P, N, K, tr, split,
+    return gemm_tn(Qm, ldq, X, ldx, C, ldc, P, N, K, tr, choose_split(P, N, K), part, sq, sqc, s);
+  const int lp = prec == QB_SAMPLE_F32 ? 1 : 2;
+  return gemm_tn_lowp(lp, Qm, ldq, X, ldx, C, ldc, P, N, K, tr, lowp_split(lp, false, P, N, K),
                       part, s);
 }
 
@@ -592,11 +591,16 @@ struct GemmScratch {
 size_t gemm_scratch(void* workspace, size_t ws_bytes, int64_t m, int64_t K, int32_t w,
                     GemmScratch* g) {
   Arena a{static_cast<char*>(workspace), ws_bytes, 0};
+  // the sample Y (m x w, depth K) in every precision, and the projection
+  // C (w x m, depth K) with the splits project_t takes
   size_t np = std::max(partial_doubles(m, w, choose_split(m, w, K, 2, true)),
                        std::max(partial_doubles(m, w, choose_split(m, w, K, 2, false)),
                                 sample_i8_partials(m, w, K)));
-  for (int slots : {1, 2})
-    np = std::max(np, partial_doubles(m, w, choose_split_fill(m, w, K, slots)));
+  np = std::max(np, partial_doubles(w, m, choose_split(w, m, K)));
+  for (int lp : {1, 2}) {
+    np = std::max(np, partial_doubles(m, w, lowp_split(lp, true, m, w, K)));
+    np = std::max(np, partial_doubles(w, m, lowp_split(lp, false, w, m, K)));
+  }
   g->part = a.take<double>(np + 1);
   g->omq = a.take<int8_t>(static_cast<size_t>(sample_i8_kp(K)) * w);
   const size_t nsq = sumsq_partials_count(m, K) + 1;

@@ -111,8 +111,13 @@ int launch_sketch(uint64_t seed, int64_t n, int64_t col0, int w, double* out, in
 // kTileM x kTileN): enough workgroups to fill the chip, at least
 // kSplitMinDepth per workgroup, partial storage bounded by kPartialCapDoubles
 int choose_split(int64_t M, int64_t N, int64_t K, int slots_per_cu = 2, bool tall_nn = false);
-// the split of the low-precision sampling products (best-filled last round)
-int choose_split_fill(int64_t M, int64_t N, int64_t K, int slots_per_cu);
+// the split with the best-filled last round of workgroups, for output tiles
+// of bm x bn
+int choose_split_fill(int64_t M, int64_t N, int64_t K, int slots_per_cu, int bm = kTileM,
+                      int bn = kTileN);
+// split-K of the low-precision products (their own tile shapes and
+// workgroups per CU): Y = X W (nn) or C = Q^T X
+int lowp_split(int precision, bool nn, int64_t M, int64_t N, int64_t K);
 // doubles of partial storage for an M x N product split `split` ways
 size_t partial_doubles(int64_t M, int64_t N, int split);
 

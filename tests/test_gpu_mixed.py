@@ -36,7 +36,12 @@ def dev(x):
 
 
 @pytest.mark.parametrize("prec", ["f32", "bf16x3"])
-@pytest.mark.parametrize("m,K,w", [(300, 500, 50), (129, 1000, 128), (1000, 4100, 256), (1, 3, 1)])
+@pytest.mark.parametrize("m,K,w", [(300, 500, 50), (129, 1000, 128), (1000, 4100, 256), (1, 3, 1),
+                                   # 256 x 128 tiles up to 128 columns, 128 x 256 above;
+                                   # ragged rows and depth, odd ld (pairwise loads off),
+                                   # several depth chunks
+                                   (1025, 777, 127), (2600, 2050, 129), (5003, 3001, 200),
+                                   (4096, 6000, 256)])
 def test_lowp_sample_product(cuda, prec, m, K, w):
     r = np.random.default_rng(m + K + w)
     X = np.asfortranarray(r.standard_normal((m, K)))
@@ -51,7 +56,8 @@ def test_lowp_sample_product(cuda, prec, m, K, w):
 
 
 @pytest.mark.parametrize("prec", ["f32", "bf16x3"])
-@pytest.mark.parametrize("K,w,N", [(500, 50, 300), (4100, 256, 257), (33, 7, 2000)])
+@pytest.mark.parametrize("K,w,N", [(500, 50, 300), (4100, 256, 257), (33, 7, 2000),
+                                   (3001, 200, 1111), (6000, 129, 4000)])
 def test_lowp_project(cuda, prec, K, w, N):
     r = np.random.default_rng(K + w + N)
     Qm = np.asfortranarray(r.standard_normal((K, w)))
