@@ -212,6 +212,29 @@ __device__ __forceinline__ void tri_index(int job, int& bi, int& bj) {
   bj = job - bi * (bi + 1) / 2;
 }
 
+// Source of a Gram matrix (or of its whole-matrix counterpart Gd): G with
+// leading dimension ld, or, when part is set, the sum of the nz depth-chunk
+// partial products part[z slot + i + j ld], z in order from 0.0, as the
+// reduction kernels form it (so the factorisation sees the same bits).
+// (Used for the batched Gram matrices, split into at most a few chunks.)
+struct GSrc {
+  const double* G;
+  int64_t ld;
+  const double* part;
+  int nz;
+  int64_t slot;
+  __device__ __forceinline__ double at(int i, int j) const {
+    if (part == nullptr) return G[i + static_cast<int64_t>(j) * ld];
+    const double* p = part + i + static_cast<int64_t>(j) * ld;
+    double v = 0.0;
+    for (int z = 0; z < nz; ++z) v += p[z * slot];
+    return v;
+  }
+};
+__device__ __forceinline__ GSrc gsrc(const double* G, int64_t ld) {
+  return GSrc{G, ld, nullptr, 1, 0};
+}
+
 // Blocked Cholesky with dropping of the w x w matrix G (column-major, ld w).
 // Result in LDS: Ts[c * TS + i] = T[c][i] = L[i][c] (T = L^T upper
 // triangular, zero for i < c and in the padding up to WMAX); flag, rdiag,
@@ -223,14 +246,13 @@ __device__ __forceinline__ void tri_index(int job, int& bi, int& bj) {
 // of two scaling is exact and leaves every pivot test unchanged, and it
 // keeps every kept pivot inside the range of the hardware reciprocal square
 // root estimate.
-// ldg: leading dimension of G.  Gd (wd x wd, ld wd): the matrix whose
+// G: the w x w matrix factorised (GSrc).  Gd (wd x wd): the matrix whose
 // largest diagonal entry fixes the power-of-two scale and the drop
 // threshold; G itself for a whole Gram matrix, the whole Gram matrix when G
 // is one of its diagonal blocks or a Schur complement (so every block is
 // scaled and tested as the unblocked factorisation would be).
 template <int WMAX, int NW>
-__device__ __forceinline__ void chol_blocked(const double* __restrict__ G, int w, int ldg,
-                                             const double* __restrict__ Gd, int wd, double* Ts,
+__device__ __forceinline__ void chol_blocked(const GSrc& G, int w, const GSrc& Gd, int wd, double* Ts,
                                              int* flag, double* rdiag, int* klist, int* kcnt,
                                              int* ulist, int* ucnt, int& sexp) {
   constexpr int TS = WMAX + 1;
@@ -246,10 +268,10 @@ __device__ __forceinline__ void chol_blocked(const double* __restrict__ G, int w
     for (int q = 0; q < PER; ++q) {
       const int idx = threadIdx.x + 64 * NW * q;
       const int i = idx % WMAX, j = idx / WMAX;
-      v[q] = (i < w && j < w && i >= j) ? G[i + static_cast<int64_t>(j) * ldg] : 0.0;
+      v[q] = (i < w && j < w && i >= j) ? G.at(i, j) : 0.0;
     }
     double gd = 0.0;
-    for (int c = lane; c < wd; c += 64) gd = fmax(gd, Gd[c + static_cast<int64_t>(c) * wd]);
+    for (int c = lane; c < wd; c += 64) gd = fmax(gd, Gd.at(c, c));
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) gd = fmax(gd, __shfl_xor(gd, off));
     int ex = 0;
@@ -370,8 +392,7 @@ __device__ __forceinline__ void lds_block16(double* M, int ra, int ka, int kb, i
 }
 
 template <int WMAX>
-__device__ __forceinline__ void chol_inv_lds_body(const double* __restrict__ G, int w, int ldg,
-                                                  const double* __restrict__ Gd, int wd,
+__device__ __forceinline__ void chol_inv_lds_body(const GSrc& G, int w, const GSrc& Gd, int wd,
                                                   int* __restrict__ kept,
                                                   double* __restrict__ Tinv, int ldt) {
   using L = LdsInvShape<WMAX>;
@@ -385,7 +406,7 @@ __device__ __forceinline__ void chol_inv_lds_body(const double* __restrict__ G, 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 
   int sexp;
-  chol_blocked<WMAX, NW>(G, w, ldg, Gd, wd, Ts, flag, rdiag, klist, &kcnt, ulist, &ucnt, sexp);
+  chol_blocked<WMAX, NW>(G, w, Gd, wd, Ts, flag, rdiag, klist, &kcnt, ulist, &ucnt, sexp);
   // T' = T with every dropped or padding index u turned into a unit row and
   // column (its inverse restricted to the kept indices is T_kept^{-1})
   const int nu = ucnt;
@@ -476,7 +497,7 @@ template <int WMAX>
 __global__ __launch_bounds__(512) void chol_inv_lds_kernel(const double* __restrict__ G, int w,
                                                            int* __restrict__ kept,
                                                            double* __restrict__ Tinv) {
-  chol_inv_lds_body<WMAX>(G, w, w, G, w, kept, Tinv, w);
+  chol_inv_lds_body<WMAX>(gsrc(G, w), w, gsrc(G, w), w, kept, Tinv, w);
 }
 
 // one diagonal block (or Schur complement) of a wider Gram matrix Gd
@@ -485,7 +506,7 @@ __global__ __launch_bounds__(512) void chol_inv_block_kernel(const double* __res
                                                              int ldg, const double* __restrict__ Gd,
                                                              int wd, int* __restrict__ kept,
                                                              double* __restrict__ Tinv, int ldt) {
-  chol_inv_lds_body<WMAX>(G, w, ldg, Gd, wd, kept, Tinv, ldt);
+  chol_inv_lds_body<WMAX>(gsrc(G, ldg), w, gsrc(Gd, wd), wd, kept, Tinv, ldt);
 }
 
 // one workgroup per problem of a batch
@@ -493,7 +514,8 @@ template <int WMAX>
 __global__ __launch_bounds__(512) void chol_inv_batched_kernel(const BatchChol* __restrict__ desc) {
   const BatchChol c = desc[blockIdx.x];
   if (c.w <= 0) return;  // a problem that takes no part in this step
-  chol_inv_lds_body<WMAX>(c.G, c.w, c.w, c.G, c.w, c.kept, c.Tinv, c.w);
+  const GSrc g = c.ksplit > 1 ? GSrc{nullptr, c.ldp, c.part, c.ksplit, c.slot} : gsrc(c.G, c.w);
+  chol_inv_lds_body<WMAX>(g, c.w, g, c.w, c.kept, c.Tinv, c.w);
 }
 
 template <int WMAX>
@@ -602,7 +624,11 @@ int chol_inv(const double* G, int w, double* T, int* kept, double* Tinv, hipStre
   return kEInval;
 }
 
-// one pass: Qout = X_kept T^{-1}
+// one pass: Qout = X_kept T^{-1}.  The Gram matrix is summed from its
+// depth chunks by the reduction kernel before the Cholesky: at m = 10^4 it
+// has about 63 chunks, and summing them inside the one-workgroup Cholesky
+// as it loads G (a chain of dependent loads per element) took 12 times as
+// long as the reduction it saves.
 int cholqr_pass(const double* X, int64_t ldx, double* Qout, int64_t ldqo, int64_t m, int w,
                 const OrthWork& ow, hipStream_t s) {
   int rc = gemm_tn(X, ldx, X, ldx, ow.gram, w, w, w, m, false, ow.split, ow.part, nullptr,

@@ -508,7 +508,8 @@ __global__ __launch_bounds__(kPlanThreads) void batch_plan_kernel(const DevProb*
         const int w = S[i].w;
         if (step_desc(s, P[i], S[i].k, w, tt, &g)) {
           cls = tt.cls[step_role(s)][width_class_hd(w)];
-          runits = reduce_blocks(g);
+          // a split Gram matrix is summed by the Cholesky that reads it
+          runits = step_role(s) == QB_ROLE_GRAM ? 0 : reduce_blocks(g);
           if (cls == c) units = static_cast<int64_t>(g.tiles_m) * g.tiles_n * g.ksplit;
         }
       }
@@ -553,7 +554,13 @@ __global__ __launch_bounds__(kPlanThreads) void batch_plan_kernel(const DevProb*
       const int64_t k = S[i].k;
       units = ((p.n + 1) / 2 + 255) / 256 * w;  // as sketch_blocks(n, w)
       sk = BatchSketch{p.seed, p.n, k, p.n, p.omega, 0, w};
-      c1 = BatchChol{p.G, p.kept, p.Tinv, w};
+      // the four Gram matrices of the iteration share one shape (w x w,
+      // depth m) and so one depth split: the Cholesky sums their chunks
+      BatchGemm gg;
+      step_desc(kStG1, p, k, w, tt, &gg);
+      const int64_t ldp = static_cast<int64_t>(gg.tiles_m) * gg.bm;
+      c1 = BatchChol{p.G, p.kept, p.Tinv, w, gg.ksplit, gg.ksplit > 1 ? gg.part : nullptr, ldp,
+                     ldp * (static_cast<int64_t>(gg.tiles_n) * gg.bn)};
       if (k > 0) c3 = c1;
       BatchGemm gb, gd;
       step_desc(kStB, p, k, w, tt, &gb);
@@ -790,6 +797,7 @@ int qb_factor_batched(qb_problem* probs, int32_t count, void* workspace, size_t 
     // kSplitTiles tiles with a depth of at least 2 kSplitChunk; the tile
     // count is smallest at w = 1 and k = 1, the depth fixed or growing
     auto may_split = [&](int st_, const Prob& p, const TileTable& t) {
+      if (step_role(st_) == QB_ROLE_GRAM) return false;  // summed by the Cholesky
       for (int wc = 0; wc <= width_class_hd(p.b); ++wc) {
         int bm = 0, bn = 0;
         batch_tile_dims_hd(t.cls[step_role(st_)][wc], &bm, &bn);

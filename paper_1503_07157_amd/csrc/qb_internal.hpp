@@ -238,10 +238,13 @@ int gemm_batched_reduce(int op, const BatchGemm* desc, int count, int64_t total_
                         unsigned long long* dev_next);
 
 struct BatchChol {  // Cholesky with dropping + inverse of one w x w Gram matrix
-  const double* G;
+  const double* G;    // G (ld w), unless part is set
   int* kept;
   double* Tinv;
   int32_t w;
+  int32_t ksplit;     // > 1: G is the sum of the Gram product's depth chunks
+  const double* part; // chunk z at part + z slot, element (i, j) at i + j ldp
+  int64_t ldp, slot;
 };
 int chol_inv_batched(const BatchChol* desc, int count, hipStream_t s);  // w <= 64
 
