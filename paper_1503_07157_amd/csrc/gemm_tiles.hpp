@@ -197,6 +197,11 @@ __device__ __forceinline__ void mma_slice(const double* Ac, const double* Bc,
   const int wm = (wave % S::WGM) * S::WM, wn = (wave / S::WGM) * S::WN;
   const int lr = lane & 15, lk = lane >> 4;
   const int pr = perm16(lr);
+  // Q^T X products (A k-contiguous): LLVM's interleaving of LDS reads with
+  // the MFMA chain (iglp_opt(1)) cut gemm_tn from 259 to 249 ms per
+  // 20000 x 16000 factorisation; on the other products it was neutral or
+  // slower (the downdate 196 -> 203 ms), and iglp_opt(0) slower everywhere
+  if constexpr (A_KCONTIG) __builtin_amdgcn_iglp_opt(1);
 #pragma unroll
   for (int k4 = 0; k4 < BK / 4; ++k4) {
     double a[S::IB], b[S::JB];
