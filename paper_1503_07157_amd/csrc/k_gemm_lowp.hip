@@ -9,7 +9,8 @@
 //
 //   precision 1 (f32):     v_mfma_f32_16x16x4_f32 on operands rounded to
 //                          float32 (relative error about 2^-24 per term)
-//   precision 2 (bf16x3):  x = hi + lo with hi = bf16(x), lo = bf16(x - hi);
+//   precision 2 (bf16x3):  x = hi + lo with hi = bf16(float(x)),
+//                          lo = bf16(float(x) - hi);
 //                          x y ~ hi_x hi_y + hi_x lo_y + lo_x hi_y on
 //                          v_mfma_f32_16x16x32_bf16 (about 2^-16 relative)
 //
@@ -77,9 +78,18 @@ __device__ __forceinline__ double2 ld_pair(const double* p, bool ok0, bool ok1, 
   return v;
 }
 
+// x ~ hi + lo to about 2^-17 relative: x rounded to float (xf), hi = xf
+// rounded to bf16, lo = the exact float difference xf - hi rounded to bf16.
+// xf is kept opaque so that each rounding to bf16 is one packed conversion
+// (v_cvt_pk_bf16_f32): written as bf16(float(x)) the compiler emits a
+// correctly rounded double -> bf16 sequence of about twelve instructions,
+// and the double-precision lo about fourteen more (counters: the bf16x3
+// sample spent about 45 % of its cycles on VALU work).
 __device__ __forceinline__ void split_bf16(double x, __bf16& hi, __bf16& lo) {
-  hi = static_cast<__bf16>(static_cast<float>(x));
-  lo = static_cast<__bf16>(static_cast<float>(x - static_cast<double>(static_cast<float>(hi))));
+  float xf = static_cast<float>(x);
+  asm volatile("" : "+v"(xf));
+  hi = static_cast<__bf16>(xf);
+  lo = static_cast<__bf16>(xf - static_cast<float>(hi));
 }
 
 // Accumulate the BM x BN tile over k in [kbeg, kend).  A is M x K, element
