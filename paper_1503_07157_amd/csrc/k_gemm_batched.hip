@@ -5,6 +5,8 @@
 // (gemm_tiles.hpp).  Problems whose product is split over depth chunks
 // leave their partial tiles to gemm_batched_reduce, which sums them in chunk
 // order, so results are bitwise reproducible.
+#include <cstdlib>
+
 #include "gemm_tiles.hpp"
 
 namespace qb {
@@ -323,8 +325,12 @@ __global__ __launch_bounds__(256) void gemm_batched_reduce_kernel(
 namespace {
 // Grids up to this many workgroups run one unit per workgroup; larger
 // bounds are walked by kWalkGrid workgroups.
-constexpr int64_t kExactGridMax = int64_t(1) << 22;
+// QB_BATCHED_WALK (set) walks every launch, so the fallback runs on batches
+// small enough for a test.
 constexpr int64_t kWalkGrid = 2048;
+int64_t exact_grid_max() {
+  return getenv("QB_BATCHED_WALK") != nullptr ? 0 : (int64_t(1) << 22);
+}
 
 template <class S, bool WALK>
 void launch_batched_as(int op, const BatchGemm* desc, int count, dim3 grid, const int64_t* total,
@@ -343,7 +349,7 @@ void launch_batched_as(int op, const BatchGemm* desc, int count, dim3 grid, cons
 template <class S>
 void launch_batched(int op, const BatchGemm* desc, int count, int64_t bound, const int64_t* total,
                     unsigned long long* next, hipStream_t s) {
-  if (bound <= kExactGridMax)  // a multiple of 8 for xcd_unit
+  if (bound <= exact_grid_max())  // a multiple of 8 for xcd_unit
     launch_batched_as<S, false>(op, desc, count, dim3(static_cast<unsigned>((bound + 7) & ~int64_t(7))),
                                 total, next, s);
   else
@@ -391,7 +397,7 @@ int gemm_batched_reduce(int op, const BatchGemm* desc, int count, int64_t total_
                         unsigned long long* dev_next) {
   if (count <= 0 || total_rblocks <= 0) return kOk;
   if (op == kBatchDD || dev_total == nullptr || dev_next == nullptr) return kEInval;
-  const bool walk = total_rblocks > kExactGridMax;
+  const bool walk = total_rblocks > exact_grid_max();
   const dim3 grid(static_cast<unsigned>(walk ? kWalkGrid : total_rblocks));
   ProfScope ps(prof_id, 0.0, 0.0, s);
   if (op == kBatchNN) {

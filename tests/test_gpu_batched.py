@@ -177,3 +177,29 @@ def test_graph_replays_match_eager(cuda, monkeypatch):
         assert a.k == b_.k == c.k and a.stop_reason == b_.stop_reason == c.stop_reason
         assert torch.equal(a.Q, b_.Q) and torch.equal(a.B, b_.B)
         assert torch.equal(a.Q, c.Q) and torch.equal(a.B, c.B)
+
+
+def test_walking_launches_match(cuda, monkeypatch):
+    """A launch whose unit bound exceeds 2^22 workgroups runs a fixed grid
+    of 2048 that takes units from a per-launch counter instead of one
+    workgroup per unit.  QB_BATCHED_WALK forces that form for every launch:
+    the factors are bitwise those of the one-workgroup-per-unit launches,
+    replayed as graphs and eagerly."""
+    specs = synth.batch_specs(count=10, seed=4043, m_range=(200, 1500), n_max=800)
+    mats = [dev32(synth.batch_matrix(sp)) for sp in specs]
+    eps = [1e-6 * float(torch.linalg.norm(A, dtype=torch.float64)) for A in mats]
+    bs = [sp.b for sp in specs]
+    seeds = [sp.seed_omega for sp in specs]
+    ref = qbmi.qb_factor_batched(mats, eps, bs, seeds)
+    monkeypatch.setenv("QB_BATCHED_WALK", "1")
+    walked = qbmi.qb_factor_batched(mats, eps, bs, seeds)
+    monkeypatch.setenv("QB_BATCHED_EAGER", "1")
+    walked_eager = qbmi.qb_factor_batched(mats, eps, bs, seeds)
+    monkeypatch.delenv("QB_BATCHED_EAGER")
+    monkeypatch.delenv("QB_BATCHED_WALK")
+    print(f"[case] ranks {[r.k for r in ref]}", flush=True)
+    for a, b_, c in zip(ref, walked, walked_eager):
+        assert a.status == b_.status == c.status and a.status >= 0
+        assert a.k == b_.k == c.k and a.stop_reason == b_.stop_reason == c.stop_reason
+        assert torch.equal(a.Q, b_.Q) and torch.equal(a.B, b_.B)
+        assert torch.equal(a.Q, c.Q) and torch.equal(a.B, c.B)
