@@ -252,7 +252,11 @@ struct Stage {
 // 230 -> 225 ms against the hand-picked table of k_gemm_batched.hip); they
 // can be changed at run time through qb_batched_set_tile.  Every class
 // computes the same products; the classes allowed for B_i and the downdate
-// are those their per-tile sums of squares have room for.
+// are those their per-tile sums of squares have room for.  Panels of 33..64
+// columns keep 64 x 32 tiles for the samples, although two column tiles
+// read R twice (counters: 1.8x the sample's algorithmic bytes at the first
+// iteration): 64 x 64 tiles there read it once but made the batch 8 ms
+// slower (half the workgroups, and one launch more per step).
 std::atomic<int> g_tile[QB_ROLES][3] = {
     {{kTileN32}, {kTileN32}, {kTileN32}},  // QB_ROLE_SAMPLE     R Omega
     {{kTileG32}, {kTileG32}, {kTileG32}},  // QB_ROLE_GRAM       X^T X
