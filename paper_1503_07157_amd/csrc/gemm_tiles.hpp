@@ -272,7 +272,45 @@ __device__ __forceinline__ void mma_loop(const double* __restrict__ A, int64_t l
     if (nslice > 1) tl.load(rA, da, rB, db);
     lds_barrier();
     int stage = 0;
-    for (int sl = 0; sl < nslice; ++sl) {
+    int sl = 0;
+    // Steady state as one basic block (no per-slice branches) for the
+    // Q^T X products with tiles of 128 or 256 rows and the 128 x 128 tiles;
+    // for the 128 x 128 tiles of Y = X W and the downdate the next slice's
+    // LDS stores and global loads are dealt between the MFMAs, and the LDS
+    // operand reads one per MFMA (sched_group_barrier).  Measured per
+    // 20000 x 16000 factorisation: downdate 196 -> 191 ms, gemm_tn 249 ->
+    // 244 ms; the 256 x 128 tiles of Y = X W keep the plain loop (peeled,
+    // 248 -> 258 ms), and so do the 64 x 64 tiles (the Gram matrices,
+    // peeled 19 -> 21 ms).
+    constexpr bool kPeel = S::BM >= 128 && (A_KCONTIG || S::BM == 128);
+    if constexpr (kPeel) {
+      for (; sl + 2 < nslice; ++sl) {
+        tl.store(As + (stage ^ 1) * S::A_LDS, Bs + (stage ^ 1) * S::B_LDS);
+        tl.load(rA, (sl + 2) * da, rB, (sl + 2) * db);
+        mma_slice<S, A_KCONTIG>(As + stage * S::A_LDS, Bs + stage * S::B_LDS, acc);
+        if constexpr (!A_KCONTIG && S::BM == 128) {
+          constexpr int kMem = FastTile<S, A_KCONTIG>::QA + FastTile<S, A_KCONTIG>::QB;
+          constexpr int kMfma = (BK / 4) * S::IB * S::JB;
+          constexpr int kReads = (BK / 4) * (S::IB + S::JB);
+          static_assert(4 * kMem + kReads == kMfma, "one MFMA per LDS read after the stores");
+#pragma unroll
+          for (int g = 0; g < kMem; ++g) {
+            __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);  // LDS write
+            __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);  // MFMA
+            __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);  // global (buffer) load
+            __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+          }
+#pragma unroll
+          for (int g = 0; g < kReads; ++g) {
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // LDS read
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+          }
+        }
+        lds_barrier();
+        stage ^= 1;
+      }
+    }
+    for (; sl < nslice; ++sl) {
       if (sl + 1 < nslice) {
         tl.store(As + (stage ^ 1) * S::A_LDS, Bs + (stage ^ 1) * S::B_LDS);
         if (sl + 2 < nslice) tl.load(rA, (sl + 2) * da, rB, (sl + 2) * db);
