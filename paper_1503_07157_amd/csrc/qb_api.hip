@@ -81,14 +81,13 @@ size_t max_partials(int64_t m, int64_t n, int b, int64_t kcap, bool exact) {
       const size_t v = partial_doubles(rows, cols, s);
       if (v > best) best = v;
     }
-    for (int lp : {1, 2})  // the low-precision sampling products
-      for (bool nn : {false, true}) {
-        const size_t v = partial_doubles(rows, cols, lowp_split(lp, nn, rows, cols, K));
-        if (v > best) best = v;
-      }
   };
   upd(m, b, n);                // Y = A Omega, Y = A Z
   upd(b, n, m);                // B_i = Q^T A, (A^T Q)^T
+  for (int lp : {1, 2}) {      // their low-precision forms (packed panel + partials)
+    best = std::max(best, lowp_scratch_doubles(lp, true, m, b, n));
+    best = std::max(best, lowp_scratch_doubles(lp, false, b, n, m));
+  }
   for (int64_t k = 1; k <= kcap; ++k) {
     upd(b, k, m);              // Q_i^T Qbar (split is not monotone in k)
     upd(m, b, k);              // Qbar C
@@ -598,8 +597,8 @@ size_t gemm_scratch(void* workspace, size_t ws_bytes, int64_t m, int64_t K, int3
                                 sample_i8_partials(m, w, K)));
   np = std::max(np, partial_doubles(w, m, choose_split(w, m, K)));
   for (int lp : {1, 2}) {
-    np = std::max(np, partial_doubles(m, w, lowp_split(lp, true, m, w, K)));
-    np = std::max(np, partial_doubles(w, m, lowp_split(lp, false, w, m, K)));
+    np = std::max(np, lowp_scratch_doubles(lp, true, m, w, K));
+    np = std::max(np, lowp_scratch_doubles(lp, false, w, m, K));
   }
   g->part = a.take<double>(np + 1);
   g->omq = a.take<int8_t>(static_cast<size_t>(sample_i8_kp(K)) * w);

@@ -148,13 +148,18 @@ int quantize_sketch(const double* om, int64_t ldo, int64_t n, int w, int8_t* q, 
 int sample_i8(const double* A, int64_t lda, const int8_t* q, double* Y, int64_t ldy, int64_t M,
               int N, int64_t K, const double* dnorm2, int e_host, double* part, hipStream_t s);
 
-// mixed-precision sampling variants (precision: 1 = f32, 2 = bf16x3)
+// mixed-precision sampling variants (precision: 1 = f32, 2 = bf16x3):
+// Y(M x N) = X W and C(P x N) = Q^T X (or C^T, transpose_out), with the
+// panel (W, or Q) rounded once into scratch, followed there by the split-K
+// partials: lowp_scratch_doubles(precision, nn, M, N, K) doubles (M = P for
+// C = Q^T X), 256-byte aligned, required.
+size_t lowp_scratch_doubles(int precision, bool nn, int64_t M, int64_t N, int64_t K);
 int gemm_nn_lowp(int precision, const double* X, int64_t ldx, const double* W, int64_t ldw,
                  double* Y, int64_t ldy, int64_t M, int64_t N, int64_t K, int split,
-                 double* part, hipStream_t s);
+                 double* scratch, hipStream_t s);
 int gemm_tn_lowp(int precision, const double* Qm, int64_t ldq, const double* X, int64_t ldx,
                  double* C, int64_t ldc, int64_t P, int64_t N, int64_t K, bool transpose_out,
-                 int split, double* part, hipStream_t s);
+                 int split, double* scratch, hipStream_t s);
 
 // R(M x N) -= Q(M x K) * B(K x N); per-workgroup sums of squares of the
 // updated R into sq_part (count returned through sq_count).
