@@ -7,10 +7,15 @@
 // the left singular vectors of B are the columns of J, the right ones the
 // normalised columns of W, and U = Q J.  Rotating the columns directly
 // keeps the high relative accuracy of the small singular values that a
-// Gram-matrix route would lose below sqrt(u) sigma_1.  One round applies
-// K/2 disjoint rotations (round-robin pairing, K = k rounded up to even),
-// one workgroup per pair; K - 1 rounds make a sweep; sweeps repeat until
-// every pair is orthogonal to a relative 1e-15.  The singular values are
+// Gram-matrix route would lose below sqrt(u) sigma_1.  The columns go in
+// blocks of two: a round pairs the blocks round-robin (K2 = ceil(k / 2)
+// rounded up to even), one workgroup per pair of blocks with their four
+// columns in registers, which rotates the four column pairs across the
+// blocks (and, in a sweep's first round, the pair inside each block); K2 - 1
+// rounds make a sweep, in which every pair of columns meets once.  Columns
+// longer than the registers hold (n > 10240) take one pair per workgroup
+// and K - 1 rounds of K/2 pairs instead.  Sweeps repeat until every pair is
+// orthogonal to a relative 1e-15.  The singular values are
 // then sorted in one workgroup (bitonic, ties by index) and U = Q J on the
 // MFMA GEMM.
 //
@@ -27,6 +32,8 @@
 // Every reduction has a fixed order: results are bitwise reproducible.
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
+#include <type_traits>
 
 #include "../../include/qb.h"
 #include "qb_internal.hpp"
@@ -130,6 +137,182 @@ __global__ __launch_bounds__(kJacThreads) void jacobi_round_kernel(
     ja[q] = c * xa - s * yb;
     jb[q] = s * xa + c * yb;
   }
+}
+
+// ---- two-column blocks -----------------------------------------------------
+// The same rotations, ordered by blocks of two columns: block q holds
+// columns 2q, 2q + 1 of Bt (a column >= k is absent and stays zero).  In
+// round r of a sweep, workgroup i takes the blocks of the round-robin pairing
+// of K2 blocks (K2 = ceil(k / 2) rounded up to even) and keeps their four
+// columns of Bt in registers while it rotates the four pairs across the two
+// blocks, two disjoint pairs at a time, and in round 0 first the pair inside
+// each block.  The rotations are recorded in LDS and applied to the four
+// (short) columns of J afterwards, in the same order.  Every pair of columns
+// still meets once per sweep, every rotation is computed from the columns
+// as they are (three dot products in a fixed order), and each column of Bt
+// is read and written once per round instead of three times per pair, in
+// half as many rounds.
+
+// rotation slot s of a round: pair (jb_p(s), jb_q(s)) of the four columns;
+// slots 0, 1 inside the blocks (round 0 only), 2 .. 5 across them
+__host__ __device__ constexpr int jb_p(int s) { return s == 0 ? 0 : s == 1 ? 2 : s == 2 ? 0 : s == 3 ? 1 : s == 4 ? 0 : 1; }
+__host__ __device__ constexpr int jb_q(int s) { return s == 0 ? 1 : s == 1 ? 3 : s == 2 ? 2 : s == 3 ? 3 : s == 4 ? 3 : 2; }
+
+// slots S and S + 1 (two disjoint pairs): the six dot products, one
+// fixed-order workgroup sum, then both rotations on the registers; the
+// parameters (c, s), or c = 2 for no rotation, go to rp[slot] (thread 0)
+template <int NT, int CAP, int S>
+__device__ __forceinline__ void jb_step(double (&x)[4][CAP], double* red, double2* rp,
+                                        double& offm, bool& changed) {
+  constexpr int P0 = jb_p(S), Q0 = jb_q(S), P1 = jb_p(S + 1), Q1 = jb_q(S + 1);
+  double s[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int e = 0; e < CAP; ++e) {  // absent entries hold zeros
+    s[0] = fma(x[P0][e], x[P0][e], s[0]);
+    s[1] = fma(x[Q0][e], x[Q0][e], s[1]);
+    s[2] = fma(x[P0][e], x[Q0][e], s[2]);
+    s[3] = fma(x[P1][e], x[P1][e], s[3]);
+    s[4] = fma(x[Q1][e], x[Q1][e], s[4]);
+    s[5] = fma(x[P1][e], x[Q1][e], s[5]);
+  }
+  constexpr int NWV = NT / 64;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int v = 0; v < 6; ++v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s[v] += __shfl_xor(s[v], off);
+  }
+  __syncthreads();  // red is free (the previous step's reads are done)
+  if (lane == 0) {
+#pragma unroll
+    for (int v = 0; v < 6; ++v) red[v * NWV + wave] = s[v];
+  }
+  __syncthreads();
+  // thread v < 6 sums value v over the waves in order; then every thread
+  // reads the six totals (reading all 6 NWV partials per thread would hold
+  // them in registers at once)
+  if (threadIdx.x < 6) {
+    const int v = threadIdx.x;
+    double t = red[v * NWV];
+    for (int w = 1; w < NWV; ++w) t += red[v * NWV + w];
+    red[6 * NWV + v] = t;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int v = 0; v < 6; ++v) s[v] = red[6 * NWV + v];
+  auto rot = [&](auto pc, auto qc, int slot, double alpha, double beta, double gamma) {
+    constexpr int P = decltype(pc)::value, Q = decltype(qc)::value;
+    double off = 0.0;
+    if (alpha > 0.0 && beta > 0.0) off = fabs(gamma) / (sqrt(alpha) * sqrt(beta));
+    offm = fmax(offm, off);
+    if (!(off > kJacTol)) {  // also every pair with an absent column
+      if (threadIdx.x == 0) rp[slot] = make_double2(2.0, 0.0);
+      return;
+    }
+    const double zeta = (beta - alpha) / (2.0 * gamma);
+    const double az = fabs(zeta);
+    const double tt = (az > 1e150 ? 0.5 / az : 1.0 / (az + sqrt(1.0 + az * az)));
+    const double t = zeta >= 0.0 ? tt : -tt;
+    const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
+#pragma unroll
+    for (int e = 0; e < CAP; ++e) {
+      const double xa = x[P][e], yb = x[Q][e];
+      x[P][e] = c * xa - sn * yb;
+      x[Q][e] = sn * xa + c * yb;
+    }
+    if (threadIdx.x == 0) rp[slot] = make_double2(c, sn);
+    changed = true;
+  };
+  rot(std::integral_constant<int, P0>{}, std::integral_constant<int, Q0>{}, S, s[0], s[1], s[2]);
+  rot(std::integral_constant<int, P1>{}, std::integral_constant<int, Q1>{}, S + 1, s[3], s[4],
+      s[5]);
+}
+
+template <int NT, int CAP>
+__global__ __launch_bounds__(NT) void jacobi_block_round_kernel(
+    double* __restrict__ Bt, int64_t ldt, int n, double* __restrict__ J, int64_t ldj, int k,
+    int K2, int r, double* __restrict__ offmax) {
+  __shared__ double red[6 * (NT / 64) + 6];
+  __shared__ double2 rp[6];
+  const int i = blockIdx.x, t = threadIdx.x;
+  int ba = rr_index(i, r, K2), bb = rr_index(K2 - 1 - i, r, K2);
+  if (ba > bb) { const int u = ba; ba = bb; bb = u; }
+  const int nb = (k + 1) / 2;  // blocks holding a column
+  if (ba >= nb) return;        // both blocks are padding
+  const bool hasb = bb < nb;
+  const int col[4] = {2 * ba, 2 * ba + 1, 2 * bb, 2 * bb + 1};
+  const bool here[4] = {true, col[1] < k, hasb, hasb && col[3] < k};
+  double x[4][CAP];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const double* src = Bt + static_cast<int64_t>(col[q]) * ldt;
+#pragma unroll
+    for (int e = 0; e < CAP; ++e) {
+      const int idx = t + NT * e;
+      x[q][e] = (here[q] && idx < n) ? src[idx] : 0.0;
+    }
+  }
+  double offm = 0.0;
+  bool changed = false;
+  if (r == 0) jb_step<NT, CAP, 0>(x, red, rp, offm, changed);
+  if (hasb) {
+    jb_step<NT, CAP, 2>(x, red, rp, offm, changed);
+    jb_step<NT, CAP, 4>(x, red, rp, offm, changed);
+  }
+  if (t == 0) offmax[i] = fmax(offmax[i], offm);
+  if (!changed) return;  // uniform: every thread took the same decisions
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if (!here[q]) continue;
+    double* dst = Bt + static_cast<int64_t>(col[q]) * ldt;
+#pragma unroll
+    for (int e = 0; e < CAP; ++e) {
+      const int idx = t + NT * e;
+      if (idx < n) dst[idx] = x[q][e];
+    }
+  }
+  __syncthreads();  // rp written by thread 0
+  // J: the recorded rotations in order, on the entries each thread owns;
+  // the columns of absent indices are never rotated, so never touched
+  const int s0 = r == 0 ? 0 : 2, s1 = hasb ? 6 : 2;
+  for (int q = t; q < k; q += NT) {
+    double jx[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) jx[c] = here[c] ? J[q + static_cast<int64_t>(col[c]) * ldj] : 0.0;
+    bool hit[4] = {false, false, false, false};
+#pragma unroll
+    for (int sl = 0; sl < 6; ++sl) {
+      if (sl < s0 || sl >= s1) continue;
+      const double2 cs = rp[sl];
+      if (cs.x > 1.5) continue;
+      const int P = jb_p(sl), Q = jb_q(sl);
+      const double xa = jx[P], yb = jx[Q];
+      jx[P] = cs.x * xa - cs.y * yb;
+      jx[Q] = cs.y * xa + cs.x * yb;
+      hit[P] = hit[Q] = true;
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      if (hit[c]) J[q + static_cast<int64_t>(col[c]) * ldj] = jx[c];
+  }
+}
+
+// one round of the blocked form, the columns of n held in CAP registers
+// per thread (512 threads, or 1024 for the longest columns: four columns
+// of 20 entries per thread spilled); jb_fits: some instance holds them
+bool jb_fits(int64_t n) { return n <= 10240; }
+void jb_launch(int n, dim3 g, hipStream_t st, double* Bt, int64_t ldt, double* J, int64_t ldj,
+               int k, int K2, int r, double* offmax) {
+  auto go = [&](auto ntc, auto capc) {
+    constexpr int NT = decltype(ntc)::value, CAP = decltype(capc)::value;
+    hipLaunchKernelGGL((jacobi_block_round_kernel<NT, CAP>), g, dim3(NT), 0, st, Bt, ldt, n, J,
+                       ldj, k, K2, r, offmax);
+  };
+  using I = std::integral_constant<int, 512>;
+  if (n <= 512 * 4) go(I{}, std::integral_constant<int, 4>{});
+  else if (n <= 512 * 8) go(I{}, std::integral_constant<int, 8>{});
+  else if (n <= 512 * 12) go(I{}, std::integral_constant<int, 12>{});
+  else go(std::integral_constant<int, 1024>{}, std::integral_constant<int, 10>{});
 }
 
 __global__ __launch_bounds__(256) void zero_kernel1(double* __restrict__ x, int64_t n) {
@@ -273,13 +456,35 @@ __global__ __launch_bounds__(256) void qr_pivot_kernel(double* __restrict__ W, i
                                                       double* __restrict__ vstore, int64_t ldv,
                                                       double* __restrict__ tau) {
   __shared__ double red[4];
+  __shared__ double bv[256];
+  __shared__ int64_t bi[256];
   __shared__ int64_t piv;
-  if (threadIdx.x == 0) {
-    double v = cval[0];
-    int64_t id = cidx[0];
-    for (int c = 1; c < ncand; ++c)
-      if (cval[c] > v) { v = cval[c]; id = cidx[c]; }
-    piv = id;
+  // argmax over the candidates, ties to the smaller index: each thread scans
+  // a strided share, then a tree in LDS (the winner is unique, so the order
+  // of the comparisons does not change it)
+  {
+    double v = -2.0;
+    int64_t id = INT64_MAX;
+    for (int c = threadIdx.x; c < ncand; c += 256) {
+      const double cv = cval[c];
+      const int64_t ci = cidx[c];
+      if (cv > v || (cv == v && ci < id)) { v = cv; id = ci; }
+    }
+    bv[threadIdx.x] = v;
+    bi[threadIdx.x] = id;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+      if (static_cast<int>(threadIdx.x) < h) {
+        const double ov = bv[threadIdx.x + h];
+        const int64_t oi = bi[threadIdx.x + h];
+        if (ov > bv[threadIdx.x] || (ov == bv[threadIdx.x] && oi < bi[threadIdx.x])) {
+          bv[threadIdx.x] = ov;
+          bi[threadIdx.x] = oi;
+        }
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) piv = bi[0];
   }
   __syncthreads();
   const int64_t p = piv;
@@ -321,6 +526,7 @@ __global__ __launch_bounds__(256) void qr_pivot_kernel(double* __restrict__ W, i
 // Apply H_j = I - tau v v^T to columns (j, n) of W (rows j..k), one wave per
 // column, and leave that column's norm over rows j+1.. with per-workgroup
 // argmax candidates for step j + 1.
+template <int KC>
 __global__ __launch_bounds__(64 * kQrCols) void qr_apply_kernel(double* __restrict__ W, int64_t ldw,
                                                                int k, int64_t n, int j,
                                                                const double* __restrict__ vstore,
@@ -336,17 +542,33 @@ __global__ __launch_bounds__(64 * kQrCols) void qr_apply_kernel(double* __restri
   const double* v = vstore + static_cast<int64_t>(j) * ldv;
   double s = -1.0;
   if (col < n) {
+    // the column's rows j.. (KC per lane) are loaded once and kept in
+    // registers for the dot product, the update and the next norm; sums in
+    // the same per-lane order as a strided loop
     double* c = W + col * ldw;
+    double cr[KC], vr[KC];
+#pragma unroll
+    for (int e = 0; e < KC; ++e) {
+      const int t = j + lane + 64 * e;
+      cr[e] = t < k ? c[t] : 0.0;
+      vr[e] = t < k ? v[t] : 0.0;
+    }
     double d = 0.0;
-    for (int t = j + lane; t < k; t += 64) d = fma(v[t], c[t], d);
+#pragma unroll
+    for (int e = 0; e < KC; ++e)
+      if (j + lane + 64 * e < k) d = fma(vr[e], cr[e], d);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) d += __shfl_xor(d, off);
     const double f = tj * d;
     double acc = 0.0;
-    for (int t = j + lane; t < k; t += 64) {
-      const double u = c[t] - f * v[t];
-      c[t] = u;
-      if (t > j) acc = fma(u, u, acc);
+#pragma unroll
+    for (int e = 0; e < KC; ++e) {
+      const int t = j + lane + 64 * e;
+      if (t < k) {
+        const double u = cr[e] - f * vr[e];
+        c[t] = u;
+        if (t > j) acc = fma(u, u, acc);
+      }
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
@@ -365,6 +587,26 @@ __global__ __launch_bounds__(64 * kQrCols) void qr_apply_kernel(double* __restri
     cval[blockIdx.x] = v0;
     cidx[blockIdx.x] = id;
   }
+}
+
+// qr_apply_kernel with registers for rows = k - j rows per column (k <= 4096)
+void qr_apply(int rows, dim3 g, hipStream_t st, double* W, int64_t ldw, int k, int64_t n, int j,
+              const double* vstore, int64_t ldv, const double* tau, double* cval, int64_t* cidx) {
+  auto go = [&](auto kc) {
+    constexpr int KC = decltype(kc)::value;
+    hipLaunchKernelGGL((qr_apply_kernel<KC>), g, dim3(64 * kQrCols), 0, st, W, ldw, k, n, j,
+                       vstore, ldv, tau, cval, cidx);
+  };
+  const int need = (rows + 63) / 64;
+  if (need <= 1) go(std::integral_constant<int, 1>{});
+  else if (need <= 2) go(std::integral_constant<int, 2>{});
+  else if (need <= 4) go(std::integral_constant<int, 4>{});
+  else if (need <= 8) go(std::integral_constant<int, 8>{});
+  else if (need <= 16) go(std::integral_constant<int, 16>{});
+  else if (need <= 24) go(std::integral_constant<int, 24>{});
+  else if (need <= 32) go(std::integral_constant<int, 32>{});
+  else if (need <= 48) go(std::integral_constant<int, 48>{});
+  else go(std::integral_constant<int, 64>{});
 }
 
 // Qt(j:k, :) -= tau_j v_j (v_j^T Qt(j:k, :)), one wave per column of Qt
@@ -487,14 +729,26 @@ int qb_svd(const double* Q, int64_t m, int64_t k, int64_t ldq, const double* B, 
   if (hipGetLastError() != hipSuccess) return QB_EHIP;
   int sw = 0;
   bool converged = (K < 2);
+  // two-column blocks when four columns of Bt and of J fit in registers,
+  // else one pair per workgroup
+  const bool blocked = jb_fits(n);
+  const int K2 = static_cast<int>(even_up((k + 1) / 2));
+  const int slots = blocked ? K2 / 2 : K / 2;
   while (!converged && sw < kMaxSweeps) {
-    hipLaunchKernelGGL(zero_kernel1, dim3(static_cast<unsigned>(cdiv(K / 2, 256))), dim3(256), 0,
-                       st, w.offmax, static_cast<int64_t>(K / 2));
-    for (int r = 0; r < K - 1; ++r)
-      hipLaunchKernelGGL(jacobi_round_kernel, dim3(static_cast<unsigned>(K / 2)),
-                         dim3(kJacThreads), 0, st, w.Bt, w.ldt, n, w.J, w.ldj, kk, K, r, w.offmax);
+    hipLaunchKernelGGL(zero_kernel1, dim3(static_cast<unsigned>(cdiv(slots, 256))), dim3(256), 0,
+                       st, w.offmax, static_cast<int64_t>(slots));
+    if (blocked) {
+      for (int r = 0; r < K2 - 1; ++r)
+        jb_launch(static_cast<int>(n), dim3(static_cast<unsigned>(K2 / 2)), st, w.Bt, w.ldt, w.J,
+                  w.ldj, kk, K2, r, w.offmax);
+    } else {
+      for (int r = 0; r < K - 1; ++r)
+        hipLaunchKernelGGL(jacobi_round_kernel, dim3(static_cast<unsigned>(K / 2)),
+                           dim3(kJacThreads), 0, st, w.Bt, w.ldt, n, w.J, w.ldj, kk, K, r,
+                           w.offmax);
+    }
     hipLaunchKernelGGL(max_kernel, dim3(1), dim3(256), 0, st, w.offmax,
-                       static_cast<int64_t>(K / 2), w.sweepmax);
+                       static_cast<int64_t>(slots), w.sweepmax);
     if (hipGetLastError() != hipSuccess) return QB_EHIP;
     double hmax = 0.0;
     if (hipMemcpyAsync(&hmax, w.sweepmax, sizeof(double), hipMemcpyDeviceToHost, st) !=
@@ -547,9 +801,8 @@ int qb_pivoted_qr(const double* Q, int64_t m, int64_t k, int64_t ldq, const doub
                        w.cidx, ncand, perm, w.vstore, w.ldw, w.tau);
     const int64_t rest = n - j - 1;
     if (rest > 0)
-      hipLaunchKernelGGL(qr_apply_kernel, dim3(static_cast<unsigned>(cdiv(rest, kQrCols))),
-                         dim3(64 * kQrCols), 0, st, w.W, w.ldw, kk, n, j, w.vstore, w.ldw, w.tau,
-                         w.cval, w.cidx);
+      qr_apply(kk - j, dim3(static_cast<unsigned>(cdiv(rest, kQrCols))), st, w.W, w.ldw, kk, n, j,
+               w.vstore, w.ldw, w.tau, w.cval, w.cidx);
     if (hipGetLastError() != hipSuccess) return QB_EHIP;
   }
   hipLaunchKernelGGL(identity_kernel, dim3(static_cast<unsigned>(cdiv(k * k, 256))), dim3(256), 0,

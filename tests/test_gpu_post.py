@@ -72,7 +72,11 @@ def test_svd_matches_oracle_on_qb_of_exp40(cuda, exp40):
     _check_svd(Q, B)
 
 
-@pytest.mark.parametrize("m,k,n", [(50, 7, 30), (60, 1, 9), (80, 40, 30), (200, 33, 200)])
+# n up to 2048, 4096, 6144 (512 threads) and 10240 (1024 threads) keep the
+# columns in registers; longer columns take one pair per workgroup
+@pytest.mark.parametrize("m,k,n", [(50, 7, 30), (60, 1, 9), (80, 40, 30), (200, 33, 200),
+                                   (70, 2, 3000), (300, 65, 5000), (120, 31, 9000),
+                                   (64, 17, 11000)])
 def test_svd_shapes_and_odd_k(cuda, m, k, n):
     r = np.random.default_rng(m + k + n)
     Q = np.linalg.qr(r.standard_normal((m, k)))[0]
