@@ -104,12 +104,14 @@ def run_variant(qbmi, lib, torch, A, eps, wl, P, sample, steps, warmup, bufs, pr
     return res, ms, prof
 
 
-def committed_traffic(kernel):
+def committed_traffic(kernel, run):
     """HBM bytes per launch of `kernel` from a committed rocprofv3 counter
-    summary under profiles/ (FETCH_SIZE + WRITE_SIZE, copy-kernel scaled).
-    None unless the SHA-256 of every source file the summary names matches
-    the current file: counters taken on an older kernel say nothing about
-    this one."""
+    summary under profiles/ (FETCH_SIZE + WRITE_SIZE, copy-kernel scaled),
+    for the run configuration `run` ("<workload>/P<power iterations>/<sample
+    precision>": a class's launches differ in shape between configurations).
+    None unless the summary holds a line for this kernel and run, and the
+    SHA-256 of every source file the line names matches the current file:
+    counters taken on an older kernel say nothing about this one."""
     import glob
     import hashlib
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
@@ -119,7 +121,7 @@ def committed_traffic(kernel):
                 if len(parts) < 2 or parts[0] != "traffic":
                     continue
                 kv = dict(p.split("=", 1) for p in parts[1:] if "=" in p)
-                if kv.get("kernel") != kernel:
+                if kv.get("kernel") != kernel or kv.get("run") != run:
                     continue
                 srcs = kv.get("source", "").split(",")
                 shas = kv.get("sha256", "").split(",")
@@ -718,7 +720,7 @@ def main():
     # dominant kernel by total time inside the profiled step
     dom_name, dom = max(prof.items(), key=lambda kv: kv[1]["ms"])
     dom_tflops = dom["flops"] / (dom["ms"] * 1e-3) / 1e12 if dom["ms"] > 0 else 0.0
-    traffic, traffic_src = committed_traffic(dom_name)
+    traffic, traffic_src = committed_traffic(dom_name, f"{wl.name}/P{P}/{args.sample}")
     roofline = {"bound": "mfma", "kernel": dom_name, "achieved": dom_tflops,
                 "peak": PEAK["f64_mfma"], "unit": "TFLOP/s", "frac": dom_tflops / PEAK["f64_mfma"],
                 "traffic": traffic, "traffic_source": traffic_src,
