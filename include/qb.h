@@ -320,7 +320,7 @@ typedef struct qb_problem {
 } qb_problem;
 
 /* Workspace for a batch (0 when any problem is invalid): one float64 copy
- * of each A plus O((m + n) b) and 4 MiB of split-K partials per problem. */
+ * of each A plus O((m + n) b) and 8 MiB of split-K partials per problem. */
 size_t qb_factor_batched_workspace_bytes(const qb_problem* probs, int32_t count);
 /* probs: HOST array; every problem's outputs are written there.  Returns
  * QB_OK when the batch ran (see each problem's status), QB_EINVAL when any

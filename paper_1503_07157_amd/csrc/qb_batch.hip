@@ -52,10 +52,12 @@ constexpr int kScal = 8;                // doubles per problem in the scalar tab
 // chunks are then summed in order.  The depth loops bound the time of these
 // products once few problems are left (measured on 512 uneven problems: a
 // target of 16 -> 64 workgroups cut the batch from 285 to 257 ms and its
-// longest problem alone from 69 to 45 ms; 256 gave no further gain).  The
-// choice depends only on the problem's own sizes, so its result does not
-// depend on the rest of the batch.  Partials take up to 4 MiB per problem.
-constexpr int64_t kSplitTiles = 64;
+// longest problem alone from 69 to 45 ms; with the device-planned loop,
+// 64 -> 128 cut the batch from 227.3 to 225.5 ms and the longest problem
+// alone from 36.8 to 32.2 ms; 256 gave no further gain).  The choice
+// depends only on the problem's own sizes, so its result does not depend
+// on the rest of the batch.  Partials take up to 8 MiB per problem.
+constexpr int64_t kSplitTiles = 128;
 constexpr int64_t kSplitChunk = 256;
 constexpr int64_t kPartDoubles = (kSplitTiles + kSplitTiles - 2) * kBatchTile * kBatchTile;
 
