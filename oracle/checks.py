@@ -1,4 +1,4 @@
-"""Quantities the paper fixes, used to pin the oracle and to judge results.
+"""Quantities the paper fixes, used to pin the oracle and to check results.
 
   eckart_young(s, k)     optimal rank-k Frobenius error (eq. minerrors,
                          Section 2.2): sqrt(sum_{j>k} s_j^2)
