@@ -528,10 +528,13 @@ int gemm_nn(const double* X, int64_t ldx, const double* W, int64_t ldw, double* 
   const int64_t kc = split > 1 ? kchunk_for(K, split) : (K > 0 ? K : 0);
   const int nz = split > 1 ? static_cast<int>(cdiv(K, kc)) : 1;
   const int64_t ldp = part_ld(M);
-  // unsplit products with too few 128 x 128 tiles to fill the chip (the
-  // T^{-1} application, short projections) take 64 x 64 tiles; tall
-  // products with enough 256-row tiles for one workgroup per CU take Tall
-  const bool small = nz == 1 && cdiv(M, Big::BM) * cdiv(N, Big::BN) < kNumCU;
+  // unsplit products with too few 128 x 128 tiles to fill the chip twice
+  // (the T^{-1} application, short projections) take 64 x 64 tiles: at
+  // 20000 x 256 x 256 the 314 tiles of 128 x 128 left most of a second
+  // round of 256 CUs idle (T^{-1} applications 21.8 -> 13.8 ms per 20000 x
+  // 16000 factorisation in 64 x 64 tiles); tall products with enough
+  // 256-row tiles for one workgroup per CU take Tall
+  const bool small = nz == 1 && cdiv(M, Big::BM) * cdiv(N, Big::BN) < 2 * kNumCU;
   const bool tall = !small && use_tall(M, N, nz);
   // stream-K for the tall tiles only (measured: 89 -> 86 ms of sampling
   // products per 10000 x 10000 factorisation); the 128 x 128 forms spill
