@@ -68,6 +68,69 @@ def test_lowp_project(cuda, prec, K, w, N):
     assert np.all(np.abs(C - ref) <= bound)
 
 
+# Full size, in the launch configuration of the 20000 x 16000, b = 256
+# factorisation (the depth split, the packed 256-wide panel, 128 x 256 and
+# 256 x 128 tiles): sampled rows of Y = X W and sampled columns of
+# C = Q^T X against float64 host products of the same rows and columns.
+# Sampled: the first and last rows and columns, both sides of tile edges,
+# the ragged tail, and random ones.  At K = 16000 the elementwise bound above
+# is far looser than the actual error, so two sharper checks are added:
+#   * f32: the reference is the float64 product of the float32-rounded
+#     inputs, leaving only the float32 accumulation (a random walk of about
+#     u sqrt(sum of squared partial sums), measured 9e-8 ||x_i|| ||w_j||
+#     for this Gaussian data); the bar 1e-6 ||x_i|| ||w_j|| still catches a
+#     single wrong term of size |x_ik w_kj| (about 6e-5 ||x_i|| ||w_j||);
+#   * bf16x3: against the float64 product; the split's residual (x - hi -
+#     lo about 2^-17 |x| after the float rounding, the dropped lo*lo terms)
+#     and the float32 accumulation add up with random signs (measured
+#     1.4e-7 ||x_i|| ||w_j|| on MI355X); bar 2e-6, which a single wrong
+#     term (about 6e-5 ||x_i|| ||w_j|| here) exceeds.
+def _sampled(n, edges, count, seed):
+    r = np.random.default_rng(seed)
+    idx = set(i for i in edges if 0 <= i < n)
+    idx.update(int(i) for i in r.integers(0, n, count))
+    return np.array(sorted(idx))
+
+
+def _check_sampled(got, A, Bm, prec, what):
+    # got ~ A @ Bm (A: sampled rows, float64; Bm: float64)
+    ref = A @ Bm
+    norms = np.outer(np.linalg.norm(A, axis=1), np.linalg.norm(Bm, axis=0))
+    K = A.shape[1]
+    assert np.all(np.abs(got - ref) <= 4 * UNIT[prec] * K * (np.abs(A) @ np.abs(Bm)))
+    if prec == "f32":
+        A32 = A.astype(np.float32).astype(np.float64)
+        B32 = Bm.astype(np.float32).astype(np.float64)
+        err = np.abs(got - A32 @ B32) / norms
+        bar = 1e-6
+    else:
+        err = np.abs(got - ref) / norms
+        bar = 2e-6
+    print(f"[case] full-size {what} {prec}: max err / (|x_i| |w_j|) {np.max(err):.2e} "
+          f"(bar {bar:.0e})", flush=True)
+    assert np.max(err) <= bar
+    assert np.max(np.abs(got - ref)) > 1e-14 * np.max(np.abs(ref))  # not the float64 path
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16x3"])
+def test_lowp_full_size_sampled(cuda, prec):
+    m, n, w = 20000, 16000, 256
+    g = torch.Generator(device="cuda").manual_seed(1503)
+    X = torch.randn((n, m), dtype=torch.float64, device="cuda", generator=g).t()
+    W = torch.randn((w, n), dtype=torch.float64, device="cuda", generator=g).t()
+    Qm = torch.randn((w, m), dtype=torch.float64, device="cuda", generator=g).t()
+    Y = qbmi.sample_product(X, W, prec)
+    C = qbmi.project(Qm, X, prec)
+    torch.cuda.synchronize()
+    rows = torch.from_numpy(_sampled(m, [0, 1, 127, 128, 255, 256, 19967, 19968, m - 1], 40, 7))
+    cols = torch.from_numpy(_sampled(n, [0, 1, 127, 128, 255, 256, 15871, 15872, n - 1], 40, 8))
+    _check_sampled(Y[rows.cuda()].cpu().numpy(), X[rows.cuda()].cpu().numpy(),
+                   W.cpu().numpy(), prec, "sample rows")
+    # C[:, j] = Q^T X[:, j]: rows of C^T = X^T Q
+    _check_sampled(C[:, cols.cuda()].t().cpu().numpy(), X[:, cols.cuda()].t().cpu().numpy(),
+                   Qm.cpu().numpy(), prec, "projection columns")
+
+
 @pytest.mark.parametrize("prec", ["f32", "bf16x3"])
 @pytest.mark.parametrize("P", [0, 1])
 @pytest.mark.parametrize("eps_rel", [1e-6, 1e-3])
