@@ -35,6 +35,29 @@ def dev(x):
     return qbmi.colmajor(torch.from_numpy(np.ascontiguousarray(x)).cuda())
 
 
+def _check_normwise(got, A, Bm, prec, not_f64):
+    """got ~ A @ Bm: the elementwise bound 4 u_p K |A||B|, and the sharper
+    norm-wise bars of the full-size test below: f32 against the float64
+    product of the float32-rounded inputs, bar 1e-6 ||a_i|| ||b_j||; bf16x3
+    against the float64 product, bar max(2e-6, 4 2^-15 / sqrt(K))
+    ||a_i|| ||b_j|| (each term carries a split error below 2^-15 |a_k b_k|;
+    with random signs, on Gaussian data, they add to about
+    2^-15 ||a_i|| ||b_j|| / sqrt(K))."""
+    ref = A @ Bm
+    K = A.shape[1]
+    assert np.all(np.abs(got - ref) <= 4 * UNIT[prec] * K * (np.abs(A) @ np.abs(Bm)))
+    norms = np.outer(np.linalg.norm(A, axis=1), np.linalg.norm(Bm, axis=0))
+    norms[norms == 0] = 1.0
+    if prec == "f32":
+        A32 = A.astype(np.float32).astype(np.float64)
+        B32 = Bm.astype(np.float32).astype(np.float64)
+        assert np.max(np.abs(got - A32 @ B32) / norms) <= 1e-6
+    else:
+        assert np.max(np.abs(got - ref) / norms) <= max(2e-6, 4 * 2.0 ** -15 / np.sqrt(K))
+    if not_f64:  # and it is not silently the float64 product
+        assert np.max(np.abs(got - ref)) > 1e-14 * np.max(np.abs(ref))
+
+
 @pytest.mark.parametrize("prec", ["f32", "bf16x3"])
 @pytest.mark.parametrize("m,K,w", [(300, 500, 50), (129, 1000, 128), (1000, 4100, 256), (1, 3, 1),
                                    # 256 x 128 tiles up to 128 columns, 128 x 256 above;
@@ -47,12 +70,7 @@ def test_lowp_sample_product(cuda, prec, m, K, w):
     X = np.asfortranarray(r.standard_normal((m, K)))
     W = np.asfortranarray(r.standard_normal((K, w)))
     Y = qbmi.sample_product(dev(X), dev(W), prec).cpu().numpy()
-    ref = X @ W
-    bound = 4 * UNIT[prec] * K * (np.abs(X) @ np.abs(W))
-    assert np.all(np.abs(Y - ref) <= bound)
-    # and it is not silently the float64 product
-    if K > 100:
-        assert np.max(np.abs(Y - ref)) > 1e-14 * np.max(np.abs(ref))
+    _check_normwise(Y, X, W, prec, K > 100)
 
 
 @pytest.mark.parametrize("prec", ["f32", "bf16x3"])
@@ -63,9 +81,7 @@ def test_lowp_project(cuda, prec, K, w, N):
     Qm = np.asfortranarray(r.standard_normal((K, w)))
     X = np.asfortranarray(r.standard_normal((K, N)))
     C = qbmi.project(dev(Qm), dev(X), prec).cpu().numpy()
-    ref = Qm.T @ X
-    bound = 4 * UNIT[prec] * K * (np.abs(Qm).T @ np.abs(X))
-    assert np.all(np.abs(C - ref) <= bound)
+    _check_normwise(C.T, X.T, Qm, prec, False)
 
 
 # Full size, in the launch configuration of the 20000 x 16000, b = 256
@@ -93,23 +109,13 @@ def _sampled(n, edges, count, seed):
 
 
 def _check_sampled(got, A, Bm, prec, what):
-    # got ~ A @ Bm (A: sampled rows, float64; Bm: float64)
-    ref = A @ Bm
+    # got ~ A @ Bm (A: the sampled rows)
     norms = np.outer(np.linalg.norm(A, axis=1), np.linalg.norm(Bm, axis=0))
-    K = A.shape[1]
-    assert np.all(np.abs(got - ref) <= 4 * UNIT[prec] * K * (np.abs(A) @ np.abs(Bm)))
-    if prec == "f32":
-        A32 = A.astype(np.float32).astype(np.float64)
-        B32 = Bm.astype(np.float32).astype(np.float64)
-        err = np.abs(got - A32 @ B32) / norms
-        bar = 1e-6
-    else:
-        err = np.abs(got - ref) / norms
-        bar = 2e-6
-    print(f"[case] full-size {what} {prec}: max err / (|x_i| |w_j|) {np.max(err):.2e} "
-          f"(bar {bar:.0e})", flush=True)
-    assert np.max(err) <= bar
-    assert np.max(np.abs(got - ref)) > 1e-14 * np.max(np.abs(ref))  # not the float64 path
+    ref = (A.astype(np.float32).astype(np.float64) @ Bm.astype(np.float32).astype(np.float64)
+           if prec == "f32" else A @ Bm)
+    print(f"[case] full-size {what} {prec}: max err / (|x_i| |w_j|) "
+          f"{np.max(np.abs(got - ref) / norms):.2e}", flush=True)
+    _check_normwise(got, A, Bm, prec, True)
 
 
 @pytest.mark.parametrize("prec", ["f32", "bf16x3"])
