@@ -10,7 +10,12 @@ directions in the residual, which later blocks must pick up.  So:
   * the rank equals the float64 oracle's when eps_rel >> delta, and may
     exceed it by whole blocks when eps_rel is below delta.
 Bars:
-  products   |Y - X W| <= 4 u_p K |X||W| elementwise, u_p = delta
+  products   |Y - X W| <= 4 u_p K |X||W| elementwise, u_p = delta; and
+             norm-wise, row i and column j: f32 within 1e-6 ||x_i|| ||w_j||
+             of the float64 product of the float32-rounded inputs, bf16x3
+             within max(2e-6, 4 2^-15 / sqrt(K)) ||x_i|| ||w_j|| of X W
+             (both below the size of one wrong term), also at the full
+             20000 x 16000 x 256 launch configuration on sampled rows
   factor     rank and widths equal to the oracle's when eps_rel >= 30 delta;
              otherwise k >= oracle k; always Q orthonormal to float64
              rounding and ||A - QB|| <= eps checked directly; Q B within
